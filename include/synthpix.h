@@ -1,0 +1,236 @@
+/*
+ * synthpix.h -- C ABI of the MI355X (gfx950) synthetic PIV image-pair generator.
+ *
+ * The generator follows SynthPix (Terpin, Bonomi, Banelli, D'Andrea):
+ *   - particles are allocated for the largest seeding density, the pair's ppp is
+ *     drawn uniformly and the excess particles are masked with zero intensity
+ *     (Section 2, "Sampling the particles");
+ *   - frame-2 particles are frame-1 particles moved by the flow (same passage);
+ *   - each particle adds I0 * exp(-8 r^2 / d^2) (Eq. 1 with rho = 0 and
+ *     sigma_x = sigma_y = d / 4), times a laser-sheet profile exp(-z^2 / (2 s^2))
+ *     (Remark 1 defers the paper's own sheet law), on a square patch of side at
+ *     most 3 d + 1 pixels (Section 2, "Efficient rasterization"), and the image
+ *     is the plain sum (Section 2, "Considerations on the aggregation");
+ *   - blur, noise and storage depth are acquisition parameters (Abstract, Section 1).
+ *
+ * Conventions.
+ *   Images are row-major, H rows by W columns; pixel (r, c) is centred at
+ *   (c + 0.5, r + 0.5); x points right, y down.  Positions and diameters are in
+ *   pixels, z in laser-sheet units, intensities in full-scale units (1.0 = white),
+ *   flows in pixels per frame on a cell-centred grid: node (i, j) sits at
+ *   ((j + 0.5) W / Gw, (i + 0.5) H / Gh), stored as interleaved (u, v) floats
+ *   [Gh][Gw][2].
+ *   Particle data are structure-of-arrays float arrays indexed by
+ *   pair.particle_offset + i, i < pair.n_max.
+ *   Images are [pair][frame][H][W] at pair.image_offset (in elements of the
+ *   output type): float when bits == 0, uint16 codes otherwise.
+ *
+ * Ownership and streams.
+ *   The caller owns every buffer.  "dev" pointers are device pointers, "host"
+ *   pointers are host pointers.  The library allocates nothing in these calls
+ *   (scratch space comes from a caller-provided workspace sized by
+ *   synthpix_workspace_size) except inside synthpix_plan_create.  Every call
+ *   validates its arguments on the host before enqueuing anything, then
+ *   enqueues its kernels asynchronously on `stream` (a hipStream_t; NULL is the
+ *   null stream) and returns.  Host-side pair tables may be reused or freed as
+ *   soon as the call returns; device-side ones must stay valid until the
+ *   stream reaches the call.
+ *
+ * Errors.
+ *   Every call returns a synthpix_status: SP_OK (0) or a negative code.  On an
+ *   error nothing has been enqueued (argument errors) or the HIP error is
+ *   reported (SP_ERR_HIP).  synthpix_last_error() returns a thread-local
+ *   message describing the last failure.  No C++ exception crosses the ABI.
+ *   Conditions only the device can see (a diameter above the declared d_max, a
+ *   tile whose sum could leave the fixed-point range) are recorded as bits in a
+ *   status word at the start of the workspace; synthpix_read_status returns it.
+ *
+ * Determinism.
+ *   Outputs are a pure function of the inputs, the seed and each pair's pair_id.
+ *   They do not depend on tiling, batching or the stream: particle contributions
+ *   are summed in exact fixed point (2^-24 full-scale units, 32-bit), so any
+ *   summation order gives the same bits.
+ */
+#ifndef SYNTHPIX_H
+#define SYNTHPIX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SYNTHPIX_VERSION 1
+
+typedef enum {
+    SP_OK = 0,
+    SP_ERR_INVALID_ARG = -1,   /* a pointer, size or parameter is out of its documented range */
+    SP_ERR_WORKSPACE = -2,     /* workspace missing, misaligned or smaller than synthpix_workspace_size */
+    SP_ERR_UNSUPPORTED = -3,   /* a configuration the kernels do not handle (e.g. too many tiles per image) */
+    SP_ERR_HIP = -4,           /* a HIP runtime call failed (no device, launch failure, ...) */
+    SP_ERR_DEVICE_STATUS = -5  /* synthpix_read_status found device-side flags */
+} synthpix_status;
+
+typedef enum { SP_EULER = 0, SP_RK4 = 1 } synthpix_integrator;
+typedef enum { SP_DIST_UNIFORM = 0, SP_DIST_NORMAL_CLIPPED = 1 } synthpix_dist;
+
+/* Device status bits (workspace word 0). */
+#define SP_STATUS_D_ABOVE_MAX   0x1u   /* a particle had d > d_max; it was not rendered */
+#define SP_STATUS_FIXED_RANGE   0x2u   /* a tile's particles could sum to >= 256 full scale */
+
+/* One image pair.  An array of these describes a batch, pairs of different size
+ * included.  56 bytes, identical layout on host and device. */
+typedef struct {
+    int32_t  H, W;              /* image rows, columns (1 .. 16384)                         */
+    int32_t  Gh, Gw;            /* flow grid rows, columns (2 .. 8192)                        */
+    int32_t  n_max;             /* particles allocated for the pair (synthpix_particle_count) */
+    int32_t  reserved;          /* must be 0                                                 */
+    int64_t  particle_offset;   /* index of the pair's first particle in the SoA arrays      */
+    int64_t  image_offset;      /* element offset of frame 1; frame 2 starts H*W later       */
+    int64_t  flow_offset;       /* float offset of the pair's [Gh][Gw][2] flow grid          */
+    uint64_t pair_id;           /* global pair index: Philox counter words 2 and 3           */
+} synthpix_pair;
+
+/* Seeding parameters (Section 2, "Sampling the particles"; the paragraph after Eq. 1). */
+typedef struct {
+    double  ppp_lo, ppp_hi;     /* seeding density range, particles per pixel, 0 < lo <= hi <= 1 */
+    int32_t d_dist;             /* synthpix_dist                                                 */
+    float   d_a, d_b;           /* uniform: d ~ U[d_a, d_b]; normal: mean d_a, std d_b           */
+    float   d_lo, d_hi;         /* normal only: clip range                                      */
+    float   I0_lo, I0_hi;       /* peak intensity range, full-scale units, 0 <= lo <= hi          */
+    float   z_lo, z_hi;         /* out-of-plane position range, laser-sheet units               */
+} synthpix_seed_params;
+
+/* Inter-frame motion (Section 2, "Sampling the particles"; Euler, dt = 1, 1 substep
+ * is the paper's x -> x + u(x)). */
+typedef struct {
+    float   dt;                 /* inter-frame time in frames, finite                 */
+    int32_t substeps;           /* 1 .. 1024                                          */
+    int32_t integrator;         /* synthpix_integrator                                */
+} synthpix_advect_params;
+
+/* Rendering and acquisition parameters. */
+typedef struct {
+    float    sheet_sigma;       /* Gaussian laser-sheet width s (> 0), sheet units             */
+    float    d_max;             /* upper bound of every diameter passed in (0 < d_max <= 16)    */
+    int32_t  blur_radius;       /* 0 (off) .. 3: taps -b..b                                      */
+    float    blur_sigma;        /* > 0 when blur_radius > 0                                      */
+    float    noise_sigma;       /* >= 0; additive N(0, sigma^2) full-scale units after the blur  */
+    int32_t  bits;              /* 0: float images; 1..16: uint16 codes of that depth            */
+    uint64_t seed;              /* key of the noise draws                                        */
+    synthpix_advect_params advect;  /* used by the backward to recompute frame-2 positions  */
+} synthpix_render_params;
+
+/* Screen tiling used by the renderer.  Tiles are tile_w x tile_h pixels
+ * (multiples of 4 and 8 respectively, 8 .. 128).  NULL selects the default. */
+typedef struct {
+    int32_t tile_w, tile_h;
+    int32_t chunk;              /* particles per binning block (256 .. 16384, multiple of 256) */
+    int32_t cap;                /* particles staged in LDS per render pass (32 .. 512)        */
+} synthpix_tiling;
+
+/* ---------------------------------------------------------------- helpers */
+
+int32_t synthpix_version(void);
+const char* synthpix_last_error(void);
+
+/* floor(H * W * ppp + 1/2) in float64 (Section 2, "Sampling the particles"). */
+synthpix_status synthpix_particle_count(int32_t H, int32_t W, double ppp, int32_t* n_out);
+
+/* The default tiling for a batch. */
+synthpix_status synthpix_default_tiling(const synthpix_pair* pairs_host, int32_t n_pairs,
+                                        const synthpix_render_params* rp, synthpix_tiling* out);
+
+/* Bytes of workspace needed by synthpix_render_pair (backward = 0) or
+ * synthpix_render_pair_backward (backward = 1) for this batch and tiling. */
+synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t n_pairs,
+                                        const synthpix_render_params* rp,
+                                        const synthpix_tiling* tiling, int32_t backward,
+                                        size_t* bytes_out);
+
+/* Where the binning results of the last synthpix_render_pair call live inside
+ * its workspace (byte offsets from the workspace start), for inspection:
+ *   tile_count  uint32 [2][tiles]  particles listed per tile (frame-major)
+ *   tile_offset int64  [2][tiles]  index of each tile's first entry in `entries`
+ *   entries     int32  [..]        pair-local particle indices; a tile's list is
+ *                                  a set (its order is unspecified)
+ * tiles = sum over pairs of ceil(W / tile_w) * ceil(H / tile_h), pairs in table
+ * order, tiles row-major inside a pair. */
+typedef struct {
+    size_t tile_count, tile_offset, entries;
+    int64_t tiles;
+} synthpix_bin_views;
+
+synthpix_status synthpix_bin_views_of(const synthpix_pair* pairs_host, int32_t n_pairs,
+                                      const synthpix_render_params* rp, const synthpix_tiling* tiling,
+                                      synthpix_bin_views* out);
+
+/* Copies the device status word (workspace word 0) to *flags after the stream
+ * has drained; returns SP_ERR_DEVICE_STATUS when any flag is set. */
+synthpix_status synthpix_read_status(const void* workspace_dev, void* stream, uint32_t* flags);
+
+/* -------------------------------------------------------------- hot path */
+
+/* Seed every pair's n_max candidate particles (Section 2, "Sampling the
+ * particles").  Per pair: ppp = ppp_lo + (ppp_hi - ppp_lo) u, n_active =
+ * min(n_max, floor(H W ppp + 1/2)); per particle i: x = W u, y = H u,
+ * z ~ U[z_lo, z_hi], d per d_dist, I0 ~ U[I0_lo, I0_hi] for i < n_active and
+ * 0 otherwise.  Draws are Philox4x32-10 words of counter
+ * (i, stream, pair_id lo, pair_id hi) under key (seed lo, seed hi).
+ * pairs_host/pairs_dev: the same n_pairs table on host and device.
+ * x, y, z, d, I0: device float arrays covering every pair's particle range.
+ * n_active_dev, ppp_dev: optional per-pair outputs (int32, float64), may be NULL. */
+synthpix_status synthpix_seed(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                              int32_t n_pairs, const synthpix_seed_params* sp, uint64_t seed,
+                              float* x, float* y, float* z, float* d, float* I0,
+                              int32_t* n_active_dev, double* ppp_dev, void* stream);
+
+/* Move frame-1 particles through the pair's frozen flow grid over dt
+ * (Section 2, "Sampling the particles"): bilinear, clamped-to-edge sampling,
+ * `substeps` steps of explicit Euler or classical RK4.
+ * flow: device floats holding every pair's grid at pair.flow_offset.
+ * x1, y1 -> x2, y2: device float arrays (x2/y2 may not alias x1/y1). */
+synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                int32_t n_pairs, const float* flow, const synthpix_advect_params* ap,
+                                const float* x1, const float* y1, float* x2, float* y2, void* stream);
+
+/* Render both exposures of every pair and apply blur, noise and storage
+ * (Eq. 1; Section 2, "Considerations on the aggregation", "Efficient
+ * rasterization").  Frame 1 uses (x1, y1), frame 2 (x2, y2); z, d, I0 are
+ * shared.  Particles with I0 <= 0, d <= 0 or non-finite position add nothing.
+ * tiling may be NULL (default); the output does not depend on it.
+ * images: device buffer, float or uint16 per rp->bits.
+ * workspace: device, 256-byte aligned, >= synthpix_workspace_size(..., 0). */
+synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                     int32_t n_pairs, const synthpix_tiling* tiling,
+                                     const float* x1, const float* y1,
+                                     const float* x2, const float* y2,
+                                     const float* z, const float* d, const float* I0,
+                                     const synthpix_render_params* rp, void* images,
+                                     void* workspace, size_t ws_bytes, void* stream);
+
+/* Gradient of a loss L of the float images J (bits must be 0) with respect to
+ * the frame-1 positions, z, d, I0, each pair's sheet width and each pair's flow
+ * grid.  Frame-2 positions are recomputed from (x1, y1) and the flow with
+ * rp->advect; footprints are recomputed, nothing from the forward is stored.
+ * grad_images: device floats dL/dJ, same layout as the forward's images.
+ * Outputs (device floats, overwritten): g_x1, g_y1, g_z, g_d, g_I0 per particle,
+ * g_sheet [n_pairs], g_flow with the flow's layout.
+ * workspace: >= synthpix_workspace_size(..., 1). */
+synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host,
+                                              const synthpix_pair* pairs_dev, int32_t n_pairs,
+                                              const synthpix_tiling* tiling, const float* flow,
+                                              const float* x1, const float* y1, const float* z,
+                                              const float* d, const float* I0,
+                                              const synthpix_render_params* rp,
+                                              const float* grad_images,
+                                              float* g_x1, float* g_y1, float* g_z, float* g_d,
+                                              float* g_I0, float* g_sheet, float* g_flow,
+                                              void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYNTHPIX_H */

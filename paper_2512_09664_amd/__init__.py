@@ -1,0 +1,12 @@
+"""MI355X-native synthetic PIV image-pair generator (HIP kernels behind a C ABI).
+
+The kernels live in ``libsynthpix.so`` (built from ``csrc/`` by ``build.py``);
+``api`` marshals PyTorch tensors and streams into the C entry points
+``synthpix_seed``, ``synthpix_advect``, ``synthpix_render_pair`` and
+``synthpix_render_pair_backward``.
+"""
+
+from . import _lib  # noqa: F401
+from .api import (PairBatch, advect, advect_params, alloc_workspace, particle_count, read_status,  # noqa: F401
+                  render_pair, render_pair_backward, render_params, seed, seed_params, split_images, tiling,
+                  workspace_size)

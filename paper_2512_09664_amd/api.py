@@ -1,0 +1,234 @@
+"""PyTorch-facing binding of the C ABI (argument marshalling only).
+
+Tensors provide device memory, ``torch.cuda.current_stream()`` provides the
+stream; every computation runs in ``libsynthpix.so``.  Names follow the C
+entry points: ``seed``, ``advect``, ``render_pair``, ``render_pair_backward``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("tensors must be contiguous CUDA (HIP) tensors")
+
+
+U16 = getattr(torch, "uint16", torch.int16)
+
+
+def particle_count(H: int, W: int, ppp: float) -> int:
+    n = ctypes.c_int32(0)
+    L.check(L.load().synthpix_particle_count(int(H), int(W), float(ppp), ctypes.byref(n)))
+    return n.value
+
+
+@dataclass
+class PairBatch:
+    """A batch of image pairs: the pair table on host and device plus the
+    sizes of the packed particle, image and flow arrays."""
+    host: ctypes.Array
+    dev: torch.Tensor
+    n_pairs: int
+    n_particles: int
+    n_pixels: int
+    n_flow: int
+    sizes: Tuple[Tuple[int, int], ...]
+    grids: Tuple[Tuple[int, int], ...]
+    n_max: Tuple[int, ...]
+
+    @staticmethod
+    def build(sizes: Sequence[Tuple[int, int]], grids: Sequence[Tuple[int, int]], n_max: Sequence[int],
+              pair_ids: Optional[Sequence[int]] = None, device="cuda") -> "PairBatch":
+        n = len(sizes)
+        arr = (L.Pair * n)()
+        po = io = fo = 0
+        for p in range(n):
+            H, W = sizes[p]
+            Gh, Gw = grids[p]
+            arr[p].H, arr[p].W, arr[p].Gh, arr[p].Gw = int(H), int(W), int(Gh), int(Gw)
+            arr[p].n_max = int(n_max[p])
+            arr[p].reserved = 0
+            arr[p].particle_offset = po
+            arr[p].image_offset = io
+            arr[p].flow_offset = fo
+            arr[p].pair_id = int(pair_ids[p]) if pair_ids is not None else p
+            po += int(n_max[p])
+            io += 2 * int(H) * int(W)
+            fo += 2 * int(Gh) * int(Gw)
+        raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+        dev = torch.from_numpy(raw).to(device)
+        return PairBatch(arr, dev, n, po, io, fo, tuple(map(tuple, sizes)), tuple(map(tuple, grids)),
+                         tuple(int(v) for v in n_max))
+
+    @property
+    def host_ptr(self):
+        return ctypes.cast(self.host, ctypes.POINTER(L.Pair))
+
+    @property
+    def dev_ptr(self):
+        return ctypes.c_void_p(self.dev.data_ptr())
+
+
+def seed_params(ppp=(0.05, 0.05), d_dist="uniform", d_params=(1.0, 5.0), I0=(0.8, 1.0), z=(-1.0, 1.0)):
+    sp = L.SeedParams()
+    sp.ppp_lo, sp.ppp_hi = float(ppp[0]), float(ppp[1])
+    if d_dist == "uniform":
+        sp.d_dist = L.SP_DIST_UNIFORM
+        sp.d_a, sp.d_b = float(d_params[0]), float(d_params[1])
+        sp.d_lo, sp.d_hi = 0.0, 0.0
+    elif d_dist == "normal":
+        sp.d_dist = L.SP_DIST_NORMAL_CLIPPED
+        sp.d_a, sp.d_b, sp.d_lo, sp.d_hi = (float(v) for v in d_params)
+    else:
+        raise ValueError(d_dist)
+    sp.I0_lo, sp.I0_hi = float(I0[0]), float(I0[1])
+    sp.z_lo, sp.z_hi = float(z[0]), float(z[1])
+    return sp
+
+
+def advect_params(dt=1.0, substeps=1, integrator="euler"):
+    ap = L.AdvectParams()
+    ap.dt = float(dt)
+    ap.substeps = int(substeps)
+    ap.integrator = {"euler": L.SP_EULER, "rk4": L.SP_RK4}[integrator]
+    return ap
+
+
+def render_params(sheet_sigma=0.5, d_max=5.0, blur_radius=0, blur_sigma=0.7, noise_sigma=0.0, bits=0, seed=0,
+                  dt=1.0, substeps=1, integrator="euler"):
+    rp = L.RenderParams()
+    rp.sheet_sigma = float(sheet_sigma)
+    rp.d_max = float(d_max)
+    rp.blur_radius = int(blur_radius)
+    rp.blur_sigma = float(blur_sigma)
+    rp.noise_sigma = float(noise_sigma)
+    rp.bits = int(bits)
+    rp.seed = int(seed)
+    rp.advect = advect_params(dt, substeps, integrator)
+    return rp
+
+
+def tiling(tile_w=32, tile_h=32, chunk=4096, cap=128):
+    t = L.Tiling()
+    t.tile_w, t.tile_h, t.chunk, t.cap = int(tile_w), int(tile_h), int(chunk), int(cap)
+    return t
+
+
+def seed(batch: PairBatch, sp, seed_value: int, out=None):
+    """Run ``synthpix_seed``; returns dict x, y, z, d, I0 (float32 [n_particles])
+    plus n_active (int32 [n_pairs]) and ppp (float64 [n_pairs])."""
+    dev = batch.dev.device
+    n = max(batch.n_particles, 1)
+    o = out or {k: torch.empty(n, dtype=torch.float32, device=dev) for k in ("x", "y", "z", "d", "I0")}
+    if "n_active" not in o:
+        o["n_active"] = torch.empty(batch.n_pairs, dtype=torch.int32, device=dev)
+        o["ppp"] = torch.empty(batch.n_pairs, dtype=torch.float64, device=dev)
+    L.check(L.load().synthpix_seed(batch.host_ptr, batch.dev_ptr, batch.n_pairs, ctypes.byref(sp),
+                                   int(seed_value), _ptr(o["x"]), _ptr(o["y"]), _ptr(o["z"]), _ptr(o["d"]),
+                                   _ptr(o["I0"]), _ptr(o["n_active"]), _ptr(o["ppp"]), _stream()))
+    return o
+
+
+def advect(batch: PairBatch, flow: torch.Tensor, ap, x1: torch.Tensor, y1: torch.Tensor, x2=None, y2=None):
+    _need_cuda(flow, x1, y1)
+    x2 = torch.empty_like(x1) if x2 is None else x2
+    y2 = torch.empty_like(y1) if y2 is None else y2
+    L.check(L.load().synthpix_advect(batch.host_ptr, batch.dev_ptr, batch.n_pairs, _ptr(flow), ctypes.byref(ap),
+                                     _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _stream()))
+    return x2, y2
+
+
+def workspace_size(batch: PairBatch, rp, tile=None, backward=False) -> int:
+    n = ctypes.c_size_t(0)
+    L.check(L.load().synthpix_workspace_size(batch.host_ptr, batch.n_pairs, ctypes.byref(rp),
+                                             ctypes.byref(tile) if tile is not None else None,
+                                             1 if backward else 0, ctypes.byref(n)))
+    return n.value
+
+
+def alloc_workspace(batch: PairBatch, rp, tile=None, backward=False) -> torch.Tensor:
+    nbytes = workspace_size(batch, rp, tile, backward)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=batch.dev.device)
+
+
+def bin_views(batch: PairBatch, rp, tile=None, workspace: torch.Tensor = None):
+    """Tile counts, offsets and member lists written into ``workspace`` by the
+    last ``render_pair`` call with the same batch, parameters and tiling."""
+    v = L.BinViews()
+    L.check(L.load().synthpix_bin_views_of(batch.host_ptr, batch.n_pairs, ctypes.byref(rp),
+                                           ctypes.byref(tile) if tile is not None else None, ctypes.byref(v)))
+    T = int(v.tiles)
+    ws = workspace
+    count = ws[v.tile_count:v.tile_count + 8 * T].view(torch.int32).view(2, T)
+    offset = ws[v.tile_offset:v.tile_offset + 16 * T].view(torch.int64).view(2, T)
+    entries = ws[v.entries:].view(torch.int32)
+    return count, offset, entries
+
+
+def read_status(workspace: torch.Tensor) -> int:
+    flags = ctypes.c_uint32(0)
+    st = L.load().synthpix_read_status(_ptr(workspace), _stream(), ctypes.byref(flags))
+    if st not in (L.SP_OK, L.SP_ERR_DEVICE_STATUS):
+        L.check(st)
+    return flags.value
+
+
+def render_pair(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, tile=None, images=None, workspace=None):
+    """Run ``synthpix_render_pair``; returns images [n_pixels] (float32 or uint16)."""
+    _need_cuda(x1, y1, x2, y2, z, d, I0)
+    dev = x1.device
+    if images is None:
+        images = torch.empty(batch.n_pixels, dtype=U16 if rp.bits > 0 else torch.float32, device=dev)
+    if workspace is None:
+        workspace = alloc_workspace(batch, rp, tile)
+    L.check(L.load().synthpix_render_pair(batch.host_ptr, batch.dev_ptr, batch.n_pairs,
+                                          ctypes.byref(tile) if tile is not None else None,
+                                          _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(z), _ptr(d), _ptr(I0),
+                                          ctypes.byref(rp), _ptr(images), _ptr(workspace),
+                                          workspace.numel(), _stream()))
+    return images
+
+
+def render_pair_backward(batch: PairBatch, flow, x1, y1, z, d, I0, rp, grad_images, tile=None, workspace=None):
+    """Run ``synthpix_render_pair_backward``; returns dict of gradients."""
+    _need_cuda(flow, x1, y1, z, d, I0, grad_images)
+    dev = x1.device
+    g = {k: torch.empty_like(x1) for k in ("x1", "y1", "z", "d", "I0")}
+    g["sheet"] = torch.empty(batch.n_pairs, dtype=torch.float32, device=dev)
+    g["flow"] = torch.empty_like(flow)
+    if workspace is None:
+        workspace = alloc_workspace(batch, rp, tile, backward=True)
+    L.check(L.load().synthpix_render_pair_backward(
+        batch.host_ptr, batch.dev_ptr, batch.n_pairs, ctypes.byref(tile) if tile is not None else None,
+        _ptr(flow), _ptr(x1), _ptr(y1), _ptr(z), _ptr(d), _ptr(I0), ctypes.byref(rp), _ptr(grad_images),
+        _ptr(g["x1"]), _ptr(g["y1"]), _ptr(g["z"]), _ptr(g["d"]), _ptr(g["I0"]), _ptr(g["sheet"]),
+        _ptr(g["flow"]), _ptr(workspace), workspace.numel(), _stream()))
+    return g
+
+
+def split_images(batch: PairBatch, images: torch.Tensor):
+    """Views [2, H, W] of each pair's two frames in a packed image buffer."""
+    out = []
+    o = 0
+    for (H, W) in batch.sizes:
+        out.append(images[o:o + 2 * H * W].view(2, H, W))
+        o += 2 * H * W
+    return out

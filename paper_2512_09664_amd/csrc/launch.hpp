@@ -1,0 +1,86 @@
+// Kernel launchers shared between the kernel translation units and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "synthpix.h"
+
+namespace sp {
+
+// Per-pair derived sizes of one render call (computed identically on host
+// and device from the pair table and the tiling).
+struct PairLayout {
+    int32_t chunk_base;     // first binning block of the pair (prefix over pairs)
+    int32_t n_chunks;       // ceil(n_max / chunk)
+    int32_t tile_base;      // first tile of the pair (prefix over pairs)
+    int32_t ntx, nty;       // tiles per row / column
+    int32_t pad_;
+    int64_t hist_base;      // first per-(frame, chunk, tile) count of the pair
+    int64_t entry_base;     // first entry slot of the pair (frame 2 at + entry_cap)
+    int64_t entry_cap;      // entry slots per frame
+};
+
+struct RenderConfig {
+    int tile_w, tile_h, chunk, cap;
+    int apron;              // blur radius b
+    int wmax;               // largest per-particle patch side the LDS tables hold
+    int kx, ky;             // bound on tiles touched per particle per axis
+    float d_max;
+};
+
+// Totals of a batch (host side).
+struct BatchTotals {
+    int64_t n_span;         // max(particle_offset + n_max)
+    int64_t chunks;         // sum n_chunks
+    int64_t tiles;          // sum ntx * nty
+    int64_t hist;           // 2 * sum n_chunks * tiles
+    int64_t entries;        // 2 * sum entry_cap
+    int64_t max_tiles;      // max ntx * nty over pairs (LDS histogram size)
+};
+
+// Workspace layout (byte offsets, 256-aligned).
+struct WorkspaceLayout {
+    size_t status;          // uint32 [4]
+    size_t layout;          // PairLayout [n_pairs]
+    size_t tile_count;      // uint32 [2 * tiles]
+    size_t tile_offset;     // int64  [2 * tiles]
+    size_t hist;            // uint32 [hist]
+    size_t entries;         // int32  [entries]
+    size_t grad_img;        // float  (backward only) dL/dI images
+    size_t x2;              // float  (backward only) recomputed frame-2 positions
+    size_t y2;
+    size_t gpart;           // float  (backward only) per particle partial sums
+    size_t total;
+};
+
+hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
+                       const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
+                       float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s);
+
+hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
+                         const synthpix_advect_params& ap, const float* x1, const float* y1, float* x2,
+                         float* y2, hipStream_t s);
+
+struct RenderArgs {
+    const synthpix_pair* pairs;
+    int n_pairs;
+    const float* x[2];
+    const float* y[2];
+    const float* z;
+    const float* d;
+    const float* I0;
+    void* images;
+    float sheet_sigma;
+    float noise_sigma;
+    int bits;
+    uint64_t seed;
+    float blur_w[7];
+};
+
+size_t render_lds_bytes(const RenderConfig& cfg);
+
+hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot,
+                         char* ws, const WorkspaceLayout& wl, hipStream_t s);
+
+}  // namespace sp

@@ -1,0 +1,195 @@
+// Particle seeding and inter-frame advection kernels (gfx950).
+//
+// Seeding follows Section 2, "Sampling the particles": n_max candidates per
+// pair drawn over the image, the pair's ppp drawn uniformly, particles past
+// n_active masked with zero intensity; per-particle parameters uniform in
+// their ranges (the paragraph after Eq. 1), the diameter optionally a clipped
+// normal.  Advection implements the same passage's x -> x + u(x), generalised to
+// dt with Euler or RK4 substeps on a bilinear, cell-centred flow grid.
+//
+// One thread per particle; SoA float stores are fully coalesced.  Both kernels
+// are bound by Philox / interpolation arithmetic, not by memory.
+#include "device_math.hpp"
+#include "launch.hpp"
+
+namespace sp {
+
+// The pair's drawn ppp and active-particle count (Philox stream 5, index 0).
+__device__ __forceinline__ int pair_active(const synthpix_pair& P, const synthpix_seed_params& prm, uint64_t seed,
+                                           double* ppp_out)
+{
+    const u32x4 w = draw(0u, STREAM_PAIR, P.pair_id, seed);
+    const double ppp = prm.ppp_lo + (prm.ppp_hi - prm.ppp_lo) * (double)u24(w.a);
+    const double na = floor((double)P.H * (double)P.W * ppp + 0.5);
+    *ppp_out = ppp;
+    return na < (double)P.n_max ? (int)na : P.n_max;
+}
+
+__global__ void __launch_bounds__(256)
+pair_scalars_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, synthpix_seed_params prm,
+                    uint64_t seed, int32_t* __restrict__ n_active_out, double* __restrict__ ppp_out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pairs) return;
+    double ppp;
+    const int na = pair_active(pairs[p], prm, seed, &ppp);
+    if (n_active_out) n_active_out[p] = na;
+    if (ppp_out) ppp_out[p] = ppp;
+}
+
+__global__ void __launch_bounds__(256)
+seed_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span,
+            synthpix_seed_params prm, uint64_t seed,
+            float* __restrict__ x, float* __restrict__ y, float* __restrict__ z,
+            float* __restrict__ d, float* __restrict__ I0)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_span) return;
+    const int p = find_pair_by_particle(pairs, n_pairs, g);
+    const synthpix_pair P = pairs[p];
+    const int64_t i64 = g - P.particle_offset;
+    if (i64 < 0 || i64 >= P.n_max) return;
+    const uint32_t i = (uint32_t)i64;
+
+    double ppp;
+    const int n_active = pair_active(P, prm, seed, &ppp);
+
+    const u32x4 gw = draw(i, STREAM_GEOM, P.pair_id, seed);
+    const u32x4 hw = draw(i, STREAM_PHOTO, P.pair_id, seed);
+    x[g] = u24(gw.a) * (float)P.W;
+    y[g] = u24(gw.b) * (float)P.H;
+    z[g] = __builtin_fmaf(prm.z_hi - prm.z_lo, u24(gw.c), prm.z_lo);
+    float dv;
+    if (prm.d_dist == SP_DIST_UNIFORM) {
+        dv = __builtin_fmaf(prm.d_b - prm.d_a, u24(gw.d), prm.d_a);
+    } else {
+        const float l = log_ra(u24_open0(hw.b));
+        const float R = __builtin_sqrtf(-2.0f * l);
+        const float n = R * cos2pi_ra(u24(hw.c));
+        float v = __builtin_fmaf(prm.d_b, n, prm.d_a);
+        v = __builtin_fmaxf(v, prm.d_lo);
+        dv = __builtin_fminf(v, prm.d_hi);
+    }
+    d[g] = dv;
+    I0[g] = ((int)i < n_active) ? __builtin_fmaf(prm.I0_hi - prm.I0_lo, u24(hw.a), prm.I0_lo) : 0.0f;
+}
+
+// Bilinear sample of the pair's (u, v) grid at image position (px, py).
+struct FlowView {
+    const float2* __restrict__ F;
+    int Gh, Gw;
+    float sx, sy;      // Gw / W, Gh / H (correctly rounded)
+};
+
+__device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, float py)
+{
+    float gx = px * fv.sx - 0.5f;
+    float gy = py * fv.sy - 0.5f;
+    gx = __builtin_fminf(__builtin_fmaxf(gx, 0.0f), (float)(fv.Gw - 1));
+    gy = __builtin_fminf(__builtin_fmaxf(gy, 0.0f), (float)(fv.Gh - 1));
+    int j0 = (int)__builtin_floorf(gx);
+    int i0 = (int)__builtin_floorf(gy);
+    j0 = j0 > fv.Gw - 2 ? fv.Gw - 2 : j0;
+    i0 = i0 > fv.Gh - 2 ? fv.Gh - 2 : i0;
+    const float fx = gx - (float)j0;
+    const float fy = gy - (float)i0;
+    const float2* row0 = fv.F + (size_t)i0 * fv.Gw + j0;
+    const float2* row1 = row0 + fv.Gw;
+    const float2 a = row0[0], b = row0[1], c = row1[0], e = row1[1];
+    float2 out;
+    {
+        const float top = __builtin_fmaf(fx, b.x - a.x, a.x);
+        const float bot = __builtin_fmaf(fx, e.x - c.x, c.x);
+        out.x = __builtin_fmaf(fy, bot - top, top);
+    }
+    {
+        const float top = __builtin_fmaf(fx, b.y - a.y, a.y);
+        const float bot = __builtin_fmaf(fx, e.y - c.y, c.y);
+        out.y = __builtin_fmaf(fy, bot - top, top);
+    }
+    return out;
+}
+
+__device__ __forceinline__ FlowView flow_view(const synthpix_pair& P, const float* flow)
+{
+    FlowView fv;
+    fv.F = reinterpret_cast<const float2*>(flow + P.flow_offset);
+    fv.Gh = P.Gh;
+    fv.Gw = P.Gw;
+    fv.sx = (float)P.Gw / (float)P.W;
+    fv.sy = (float)P.Gh / (float)P.H;
+    return fv;
+}
+
+// One frozen-field substep sequence; the update order is fixed (see the
+// reference arithmetic): Euler p = fma(h, u, p); RK4 stages at fma(h/2, k, p)
+// and fma(h, k3, p), update p = fma(h, (((k1 + 2 k2) + 2 k3) + k4) / 6, p).
+__device__ __forceinline__ float2 integrate(const FlowView& fv, float px, float py, float dt,
+                                            int substeps, int integrator)
+{
+    const float h = dt / (float)substeps;
+    const float hh = h * 0.5f;
+    for (int s = 0; s < substeps; ++s) {
+        if (integrator == SP_EULER) {
+            const float2 u = sample_flow(fv, px, py);
+            px = __builtin_fmaf(h, u.x, px);
+            py = __builtin_fmaf(h, u.y, py);
+        } else {
+            const float2 k1 = sample_flow(fv, px, py);
+            const float2 k2 = sample_flow(fv, __builtin_fmaf(hh, k1.x, px), __builtin_fmaf(hh, k1.y, py));
+            const float2 k3 = sample_flow(fv, __builtin_fmaf(hh, k2.x, px), __builtin_fmaf(hh, k2.y, py));
+            const float2 k4 = sample_flow(fv, __builtin_fmaf(h, k3.x, px), __builtin_fmaf(h, k3.y, py));
+            const float su = ((k1.x + 2.0f * k2.x) + 2.0f * k3.x) + k4.x;
+            const float sv = ((k1.y + 2.0f * k2.y) + 2.0f * k3.y) + k4.y;
+            px = __builtin_fmaf(h, su / 6.0f, px);
+            py = __builtin_fmaf(h, sv / 6.0f, py);
+        }
+    }
+    return make_float2(px, py);
+}
+
+__global__ void __launch_bounds__(256)
+advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span,
+              const float* __restrict__ flow, synthpix_advect_params ap,
+              const float* __restrict__ x1, const float* __restrict__ y1,
+              float* __restrict__ x2, float* __restrict__ y2)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_span) return;
+    const int p = find_pair_by_particle(pairs, n_pairs, g);
+    const synthpix_pair P = pairs[p];
+    const int64_t i = g - P.particle_offset;
+    if (i < 0 || i >= P.n_max) return;
+    const FlowView fv = flow_view(P, flow);
+    const float2 r = integrate(fv, x1[g], y1[g], ap.dt, ap.substeps, ap.integrator);
+    x2[g] = r.x;
+    y2[g] = r.y;
+}
+
+hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
+                       const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
+                       float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s)
+{
+    if (n_active || ppp)
+        hipLaunchKernelGGL(pair_scalars_kernel, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, pairs_dev,
+                           n_pairs, prm, seed, n_active, ppp);
+    if (n_span > 0) {
+        const int64_t blocks = (n_span + 255) / 256;
+        hipLaunchKernelGGL(seed_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
+                           prm, seed, x, y, z, d, I0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
+                         const synthpix_advect_params& ap, const float* x1, const float* y1, float* x2,
+                         float* y2, hipStream_t s)
+{
+    if (n_span <= 0) return hipSuccess;
+    const int64_t blocks = (n_span + 255) / 256;
+    hipLaunchKernelGGL(advect_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
+                       flow, ap, x1, y1, x2, y2);
+    return hipGetLastError();
+}
+
+}  // namespace sp

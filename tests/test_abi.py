@@ -1,0 +1,150 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point the header declares, and rejects invalid arguments before
+enqueuing anything."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "synthpix.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2512_09664_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2512_09664_amd import build
+        build.build()
+    return _lib
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(synthpix_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path_calls():
+    syms = declared_symbols()
+    for name in ("synthpix_seed", "synthpix_advect", "synthpix_render_pair", "synthpix_render_pair_backward"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert set(declared_symbols()) <= set(L.SIGNATURES), "binding lacks a declared symbol"
+
+
+def test_particle_count_and_errors(L):
+    lib = L.load()
+    n = ctypes.c_int32()
+    assert lib.synthpix_particle_count(256, 256, 0.02, ctypes.byref(n)) == 0 and n.value == 1311
+    assert lib.synthpix_particle_count(1024, 1024, 0.05, ctypes.byref(n)) == 0 and n.value == 52429
+    assert lib.synthpix_particle_count(0, 5, 0.1, ctypes.byref(n)) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_particle_count(5, 5, 1.5, ctypes.byref(n)) == L.SP_ERR_INVALID_ARG
+    assert b"ppp" in lib.synthpix_last_error()
+
+
+def _pairs(L, specs):
+    arr = (L.Pair * len(specs))()
+    po = 0
+    for p, (H, W, Gh, Gw, n) in enumerate(specs):
+        arr[p].H, arr[p].W, arr[p].Gh, arr[p].Gw, arr[p].n_max = H, W, Gh, Gw, n
+        arr[p].particle_offset = po
+        po += n
+    return arr
+
+
+def _rp(L, **kw):
+    rp = L.RenderParams()
+    rp.sheet_sigma, rp.d_max, rp.blur_radius, rp.blur_sigma, rp.noise_sigma, rp.bits = 0.5, 5.0, 1, 0.7, 0.0, 12
+    for k, v in kw.items():
+        setattr(rp, k, v)
+    return rp
+
+
+def test_workspace_size_and_validation(L):
+    lib = L.load()
+    pairs = _pairs(L, [(1024, 1024, 256, 256, 52429), (256, 512, 64, 128, 6554)])
+    n = ctypes.c_size_t()
+    assert lib.synthpix_workspace_size(pairs, 2, ctypes.byref(_rp(L)), None, 0, ctypes.byref(n)) == 0
+    fwd = n.value
+    assert fwd > 0 and fwd % 256 == 0
+    assert lib.synthpix_workspace_size(pairs, 2, ctypes.byref(_rp(L)), None, 1, ctypes.byref(n)) == 0
+    assert n.value > fwd
+    bad = [dict(sheet_sigma=0.0), dict(d_max=0.0), dict(d_max=17.0), dict(blur_radius=4),
+           dict(blur_radius=1, blur_sigma=0.0), dict(noise_sigma=-1.0), dict(bits=17)]
+    for kw in bad:
+        assert lib.synthpix_workspace_size(pairs, 2, ctypes.byref(_rp(L, **kw)), None, 0,
+                                           ctypes.byref(n)) == L.SP_ERR_INVALID_ARG, kw
+    t = L.Tiling(6, 32, 4096, 128)
+    assert lib.synthpix_workspace_size(pairs, 2, ctypes.byref(_rp(L)), ctypes.byref(t), 0,
+                                       ctypes.byref(n)) == L.SP_ERR_INVALID_ARG
+    big = _pairs(L, [(16384, 16384, 64, 64, 10)])
+    assert lib.synthpix_workspace_size(big, 1, ctypes.byref(_rp(L)), None, 0,
+                                       ctypes.byref(n)) == L.SP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("field,value", [("H", 0), ("W", 20000), ("Gh", 1), ("n_max", -1), ("reserved", 3)])
+def test_pair_table_validation(L, field, value):
+    lib = L.load()
+    pairs = _pairs(L, [(64, 64, 16, 16, 100)])
+    setattr(pairs[0], field, value)
+    sp_ = L.SeedParams(0.02, 0.02, 0, 1.0, 2.0, 0, 0, 0.8, 1.0, -1, 1)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    st = lib.synthpix_seed(pairs, fake, 1, ctypes.byref(sp_), 0, fake, fake, fake, fake, fake, None, None, None)
+    assert st == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_last_error()
+
+
+def test_seed_parameter_validation(L):
+    lib = L.load()
+    pairs = _pairs(L, [(64, 64, 16, 16, 82)])
+    fake = ctypes.c_void_p(0x1000)
+    cases = [L.SeedParams(0.0, 0.02, 0, 1.0, 2.0, 0, 0, 0.8, 1.0, -1, 1),     # ppp_lo = 0
+             L.SeedParams(0.03, 0.02, 0, 1.0, 2.0, 0, 0, 0.8, 1.0, -1, 1),    # lo > hi
+             L.SeedParams(0.02, 0.02, 5, 1.0, 2.0, 0, 0, 0.8, 1.0, -1, 1),    # unknown distribution
+             L.SeedParams(0.02, 0.02, 0, -1.0, 2.0, 0, 0, 0.8, 1.0, -1, 1),   # d <= 0
+             L.SeedParams(0.02, 0.02, 1, 2.5, 0.5, 0.0, 5.0, 0.8, 1.0, -1, 1),  # clip lo = 0
+             L.SeedParams(0.02, 0.02, 0, 1.0, 2.0, 0, 0, 1.0, 0.8, -1, 1),    # I0 lo > hi
+             L.SeedParams(0.02, 0.03, 0, 1.0, 2.0, 0, 0, 0.8, 1.0, -1, 1)]    # n_max != rule(ppp_hi)
+    for c in cases:
+        assert lib.synthpix_seed(pairs, fake, 1, ctypes.byref(c), 0, fake, fake, fake, fake, fake, None, None,
+                                 None) == L.SP_ERR_INVALID_ARG
+    good = L.SeedParams(0.02, 0.02, 0, 1.0, 2.0, 0, 0, 0.8, 1.0, -1, 1)
+    assert lib.synthpix_seed(pairs, fake, 1, ctypes.byref(good), 0, None, fake, fake, fake, fake, None, None,
+                             None) == L.SP_ERR_INVALID_ARG   # NULL output
+
+
+def test_advect_and_render_validation(L):
+    lib = L.load()
+    pairs = _pairs(L, [(64, 64, 16, 16, 100)])
+    fake = ctypes.c_void_p(0x1000)
+    ap = L.AdvectParams(1.0, 0, 1)
+    assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
+                               ctypes.c_void_p(0x3000), None) == L.SP_ERR_INVALID_ARG
+    ap = L.AdvectParams(1.0, 4, 7)
+    assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
+                               ctypes.c_void_p(0x3000), None) == L.SP_ERR_INVALID_ARG
+    ap = L.AdvectParams(1.0, 4, 1)
+    assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, fake, ctypes.c_void_p(0x3000),
+                               None) == L.SP_ERR_INVALID_ARG   # aliasing
+    # workspace too small / misaligned
+    rp = _rp(L)
+    st = lib.synthpix_render_pair(pairs, fake, 1, None, fake, fake, fake, fake, fake, fake, fake, ctypes.byref(rp),
+                                  fake, ctypes.c_void_p(0x10000), 256, None)
+    assert st == L.SP_ERR_WORKSPACE
+    st = lib.synthpix_render_pair(pairs, fake, 1, None, fake, fake, fake, fake, fake, fake, fake, ctypes.byref(rp),
+                                  fake, ctypes.c_void_p(0x10010), 1 << 30, None)
+    assert st == L.SP_ERR_WORKSPACE
+    # overlapping particle ranges
+    two = _pairs(L, [(64, 64, 16, 16, 100), (64, 64, 16, 16, 100)])
+    two[1].particle_offset = 50
+    assert lib.synthpix_render_pair(two, fake, 2, None, fake, fake, fake, fake, fake, fake, fake,
+                                    ctypes.byref(rp), fake, ctypes.c_void_p(0x10000), 1 << 30,
+                                    None) == L.SP_ERR_INVALID_ARG

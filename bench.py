@@ -1,0 +1,197 @@
+#!/usr/bin/env python
+"""Throughput of the generator's hot path on one MI355X.
+
+One step = one batch through the whole path: seed particles -> advect them
+through each pair's flow -> bin -> render both exposures -> blur, noise and
+integer codes, all inputs resident in HBM.  Default workload: 64 pairs of
+1024x1024 at 0.05 ppp (Lamb-Oseen flows, RK4 x4, 3x3 blur, noise 0.01,
+12-bit codes).  Prints ONE JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "image pairs/s & Gpx/s at 1024²,0.05 ppp; % HBM roofline; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+RENDER_SRC = os.path.join(ROOT, "paper_2512_09664_amd", "csrc", "bin_render.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_tile_scale_1024_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def describe(wl):
+    H, W = wl.sizes[0]
+    d = (f"U[{wl.d_params[0]}, {wl.d_params[1]}]" if wl.d_dist == "uniform"
+         else f"N({wl.d_params[0]}, {wl.d_params[1]}) clip [{wl.d_params[2]}, {wl.d_params[3]}]")
+    return {"workload": wl.name, "pairs": wl.n_pairs,
+            "sizes": "x".join(map(str, (H, W))) if len(set(wl.sizes)) == 1 else "uneven",
+            "ppp": list(wl.ppp), "d": d, "flow": f"{wl.flow} grid image/{wl.grid_div}",
+            "integrator": f"{wl.integrator}x{wl.substeps}", "blur_radius": wl.blur_radius,
+            "blur_sigma": wl.blur_sigma, "noise_sigma": wl.noise_sigma, "bits": wl.bits}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="scale_1024")
+    ap.add_argument("--plain-steps", type=int, default=3, help="steps of the per-pair-launch comparison")
+    ap.add_argument("--cpu-sample-pairs", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(pairs are independent: each GPU would run this same batch on its own share)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2512_09664_amd as sp
+    from workloads import get_workload, make_flows
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wl = get_workload(args.workload)
+    log(f"[bench] workload {wl.name}: {wl.n_pairs} pairs, building inputs")
+    flows = make_flows(wl.flow, wl.seed, wl.sizes, wl.grid_div, wl.max_disp, wl.dt, wl.uniform_uv)
+    n_max = [sp.particle_count(H, W, wl.ppp[1]) for (H, W) in wl.sizes]
+    batch = sp.PairBatch.build(wl.sizes, [f.shape[:2] for f in flows], n_max, device=dev)
+    flow = torch.from_numpy(np.concatenate([f.reshape(-1) for f in flows])).to(dev)
+    sprm = sp.seed_params(wl.ppp, wl.d_dist, wl.d_params, wl.I0, wl.z)
+    aprm = sp.advect_params(wl.dt, wl.substeps, wl.integrator)
+    rprm = sp.render_params(wl.sheet_sigma, wl.d_max, wl.blur_radius, wl.blur_sigma, wl.noise_sigma, wl.bits,
+                            wl.seed, wl.dt, wl.substeps, wl.integrator)
+    P = sp.seed(batch, sprm, wl.seed)
+    x2 = torch.empty_like(P["x"])
+    y2 = torch.empty_like(P["y"])
+    images = torch.empty(batch.n_pixels, dtype=sp.api.U16 if wl.bits else torch.float32, device=dev)
+    ws = sp.alloc_workspace(batch, rprm)
+
+    def step(k):
+        rprm.seed = wl.seed + k                       # a fresh batch of particles and noise per step
+        sp.seed(batch, sprm, wl.seed + k, out=P)
+        sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2)
+        sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, images, ws)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    flags = sp.read_status(ws)
+    if flags:
+        raise RuntimeError(f"device status flags {flags:#x}")
+    sp.timing_read(None)                              # drop anything recorded so far
+    sp.timing_enable(True)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sp.timing_enable(False)
+    kernels = {}
+    for name in ("seed", "advect", "bin_layout", "bin_count", "bin_scan", "bin_scatter", "render_tile"):
+        ms, n = sp.timing_read(name)
+        if n:
+            kernels[name] = {"avg_us": 1000.0 * ms / n, "launches": n}
+    elapsed = t1 - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    pairs_per_s = wl.n_pairs * args.steps / elapsed
+    px = wl.pixels()
+    gpx_per_s = px * args.steps / elapsed / 1e9
+    out_bytes = px * (2 if wl.bits else 4)
+    flow_bytes = int(flow.numel()) * 4
+    step_hbm_frac = (out_bytes + flow_bytes) / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+
+    # dominant kernel: the fused tile renderer; its algorithmic bytes are the stored codes
+    rt = kernels.get("render_tile", {"avg_us": float("nan")})
+    achieved = out_bytes / (rt["avg_us"] * 1e-6) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_sha") == source_sha(RENDER_SRC) and tr.get("workload") == wl.name:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+
+    # batched launch vs one launch sequence per pair, same GPU, same work
+    plain = None
+    if args.plain_steps > 0:
+        singles = []
+        for p in range(wl.n_pairs):
+            H, W = wl.sizes[p]
+            po = batch.host[p].particle_offset
+            fo = batch.host[p].flow_offset
+            io = batch.host[p].image_offset
+            b1 = sp.PairBatch.build([wl.sizes[p]], [flows[p].shape[:2]], [n_max[p]], [p], device=dev)
+            sl = slice(po, po + n_max[p])
+            singles.append((b1, flow[fo:fo + flows[p].size], {k: P[k][sl] for k in ("x", "y", "z", "d", "I0")},
+                            x2[sl], y2[sl], images[io:io + 2 * H * W]))
+        for b1, fl1, P1, x21, y21, im1 in singles:
+            P1["n_active"] = P["n_active"][:1]
+            P1["ppp"] = P["ppp"][:1]
+
+        def plain_step(k):
+            rprm.seed = wl.seed + k
+            for b1, fl1, P1, x21, y21, im1 in singles:
+                sp.seed(b1, sprm, wl.seed + k, out=P1)
+                sp.advect(b1, fl1, aprm, P1["x"], P1["y"], x21, y21)
+                sp.render_pair(b1, P1["x"], P1["y"], x21, y21, P1["z"], P1["d"], P1["I0"], rprm, None, im1, ws)
+
+        plain_step(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.plain_steps):
+            plain_step(k)
+        torch.cuda.synchronize()
+        plain_pairs_per_s = wl.n_pairs * args.plain_steps / (time.perf_counter() - t0)
+        plain = {"pairs_per_s": round(plain_pairs_per_s, 1), "batched_vs_plain": round(pairs_per_s / plain_pairs_per_s, 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import pipeline as opipe
+        n = min(args.cpu_sample_pairs, wl.n_pairs)
+        log(f"[bench] timing the float64 CPU oracle on {n} pairs")
+        t0 = time.perf_counter()
+        for p in range(n):
+            H, W = wl.sizes[p]
+            opipe.generate_pair(wl, p, flows[p], H, W)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(n / dt, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n} of {wl.n_pairs} pairs of {wl.name}, full path (seed, RK4 advect, render, blur, "
+                         f"noise, codes) in float64 NumPy, one process, {dt:.1f} s"}
+
+    line = {"metric": METRIC, "value": round(pairs_per_s, 1), "unit": "pairs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": describe(wl), "gpx_per_s": round(gpx_per_s, 2),
+            "step_hbm_frac": round(step_hbm_frac, 4), "kernels_us": {k: round(v["avg_us"], 2) for k, v in
+                                                                      kernels.items()},
+            "plain": plain, "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,15 @@ synthpix_status synthpix_bin_views_of(const synthpix_pair* pairs_host, int32_t n
  * has drained; returns SP_ERR_DEVICE_STATUS when any flag is set. */
 synthpix_status synthpix_read_status(const void* workspace_dev, void* stream, uint32_t* flags);
 
+/* Measurement helper: while enabled (on != 0), every kernel launch made by the
+ * library is bracketed by two hipEvents recorded on its stream.
+ * synthpix_timing_read waits for the recorded events of kernel `name` (NULL:
+ * all kernels), returns their summed elapsed milliseconds and launch count,
+ * and forgets them.  Kernel names: "seed", "advect", "bin_layout", "bin_count",
+ * "bin_scan", "bin_scatter", "render_tile" (and the backward's kernels). */
+synthpix_status synthpix_timing_enable(int32_t on);
+synthpix_status synthpix_timing_read(const char* name, double* total_ms, int64_t* launches);
+
 /* -------------------------------------------------------------- hot path */
 
 /* Seed every pair's n_max candidate particles (Section 2, "Sampling the

@@ -24,7 +24,10 @@ from . import philox as ph
 
 
 def blur_weights(radius: int, sigma: float) -> np.ndarray:
-    """float32 taps w[0..2b] (computed in float64, rounded once)."""
+    """float32 taps w[0..2b] (computed in float64, rounded once).  The blur width
+    is an acquisition parameter carried in binary32, so it is taken at its
+    binary32 value."""
+    sigma = float(np.float32(sigma))
     k = np.arange(-radius, radius + 1, dtype=np.float64)
     g = np.exp(-(k * k) / (2.0 * float(sigma) ** 2))
     return (g / g.sum()).astype(np.float32)

@@ -84,6 +84,8 @@ SIGNATURES = {
     "synthpix_workspace_size": [_PP, ctypes.c_int32, ctypes.POINTER(RenderParams), ctypes.POINTER(Tiling),
                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "synthpix_read_status": [_P, _P, ctypes.POINTER(ctypes.c_uint32)],
+    "synthpix_timing_enable": [ctypes.c_int32],
+    "synthpix_timing_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     "synthpix_bin_views_of": [_PP, ctypes.c_int32, ctypes.POINTER(RenderParams), ctypes.POINTER(Tiling),
                               ctypes.POINTER(BinViews)],
     "synthpix_seed": [_PP, _P, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.c_uint64,

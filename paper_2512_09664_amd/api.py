@@ -183,6 +183,18 @@ def bin_views(batch: PairBatch, rp, tile=None, workspace: torch.Tensor = None):
     return count, offset, entries
 
 
+def timing_enable(on: bool = True):
+    L.check(L.load().synthpix_timing_enable(1 if on else 0))
+
+
+def timing_read(name: Optional[str] = None):
+    """(total milliseconds, launches) of the timed launches of kernel ``name``."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    L.check(L.load().synthpix_timing_read(name.encode() if name else None, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 def read_status(workspace: torch.Tensor) -> int:
     flags = ctypes.c_uint32(0)
     st = L.load().synthpix_read_status(_ptr(workspace), _stream(), ctypes.byref(flags))

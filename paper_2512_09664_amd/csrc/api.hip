@@ -232,6 +232,19 @@ synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t
     return SP_OK;
 }
 
+synthpix_status synthpix_timing_enable(int32_t on)
+{
+    sp::timing_enable(on != 0);
+    return SP_OK;
+}
+
+synthpix_status synthpix_timing_read(const char* name, double* total_ms, int64_t* launches)
+{
+    if (!total_ms || !launches) return fail(SP_ERR_INVALID_ARG, "total_ms and launches must be non-NULL");
+    if (sp::timing_read(name, total_ms, launches) != 0) return fail(SP_ERR_HIP, "reading timing events failed");
+    return SP_OK;
+}
+
 synthpix_status synthpix_bin_views_of(const synthpix_pair* pairs_host, int32_t n_pairs,
                                       const synthpix_render_params* rp, const synthpix_tiling* tiling,
                                       synthpix_bin_views* out)

@@ -417,19 +417,31 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
     uint32_t* hist = reinterpret_cast<uint32_t*>(ws + wl.hist);
     int32_t* entries = reinterpret_cast<int32_t*>(ws + wl.entries);
 
-    hipLaunchKernelGGL(bin_layout, dim3(1), dim3(256), 0, s, a.pairs, a.n_pairs, cfg, L, status);
+    {
+        TimedScope ts("bin_layout", s);
+        hipLaunchKernelGGL(bin_layout, dim3(1), dim3(256), 0, s, a.pairs, a.n_pairs, cfg, L, status);
+    }
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
-    if (tot.chunks > 0)
+    if (tot.chunks > 0) {
+        TimedScope ts("bin_count", s);
         hipLaunchKernelGGL(bin_pass<false>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s,
                            a.pairs, L, a.n_pairs, a, cfg, hist, entries, status);
-    hipLaunchKernelGGL(bin_scan, dim3((unsigned)a.n_pairs, 2), dim3(256), 0, s, L, hist, tile_count,
-                       tile_offset, tot.tiles);
-    if (tot.chunks > 0)
+    }
+    {
+        TimedScope ts("bin_scan", s);
+        hipLaunchKernelGGL(bin_scan, dim3((unsigned)a.n_pairs, 2), dim3(256), 0, s, L, hist, tile_count,
+                           tile_offset, tot.tiles);
+    }
+    if (tot.chunks > 0) {
+        TimedScope ts("bin_scatter", s);
         hipLaunchKernelGGL(bin_pass<true>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s,
                            a.pairs, L, a.n_pairs, a, cfg, hist, entries, status);
-    if (tot.tiles > 0)
+    }
+    if (tot.tiles > 0) {
+        TimedScope ts("render_tile", s);
         hipLaunchKernelGGL(render_tile, dim3((unsigned)(2 * tot.tiles)), dim3(256), render_lds_bytes(cfg), s,
                            a.pairs, L, a.n_pairs, a, cfg, tile_count, tile_offset, entries, tot.tiles, status);
+    }
     return hipGetLastError();
 }
 

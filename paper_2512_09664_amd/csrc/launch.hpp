@@ -8,6 +8,21 @@
 
 namespace sp {
 
+// RAII bracket of one kernel launch with timing events (no-op unless enabled).
+class TimedScope {
+public:
+    TimedScope(const char* name, hipStream_t s);
+    ~TimedScope();
+    TimedScope(const TimedScope&) = delete;
+    TimedScope& operator=(const TimedScope&) = delete;
+private:
+    const char* name_;
+    hipStream_t stream_;
+    hipEvent_t start_;
+};
+void timing_enable(bool on);
+int timing_read(const char* name, double* total_ms, int64_t* launches);
+
 // Per-pair derived sizes of one render call (computed identically on host
 // and device from the pair table and the tiling).
 struct PairLayout {

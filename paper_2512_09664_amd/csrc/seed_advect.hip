@@ -170,6 +170,7 @@ hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_sp
                        const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
                        float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s)
 {
+    TimedScope ts("seed", s);
     if (n_active || ppp)
         hipLaunchKernelGGL(pair_scalars_kernel, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, pairs_dev,
                            n_pairs, prm, seed, n_active, ppp);
@@ -187,6 +188,7 @@ hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_
 {
     if (n_span <= 0) return hipSuccess;
     const int64_t blocks = (n_span + 255) / 256;
+    TimedScope ts("advect", s);
     hipLaunchKernelGGL(advect_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
                        flow, ap, x1, y1, x2, y2);
     return hipGetLastError();

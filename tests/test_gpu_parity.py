@@ -92,7 +92,10 @@ def test_advect_matches_oracle(ra, integ, n, dt):
         rx, ry = ra.advect(fl[p], H, W, parts[p]["x"], parts[p]["y"], dt, n, integ)
         assert np.array_equal(gx[sl], rx) and np.array_equal(gy[sl], ry), p
         ox, oy = oadv.advect(fl[p], H, W, parts[p]["x"], parts[p]["y"], dt, n, integ)
-        assert np.max(np.abs(gx[sl] - ox)) < 1e-4 and np.max(np.abs(gy[sl] - oy)) < 1e-4
+        # binary32 drift: about two roundings of the position per substep plus the
+        # start value's own spacing
+        tol = (4 + 2 * n) * float(np.spacing(np.float32(max(np.abs(ox).max(), np.abs(oy).max()))))
+        assert np.max(np.abs(gx[sl] - ox)) <= tol and np.max(np.abs(gy[sl] - oy)) <= tol
 
 
 # ----------------------------------------------------------------------------- render
@@ -226,53 +229,80 @@ def test_codes_bit_exact_noise_off(ra, bits):
 
 
 def test_noise_matches_oracle():
+    """Noise uses the GPU's fast log/sqrt/sin/cos, so it is compared within
+    tolerance: float images within 1e-5 of the peak; integer codes equal except
+    where the float64 value K * L lies within L * eps of a rounding boundary,
+    eps being the largest float difference measured on the same draws."""
     sizes = [(64, 130), (32, 32)]
     arrs, n_max = _render_case(61, sizes, 300, zero_frac=0.0)
     pids = [4, 9]
     b = gu.batch_for(sizes, [(4, 4)] * 2, n_max, pids)
     sigma = 0.02
-    for bits in (0, 12):
-        rp = sp.render_params(0.5, 5.0, 1, 0.7, sigma, bits, seed=77)
-        img = _render_gpu(b, arrs, rp)
-        w = oep.blur_weights(1, 0.7)
-        o = po = 0
-        for p, (H, W) in enumerate(sizes):
-            sl = slice(po, po + n_max[p])
-            po += n_max[p]
-            for f, (xk, yk) in enumerate((("x1", "y1"), ("x2", "y2"))):
-                J = oep.blur(orend.render_frame(arrs[xk][sl], arrs[yk][sl], arrs["z"][sl], arrs["d"][sl],
-                                                arrs["I0"][sl], H, W, 0.5), w)
-                K = J + sigma * oep.noise_normals(H, W, f, pids[p], 77)
-                got = img[o:o + H * W].reshape(H, W)
-                o += H * W
-                if bits == 0:
-                    assert np.max(np.abs(got - K)) <= TOL * max(1.0, J.max()), (p, f)
-                else:
-                    q = oep.quantise(K, bits).astype(np.int64)
-                    diff = np.abs(got.astype(np.int64) - q)
-                    assert diff.max() <= 1, (p, f)
-                    # a code may differ only where K * L sits within 1e-4 of a half-integer
-                    frac = np.abs((K * 4095) % 1.0 - 0.5)
-                    assert np.all(frac[diff > 0] < 1e-4), (p, f)
+    w = oep.blur_weights(1, 0.7)
+    refs = []
+    o = po = 0
+    for p, (H, W) in enumerate(sizes):
+        sl = slice(po, po + n_max[p])
+        po += n_max[p]
+        for f, (xk, yk) in enumerate((("x1", "y1"), ("x2", "y2"))):
+            J = oep.blur(orend.render_frame(arrs[xk][sl], arrs[yk][sl], arrs["z"][sl], arrs["d"][sl],
+                                            arrs["I0"][sl], H, W, 0.5), w)
+            refs.append((o, H, W, J, J + np.float32(sigma) * oep.noise_normals(H, W, f, pids[p], 77)))
+            o += H * W
+    img = _render_gpu(b, arrs, sp.render_params(0.5, 5.0, 1, 0.7, sigma, 0, seed=77), None)
+    eps = 0.0
+    for (o, H, W, J, K) in refs:
+        got = img[o:o + H * W].reshape(H, W)
+        err = np.max(np.abs(got - K))
+        assert err <= TOL * max(1.0, J.max())
+        eps = max(eps, err)
+    L = 4095
+    codes = _render_gpu(b, arrs, sp.render_params(0.5, 5.0, 1, 0.7, sigma, 12, seed=77), None)
+    for (o, H, W, J, K) in refs:
+        got = codes[o:o + H * W].reshape(H, W).astype(np.int64)
+        q = oep.quantise(K, 12).astype(np.int64)
+        diff = np.abs(got - q)
+        assert diff.max() <= 1
+        dist = np.abs((K * L) % 1.0 - 0.5)            # distance to the nearest rounding boundary
+        assert np.all(dist[diff > 0] <= L * eps * 1.01 + 1e-9), (dist[diff > 0], eps)
 
 
 # ----------------------------------------------------------------------------- end to end
 
 def _e2e(ra, wl, n_check=None):
-    batch, flows, P, x2, y2, img = gu.run_pipeline(wl, noise=0.0)
-    im = gu.to_np(img)
+    """Whole path, noise off.  (1) GPU output bit-exact with the binary32 mirror
+    (codes or floats).  (2) GPU float images within 1e-5 of the peak of the
+    float64 render+blur of the mirror's binary32 positions: the render and blur
+    arithmetic against the definition.  (3) The error against the all-float64
+    pipeline (positions integrated in float64 too) is reported; it adds the
+    binary32 spacing of the positions times the image gradient, and is only
+    held to 1e-3 of the peak."""
+    _, flows, _, _, _, img = gu.run_pipeline(wl, noise=0.0)
+    _, _, _, _, _, fimg = gu.run_pipeline(wl, noise=0.0, bits=0)
+    im, fim = gu.to_np(img), gu.to_np(fimg)
+    w = oep.blur_weights(wl.blur_radius, wl.blur_sigma) if wl.blur_radius else None
     o = 0
     for p, (H, W) in enumerate(wl.sizes):
         n = 2 * H * W
         if n_check is None or p in n_check:
             _say("e2e", wl.name, p, H, W)
-            got = im[o:o + n].reshape(2, H, W)
             mir = ra.generate_pair_noiseless(wl, p, flows[p], H, W)
             key = "codes" if wl.bits > 0 else "J"
-            assert np.array_equal(got, mir[key]), (wl.name, p)
-            if wl.bits == 0:
-                ref = opipe.generate_pair(wl.with_(noise_sigma=0.0), p, flows[p], H, W)["J"]
-                assert np.max(np.abs(got - ref)) <= TOL * ref.max(), (wl.name, p)
+            assert np.array_equal(im[o:o + n].reshape(2, H, W), mir[key]), (wl.name, p)
+            got = fim[o:o + n].reshape(2, H, W)
+            assert np.array_equal(got, ra.generate_pair_noiseless(wl.with_(bits=0), p, flows[p], H, W)["J"])
+            Pm = mir["particles"]
+            ref = np.stack([orend.render_frame(xx, yy, Pm["z"], Pm["d"], Pm["I0"], H, W, wl.sheet_sigma)
+                            for (xx, yy) in ((Pm["x"], Pm["y"]), (mir["x2"], mir["y2"]))])
+            if w is not None:
+                ref = np.stack([oep.blur(ref[0], w), oep.blur(ref[1], w)])
+            peak = max(ref.max(), 1e-30)
+            assert np.max(np.abs(got - ref)) <= TOL * peak, (wl.name, p)
+            full = opipe.generate_pair(wl.with_(noise_sigma=0.0), p, flows[p], H, W)["J"]
+            err64 = float(np.max(np.abs(got - full)))
+            print(f"[e2e] {wl.name} pair {p}: max |GPU - float64 pipeline| = {err64:.3e} "
+                  f"({err64 / peak:.2e} of peak)", flush=True)
+            assert err64 <= 1e-3 * peak
         o += n
 
 
@@ -346,7 +376,10 @@ def test_full_size_scale_1024_sampled(ra):
                 g = int(im[p * 2 * plane + f * plane + r * W + c])
                 assert abs(g - q) <= 1, (p, f, r, c, g, q, K)
                 if abs(g - q) == 1:
-                    assert abs((K * 4095) % 1.0 - 0.5) < 1e-4
+                    # only next to a rounding boundary: float error budget 1e-5 of the
+                    # noise term plus the render's 1e-6 of full scale
+                    bound = 4095 * (1e-5 * wl.noise_sigma * abs(noise[r, c]) + 1e-6)
+                    assert abs((K * 4095) % 1.0 - 0.5) <= bound, (p, f, r, c)
                 checked += 1
     assert checked == 3 * 2 * 24
     # noise off: whole pairs bit-exact against the mirror

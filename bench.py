@@ -56,6 +56,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3, help="steps of the per-pair-launch comparison")
     ap.add_argument("--cpu-sample-pairs", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="also run a plain device copy of MB megabytes (counter calibration under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -111,7 +113,7 @@ def main():
     t1 = time.perf_counter()
     sp.timing_enable(False)
     kernels = {}
-    for name in ("seed", "advect", "bin_layout", "bin_count", "bin_scan", "bin_scatter", "render_tile"):
+    for name in ("seed", "advect", "bin_layout", "prep", "bin_count", "bin_scan", "bin_scatter", "render_tile"):
         ms, n = sp.timing_read(name)
         if n:
             kernels[name] = {"avg_us": 1000.0 * ms / n, "launches": n}
@@ -168,6 +170,15 @@ def main():
         torch.cuda.synchronize()
         plain_pairs_per_s = wl.n_pairs * args.plain_steps / (time.perf_counter() - t0)
         plain = {"pairs_per_s": round(plain_pairs_per_s, 1), "batched_vs_plain": round(pairs_per_s / plain_pairs_per_s, 3)}
+
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {nbytes} bytes")
 
     cpu = None
     if not args.no_cpu_baseline:

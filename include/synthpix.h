@@ -122,12 +122,13 @@ typedef struct {
     synthpix_advect_params advect;  /* used by the backward to recompute frame-2 positions  */
 } synthpix_render_params;
 
-/* Screen tiling used by the renderer.  Tiles are tile_w x tile_h pixels
- * (multiples of 4 and 8 respectively, 8 .. 128).  NULL selects the default. */
+/* Screen tiling used by the renderer.  Tiles are tile_w x tile_h pixels, one of
+ * 8x8, 16x16, 32x16, 32x32, 64x16, 64x32, 64x64, 128x32.  NULL selects the
+ * default. */
 typedef struct {
     int32_t tile_w, tile_h;
     int32_t chunk;              /* particles per binning block (256 .. 16384, multiple of 256) */
-    int32_t cap;                /* particles staged in LDS per render pass (32 .. 512)        */
+    int32_t cap;                /* particles staged in LDS per render pass (32 .. 256)        */
 } synthpix_tiling;
 
 /* ---------------------------------------------------------------- helpers */

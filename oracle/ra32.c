@@ -22,8 +22,9 @@
  *   - ln and cos(2 pi u) for the Box-Muller normal of the diameter use the same
  *     style of reduction (atanh series, quadrant reduction).
  *   - a particle's contribution to a pixel is quantised to 2^-24 full-scale
- *     units, t = ((A * 2^24) * gy) * gx truncated to an unsigned 32-bit integer,
- *     and summed in 32-bit integers: the sum is exact and order-free.
+ *     units, t = (min(A * 2^24, 2^32 - 256) * gy) * gx truncated to an unsigned
+ *     32-bit integer, and summed in 32-bit integers: the sum is exact and
+ *     order-free.
  */
 #include <math.h>
 #include <stdint.h>
@@ -255,12 +256,9 @@ int ra_support_range(float p, float R, int n, int* lo, int* hi)
 
 /* --------------------------------------------------------------- rendering */
 
-static uint32_t quant(float t)
-{
-    if (!(t > 0.0f)) return 0u;
-    if (t >= 4294967296.0f) return 0xffffffffu;
-    return (uint32_t)t;
-}
+/* t = (Af gy) gx with 0 <= gx, gy <= 1 and 0 <= Af <= 2^32 - 256, so t fits an
+ * unsigned 32-bit integer: plain truncation. */
+static uint32_t quant(float t) { return (uint32_t)t; }
 
 /* Fixed-point exposure: acc[r*W + c] = sum over particles of the 2^-24-quantised
  * contribution.  sheet_sigma is the Gaussian laser-sheet width s. */
@@ -278,7 +276,7 @@ void ra_render_fixed(int H, int W, int n, const float* x, const float* y, const 
         if (!ra_support_range(y[i], R, H, &r0, &r1)) continue;
         if (c1 - c0 >= 1024) continue;             /* diameters beyond ~340 px are not modelled */
         const float A = I0[i] * ra_E((z[i] * z[i]) * cs);
-        const float Af = A * 16777216.0f;
+        const float Af = fminf(A * 16777216.0f, 4294967040.0f);   /* 2^24 A, at most 2^32 - 256 */
         const float kap = 8.0f / (d[i] * d[i]);
         for (int c = c0; c <= c1; ++c) {
             float dx = ((float)c + 0.5f) - x[i];

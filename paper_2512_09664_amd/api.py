@@ -132,6 +132,12 @@ def tiling(tile_w=32, tile_h=32, chunk=4096, cap=128):
     return t
 
 
+def default_tiling(batch: PairBatch, rp):
+    t = L.Tiling()
+    L.check(L.load().synthpix_default_tiling(batch.host_ptr, batch.n_pairs, ctypes.byref(rp), ctypes.byref(t)))
+    return t
+
+
 def seed(batch: PairBatch, sp, seed_value: int, out=None):
     """Run ``synthpix_seed``; returns dict x, y, z, d, I0 (float32 [n_particles])
     plus n_active (int32 [n_pairs]) and ppp (float64 [n_pairs])."""

@@ -90,11 +90,12 @@ synthpix_status check_render_params(const synthpix_render_params* rp)
 
 synthpix_status check_tiling(const synthpix_tiling& t)
 {
-    if (t.tile_w < 8 || t.tile_w > 128 || (t.tile_w & 3) || t.tile_h < 8 || t.tile_h > 128 || (t.tile_h & 7))
-        return fail(SP_ERR_INVALID_ARG, "tile must be 8..128 wide (multiple of 4) and 8..128 high (multiple of 8)");
+    if (!sp::render_shape_supported(t.tile_w, t.tile_h))
+        return fail(SP_ERR_INVALID_ARG, "tile %d x %d is not one of the compiled shapes (8x8, 16x16, 32x16, 32x32, "
+                    "64x16, 64x32, 64x64, 128x32)", t.tile_w, t.tile_h);
     if (t.chunk < 256 || t.chunk > 16384 || (t.chunk & 255))
         return fail(SP_ERR_INVALID_ARG, "chunk must be a multiple of 256 in [256, 16384]");
-    if (t.cap < 32 || t.cap > 512) return fail(SP_ERR_INVALID_ARG, "cap must be in [32, 512]");
+    if (t.cap < 32 || t.cap > 256) return fail(SP_ERR_INVALID_ARG, "cap must be in [32, 256]");
     return SP_OK;
 }
 
@@ -118,9 +119,14 @@ sp::RenderConfig make_config(const synthpix_render_params& rp, const synthpix_ti
     c.cap = t.cap;
     c.apron = rp.blur_radius;
     c.d_max = rp.d_max;
+    c.log_tw = 0;
+    while ((1 << c.log_tw) < c.tile_w) ++c.log_tw;
+    c.log_th = 0;
+    while ((1 << c.log_th) < c.tile_h) ++c.log_th;
     const int span = (int)std::floor(3.0 * (double)rp.d_max) + 4;   // patch side bound incl. rounding
     const int RW = c.tile_w + 2 * c.apron, RH = c.tile_h + 2 * c.apron;
     c.wmax = span < (RW > RH ? RW : RH) ? span : (RW > RH ? RW : RH);
+    c.wm4 = (c.wmax + 3) & ~3;
     c.kx = (span + 2 * c.apron) / c.tile_w + 2;
     c.ky = (span + 2 * c.apron) / c.tile_h + 2;
     return c;
@@ -164,6 +170,7 @@ sp::WorkspaceLayout workspace_layout(int32_t n_pairs, const sp::BatchTotals& T, 
     w.tile_offset = o; o = align256(o + sizeof(int64_t) * 2 * (size_t)T.tiles);
     w.hist = o; o = align256(o + sizeof(uint32_t) * (size_t)T.hist);
     w.entries = o; o = align256(o + sizeof(int32_t) * (size_t)T.entries);
+    w.records = o; o = align256(o + 2 * 16 * (size_t)T.n_span);
     if (backward) {
         size_t px = 0;
         for (int32_t p = 0; p < n_pairs; ++p) px += 2 * (size_t)ph[p].H * ph[p].W;
@@ -179,10 +186,10 @@ sp::WorkspaceLayout workspace_layout(int32_t n_pairs, const sp::BatchTotals& T, 
 synthpix_tiling default_tiling()
 {
     synthpix_tiling t;
-    t.tile_w = 32;
+    t.tile_w = 64;
     t.tile_h = 32;
     t.chunk = 4096;
-    t.cap = 128;
+    t.cap = 64;
     return t;
 }
 
@@ -360,8 +367,8 @@ synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synt
     if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < wl.total)
         return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, wl.total);
-    if (sp::render_lds_bytes(cfg) > 65536)
-        return fail(SP_ERR_UNSUPPORTED, "tiling needs %zu bytes of LDS per workgroup (max 65536)",
+    if (sp::render_lds_bytes(cfg) > 160 * 1024)
+        return fail(SP_ERR_UNSUPPORTED, "tiling needs %zu bytes of LDS per workgroup (max 163840)",
                     sp::render_lds_bytes(cfg));
     sp::RenderArgs a{};
     a.pairs = pairs_dev;

@@ -7,6 +7,8 @@
 //
 // Pipeline of one call (all pairs of a batch at once):
 //   bin_layout  : per-pair prefix tables (one block)
+//   prep        : per particle and frame, a 16-byte record (x, y, d, fixed-point
+//                 peak); d < 0 marks a particle that adds nothing
 //   bin_count   : per (pair, frame, particle chunk) LDS histogram of tile hits
 //   bin_scan    : per (pair, frame) exclusive scan -> tile offsets and per-chunk bases
 //   bin_scatter : per chunk, LDS cursors -> particle indices into tile lists
@@ -97,29 +99,53 @@ bin_layout(const synthpix_pair* __restrict__ pairs, int n_pairs, RenderConfig cf
     }
 }
 
+// ------------------------------------------------------------------ particle records
+
+// Per particle and frame: (x, y, d, Af) with Af = min(2^24 I0 exp(-z^2 / (2 s^2)),
+// 2^32 - 256).  d is replaced by -1 for particles that add nothing (I0 <= 0,
+// d <= 0 or not a number, non-finite position) or whose d exceeds d_max (flagged).
+__global__ void __launch_bounds__(256)
+prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span, RenderArgs a,
+             float d_max, float4* __restrict__ rec0, float4* __restrict__ rec1, uint32_t* __restrict__ status)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_span) return;
+    const int p = find_pair_by_particle(pairs, n_pairs, g);
+    const int64_t i = g - pairs[p].particle_offset;
+    if (i < 0 || i >= pairs[p].n_max) return;
+    const float cs = 0.5f / (a.sheet_sigma * a.sheet_sigma);
+    const float z = a.z[g], d = a.d[g], I0 = a.I0[g];
+    const float x1 = a.x[0][g], y1 = a.y[0][g], x2 = a.x[1][g], y2 = a.y[1][g];
+    const float Af = fixed_peak(I0 * expneg((z * z) * cs));
+    float dd = d;
+    if (!(I0 > 0.0f) || !(d > 0.0f)) dd = -1.0f;
+    if (dd > 0.0f && !(d <= d_max)) {
+        atomicOr(status, SP_STATUS_D_ABOVE_MAX);
+        dd = -1.0f;
+    }
+    const float d1 = (__builtin_isfinite(x1) && __builtin_isfinite(y1)) ? dd : -1.0f;
+    const float d2 = (__builtin_isfinite(x2) && __builtin_isfinite(y2)) ? dd : -1.0f;
+    rec0[g] = make_float4(x1, y1, d1, Af);
+    rec1[g] = make_float4(x2, y2, d2, Af);
+}
+
 // ------------------------------------------------------------------ membership
 
-// Tile rectangle touched by one particle in one frame: its support, clipped to
-// the image, grown by the blur apron.  False when the particle adds nothing.
-__device__ __forceinline__ bool tile_rect(float x, float y, float d, float I0, int H, int W,
-                                          const RenderConfig& cfg, int ntx, int nty,
-                                          int& tx0, int& tx1, int& ty0, int& ty1,
-                                          uint32_t* status)
+// Tile rectangle touched by one particle record: its support, clipped to the
+// image, grown by the blur apron.  False when the particle adds nothing.
+__device__ __forceinline__ bool tile_rect(const float4 r, int H, int W, const RenderConfig& cfg, int ntx, int nty,
+                                          int& tx0, int& tx1, int& ty0, int& ty1)
 {
-    if (!particle_valid(x, y, d, I0)) return false;
-    if (!(d <= cfg.d_max)) {
-        atomicOr(status, SP_STATUS_D_ABOVE_MAX);
-        return false;
-    }
-    const float R = 1.5f * d;
+    if (!(r.z > 0.0f)) return false;
+    const float R = 1.5f * r.z;
     int c0, c1, r0, r1;
-    if (!support_range(x, R, W, c0, c1)) return false;
-    if (!support_range(y, R, H, r0, r1)) return false;
+    if (!support_range(r.x, R, W, c0, c1)) return false;
+    if (!support_range(r.y, R, H, r0, r1)) return false;
     const int b = cfg.apron;
-    tx0 = c0 - b < 0 ? 0 : (c0 - b) / cfg.tile_w;
-    ty0 = r0 - b < 0 ? 0 : (r0 - b) / cfg.tile_h;
-    tx1 = (c1 + b) / cfg.tile_w;
-    ty1 = (r1 + b) / cfg.tile_h;
+    tx0 = c0 - b < 0 ? 0 : (c0 - b) >> cfg.log_tw;
+    ty0 = r0 - b < 0 ? 0 : (r0 - b) >> cfg.log_th;
+    tx1 = (c1 + b) >> cfg.log_tw;
+    ty1 = (r1 + b) >> cfg.log_th;
     tx1 = tx1 > ntx - 1 ? ntx - 1 : tx1;
     ty1 = ty1 > nty - 1 ? nty - 1 : ty1;
     return true;
@@ -130,29 +156,26 @@ __device__ __forceinline__ bool tile_rect(float x, float y, float d, float I0, i
 template <bool SCATTER>
 __global__ void __launch_bounds__(256)
 bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
-         RenderArgs a, RenderConfig cfg, uint32_t* __restrict__ hist, int32_t* __restrict__ entries,
-         uint32_t* __restrict__ status)
+         const float4* __restrict__ rec0, const float4* __restrict__ rec1, RenderConfig cfg,
+         uint32_t* __restrict__ hist, int32_t* __restrict__ entries, unsigned n_chunks_total)
 {
     extern __shared__ uint32_t lh[];
     const int f = blockIdx.y;
-    const int p = find_pair_by_chunk(L, n_pairs, blockIdx.x);
+    const unsigned cb = xcd_contiguous(blockIdx.x, n_chunks_total);
+    const int p = find_pair_by_chunk(L, n_pairs, cb);
     const synthpix_pair P = pairs[p];
     const PairLayout PL = L[p];
-    const int chunk = blockIdx.x - PL.chunk_base;
+    const int chunk = (int)cb - PL.chunk_base;
     const int nt = PL.ntx * PL.nty;
     uint32_t* gh = hist + PL.hist_base + ((int64_t)f * PL.n_chunks + chunk) * nt;
     for (int t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = SCATTER ? gh[t] : 0u;
     __syncthreads();
     const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
-    const float* __restrict__ xf = a.x[f];
-    const float* __restrict__ yf = a.y[f];
+    const float4* __restrict__ rec = f ? rec1 : rec0;
     int32_t* seg = entries + PL.entry_base + (int64_t)f * PL.entry_cap;
     for (int i = chunk * cfg.chunk + threadIdx.x; i < i_end; i += blockDim.x) {
-        const int64_t g = P.particle_offset + i;
         int tx0, tx1, ty0, ty1;
-        if (!tile_rect(xf[g], yf[g], a.d[g], a.I0[g], P.H, P.W, cfg, PL.ntx, PL.nty, tx0, tx1, ty0, ty1,
-                       status))
-            continue;
+        if (!tile_rect(rec[P.particle_offset + i], P.H, P.W, cfg, PL.ntx, PL.nty, tx0, tx1, ty0, ty1)) continue;
         for (int ty = ty0; ty <= ty1; ++ty)
             for (int tx = tx0; tx <= tx1; ++tx) {
                 const uint32_t slot = atomicAdd(&lh[ty * PL.ntx + tx], 1u);
@@ -212,199 +235,339 @@ bin_scan(const PairLayout* __restrict__ L, uint32_t* __restrict__ hist, uint32_t
 
 // ------------------------------------------------------------------ render
 
-struct StagedParticle {
-    int c0, w, r0, h;        // patch rectangle in region-local pixels
-    float Af, kap, x, y;     // 2^24 * peak, 8/d^2, position
+// LDS carve-up of one render workgroup (all offsets 16-byte aligned).
+struct RenderLds {
+    int acc_words;           // RH * RW + 8 of slack, rounded up to a multiple of 4
+    int tables;              // CAP * WM4 floats per table
+    size_t bytes;
 };
 
+__host__ __device__ inline RenderLds render_lds_shape(int tw, int th, int apron, int cap, int wm4)
+{
+    RenderLds L;
+    const int RW = tw + 2 * apron, RH = th + 2 * apron;
+    L.acc_words = (RH * RW + 8 + 3) & ~3;
+    L.tables = cap * wm4;
+    size_t work = (size_t)cap * 16                                  // staged (x, y, kappa, Af)
+                + (size_t)cap * 4                                   // staged patch box
+                + 2 * (size_t)L.tables * sizeof(float)              // gx, rs
+                + 2 * (size_t)L.tables * sizeof(uint16_t)           // work items
+                + 64;                                                // scan scratch
+    size_t blur = (size_t)RH * tw * sizeof(float);
+    L.bytes = (size_t)L.acc_words * 4 + (work > blur ? work : blur);
+    return L;
+}
+
+__host__ __device__ inline RenderLds render_lds(const RenderConfig& c)
+{
+    return render_lds_shape(c.tile_w, c.tile_h, c.apron, c.cap, c.wm4);
+}
+
+// Exclusive block scan of two counters (256 threads = 4 waves of 64).
+__device__ __forceinline__ void scan2(int a, int b, int* s_wave, int& ea, int& eb, int& ta, int& tb)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    int ia = a, ib = b;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int xa = __shfl_up(ia, off, 64);
+        const int xb = __shfl_up(ib, off, 64);
+        if (lane >= off) { ia += xa; ib += xb; }
+    }
+    if (lane == 63) { s_wave[wid] = ia; s_wave[4 + wid] = ib; }
+    __syncthreads();
+    int pa = 0, pb = 0;
+    ta = tb = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int va = s_wave[w], vb = s_wave[4 + w];
+        if (w < wid) { pa += va; pb += vb; }
+        ta += va;
+        tb += vb;
+    }
+    ea = pa + ia - a;
+    eb = pb + ib - b;
+}
+
+__device__ __forceinline__ uint32_t pack_box(int c0, int w, int r0, int h)
+{
+    return (uint32_t)c0 | ((uint32_t)w << 8) | ((uint32_t)r0 << 16) | ((uint32_t)h << 24);
+}
+
+// Tile renderer, templated on the tile shape and the blur radius (tile-local
+// index arithmetic becomes shifts, blur loops unroll).
+template <int TW, int TH, int B>
 __global__ void __launch_bounds__(256)
 render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
-            RenderArgs a, RenderConfig cfg, const uint32_t* __restrict__ tile_count,
-            const int64_t* __restrict__ tile_offset, const int32_t* __restrict__ entries,
-            int64_t tiles_total, uint32_t* __restrict__ status)
+            const float4* __restrict__ rec0, const float4* __restrict__ rec1, EpilogueArgs a, int cap, int wm4,
+            const uint32_t* __restrict__ tile_count, const int64_t* __restrict__ tile_offset,
+            const int32_t* __restrict__ entries, int64_t tiles_total, uint32_t* __restrict__ status)
 {
+    static_assert(TW % 4 == 0 && (TW & (TW - 1)) == 0 && (TH & (TH - 1)) == 0, "power-of-two tiles");
+    static_assert(TW + 6 < 256 && TH + 6 < 256, "patch boxes are packed in bytes");
+    static_assert(B >= 0 && B <= 3, "blur radius 0..3");
+    constexpr int Q4 = TW / 4;
+    float wb[2 * B + 1];
+#pragma unroll
+    for (int q = 0; q <= 2 * B; ++q) wb[q] = a.blur_w[q];
     extern __shared__ __align__(16) unsigned char smem[];
-    const int b = cfg.apron;
-    const int RW = cfg.tile_w + 2 * b;
-    const int RH = cfg.tile_h + 2 * b;
-    const int CAP = cfg.cap;
-    const int WM = cfg.wmax;
-    uint32_t* acc = reinterpret_cast<uint32_t*>(smem);                       // RH * RW
-    StagedParticle* sp_ = reinterpret_cast<StagedParticle*>(acc + RH * RW);  // CAP
-    float* gx = reinterpret_cast<float*>(sp_ + CAP);                         // CAP * WM
-    float* rs = gx + CAP * WM;                                               // CAP * WM
-    float* tmp = reinterpret_cast<float*>(sp_);   // blur scratch RH * tile_w, reuses the tables
+    const RenderLds lay = render_lds_shape(TW, TH, B, cap, wm4);
+    constexpr int b = B;
+    constexpr int RW = TW + 2 * B;
+    constexpr int RH = TH + 2 * B;
+    const int WM = wm4;
+    uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
+    float4* stg = reinterpret_cast<float4*>(acc + lay.acc_words);       // (x, y, kappa, Af)
+    uint32_t* box = reinterpret_cast<uint32_t*>(stg + cap);              // c0 | w | r0 | h bytes
+    float* gx = reinterpret_cast<float*>(box + cap);
+    float* rs = gx + lay.tables;
+    uint16_t* items = reinterpret_cast<uint16_t*>(rs + lay.tables);     // 2 * tables entries
+    int* s_wave = reinterpret_cast<int*>(items + 2 * lay.tables);
+    float* tmp = reinterpret_cast<float*>(stg);   // blur scratch, reuses the particle tables
     __shared__ unsigned long long s_asum;
 
-    const int64_t item = blockIdx.x;
-    const int f = (int)(item / tiles_total);
+    // one (frame, tile) item per workgroup; XCD-contiguous numbering keeps
+    // neighbouring tiles (which share particles) on one L2
+    const int64_t item = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int f = item >= tiles_total ? 1 : 0;
     const int64_t tile = item - (int64_t)f * tiles_total;
     const int p = find_pair_by_tile(L, n_pairs, tile);
-    const synthpix_pair P = pairs[p];
-    const PairLayout PL = L[p];
-    const int tl = (int)(tile - PL.tile_base);
-    const int tx = tl % PL.ntx;
-    const int ty = tl / PL.ntx;
-    const int rx0 = tx * cfg.tile_w - b;   // region origin in image pixels
-    const int ry0 = ty * cfg.tile_h - b;
+    const int pW = pairs[p].W, pH = pairs[p].H;
+    const int64_t p_off = pairs[p].particle_offset, p_img = pairs[p].image_offset;
+    const uint64_t pid = pairs[p].pair_id;
+    const int64_t tile_base = L[p].tile_base;
+    const int ntx = L[p].ntx;
+    const int tl = (int)(tile - tile_base);
+    const int ty = tl / ntx;
+    const int tx = tl - ty * ntx;
+    const int rx0 = tx * TW - b;          // region origin in image pixels
+    const int ry0 = ty * TH - b;
     const int cnt = (int)tile_count[item];
     const int64_t off = tile_offset[item];
-    const float cs = 0.5f / (a.sheet_sigma * a.sheet_sigma);
-    const float* __restrict__ xf = a.x[f];
-    const float* __restrict__ yf = a.y[f];
+    const float4* __restrict__ rec = f ? rec1 : rec0;
 
-    for (int k = threadIdx.x; k < RH * RW; k += blockDim.x) acc[k] = 0u;
+    for (int k = threadIdx.x; k < (lay.acc_words >> 2); k += 256)
+        reinterpret_cast<uint4*>(acc)[k] = make_uint4(0u, 0u, 0u, 0u);
     if (threadIdx.x == 0) s_asum = 0ull;
 
-    for (int base = 0; base < cnt; base += CAP) {
-        const int n = min(CAP, cnt - base);
+    for (int base = 0; base < cnt; base += cap) {
+        const int n = min(cap, cnt - base);
         __syncthreads();
+        // stage: one particle per thread
+        int w = 0, h = 0, c0 = 0, r0 = 0;
         if ((int)threadIdx.x < n) {
             const int idx = entries[off + base + threadIdx.x];
-            const int64_t g = P.particle_offset + idx;
-            const float x = xf[g], y = yf[g], z = a.z[g], d = a.d[g], I0 = a.I0[g];
-            const float R = 1.5f * d;
-            int c0 = 0, c1 = -1, r0 = 0, r1 = -1;
-            StagedParticle s;
-            s.w = 0;
-            s.h = 0;
-            if (support_range(x, R, P.W, c0, c1) && support_range(y, R, P.H, r0, r1)) {
-                c0 = max(c0, rx0);
-                c1 = min(c1, rx0 + RW - 1);
-                r0 = max(r0, ry0);
-                r1 = min(r1, ry0 + RH - 1);
-                if (c0 <= c1 && r0 <= r1) {
-                    s.c0 = c0 - rx0;
-                    s.r0 = r0 - ry0;
-                    s.w = c1 - c0 + 1;
-                    s.h = r1 - r0 + 1;
-                    if (s.w > WM || s.h > WM) {          // cannot happen for d <= d_max
+            const float4 r = rec[p_off + idx];
+            const float R = 1.5f * r.z;
+            int a0, a1, b0, b1;
+            if (support_range(r.x, R, pW, a0, a1) && support_range(r.y, R, pH, b0, b1)) {
+                a0 = max(a0, rx0);
+                a1 = min(a1, rx0 + RW - 1);
+                b0 = max(b0, ry0);
+                b1 = min(b1, ry0 + RH - 1);
+                if (a0 <= a1 && b0 <= b1) {
+                    w = a1 - a0 + 1;
+                    h = b1 - b0 + 1;
+                    if (w > WM || h > WM) {            // cannot happen for d <= d_max
                         atomicOr(status, SP_STATUS_D_ABOVE_MAX);
-                        s.w = 0;
-                        s.h = 0;
+                        w = 0;
+                        h = 0;
                     }
+                    c0 = a0 - rx0;
+                    r0 = b0 - ry0;
                 }
             }
-            const float A = I0 * expneg((z * z) * cs);
-            s.Af = A * 16777216.0f;
-            s.kap = 8.0f / (d * d);
-            s.x = x;
-            s.y = y;
-            sp_[threadIdx.x] = s;
-            atomicAdd(&s_asum, (unsigned long long)quant24(s.Af));
+            stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (r.z * r.z), r.w);
+            box[threadIdx.x] = pack_box(c0, w, r0, h);
+            if (w > 0) atomicAdd(&s_asum, (unsigned long long)(uint32_t)r.w);
+        }
+        // work items: one per patch line j < max(w, h); item j carries the j-th
+        // column factor (if j < w) and the j-th row factor (if j < h)
+        const int m = w > h ? w : h;
+        int em, dummy, tm_, tdummy;
+        scan2(m, 0, s_wave, em, dummy, tm_, tdummy);
+        const uint16_t tag = (uint16_t)(threadIdx.x << 8);
+        for (int j = 0; j < m; ++j) items[em + j] = tag | (uint16_t)j;
+        __syncthreads();
+        // separable factors: gx per patch column, rs = Af * gy per patch row
+        // (every argument lies in [0, 18.1]: no range check needed)
+        for (int i = threadIdx.x; i < tm_; i += 256) {
+            const int it = items[i];
+            const int k = it >> 8, j = it & 255;
+            const float4 sf = stg[k];
+            const uint32_t bx = box[k];
+            if (j < (int)((bx >> 8) & 255u)) {
+                const float dx = ((float)(rx0 + (int)(bx & 255u) + j) + 0.5f) - sf.x;
+                gx[k * WM + j] = expneg_lt80(sf.z * (dx * dx));
+            }
+            if (j < (int)(bx >> 24)) {
+                const float dy = ((float)(ry0 + (int)((bx >> 16) & 255u) + j) + 0.5f) - sf.y;
+                rs[k * WM + j] = sf.w * expneg_lt80(sf.z * (dy * dy));
+            }
         }
         __syncthreads();
-        // separable factors: column factors gx and row factors rs = Af * gy
-        for (int it = threadIdx.x; it < n * WM; it += blockDim.x) {
-            const int k = it / WM;
-            const int j = it - k * WM;
-            const StagedParticle s = sp_[k];
-            if (j < s.w) {
-                const float dx = ((float)(rx0 + s.c0 + j) + 0.5f) - s.x;
-                gx[it] = expneg(s.kap * (dx * dx));
+        // splat: one patch row per work item, eight columns per step; lanes past
+        // the patch edge add zero (the accumulator has slack for the overrun)
+        for (int i = threadIdx.x; i < tm_; i += 256) {
+            const int it = items[i];
+            const int k = it >> 8, j = it & 255;
+            const uint32_t bx = box[k];
+            if (j >= (int)(bx >> 24)) continue;
+            const int pc0 = (int)(bx & 255u), pw = (int)((bx >> 8) & 255u), pr0 = (int)((bx >> 16) & 255u);
+            const float rv = rs[k * WM + j];
+            const float* gk = gx + k * WM;
+            uint32_t* dst = acc + (pr0 + j) * RW + pc0;
+            for (int cs0 = 0; cs0 < pw; cs0 += 8) {
+                const int cw = pw - cs0;
+                const float4 g0 = *reinterpret_cast<const float4*>(gk + cs0);
+                atomicAdd(dst + cs0 + 0, (uint32_t)(rv * g0.x));
+                atomicAdd(dst + cs0 + 1, cw > 1 ? (uint32_t)(rv * g0.y) : 0u);
+                atomicAdd(dst + cs0 + 2, cw > 2 ? (uint32_t)(rv * g0.z) : 0u);
+                atomicAdd(dst + cs0 + 3, cw > 3 ? (uint32_t)(rv * g0.w) : 0u);
+                if (cw > 4) {
+                    const float4 g1 = *reinterpret_cast<const float4*>(gk + cs0 + 4);
+                    atomicAdd(dst + cs0 + 4, (uint32_t)(rv * g1.x));
+                    atomicAdd(dst + cs0 + 5, cw > 5 ? (uint32_t)(rv * g1.y) : 0u);
+                    atomicAdd(dst + cs0 + 6, cw > 6 ? (uint32_t)(rv * g1.z) : 0u);
+                    atomicAdd(dst + cs0 + 7, cw > 7 ? (uint32_t)(rv * g1.w) : 0u);
+                }
             }
-            if (j < s.h) {
-                const float dy = ((float)(ry0 + s.r0 + j) + 0.5f) - s.y;
-                rs[it] = s.Af * expneg(s.kap * (dy * dy));
-            }
-        }
-        __syncthreads();
-        // splat one patch row per work item
-        for (int it = threadIdx.x; it < n * WM; it += blockDim.x) {
-            const int k = it / WM;
-            const int j = it - k * WM;
-            const StagedParticle s = sp_[k];
-            if (j >= s.h) continue;
-            const float rv = rs[it];
-            const float* gxk = gx + k * WM;
-            uint32_t* dst = acc + (s.r0 + j) * RW + s.c0;
-            for (int c = 0; c < s.w; ++c) atomicAdd(dst + c, quant24(rv * gxk[c]));
         }
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_asum >= 4294967296ull) atomicOr(status, SP_STATUS_FIXED_RANGE);
 
-    // fixed point -> float, in place
-    float* v = reinterpret_cast<float*>(acc);
-    for (int k = threadIdx.x; k < RH * RW; k += blockDim.x) v[k] = (float)acc[k] * 0x1p-24f;
-    __syncthreads();
-
-    const int TW = cfg.tile_w;
-    if (b > 0) {
-        // horizontal pass over all region rows, tile columns
-        for (int k = threadIdx.x; k < RH * TW; k += blockDim.x) {
-            const int r = k / TW;
-            const int c = k - r * TW;
-            const float* src = v + r * RW + c;
-            float s = 0.0f;
-            for (int q = 0; q <= 2 * b; ++q) s = __builtin_fmaf(a.blur_w[q], src[q], s);
-            tmp[k] = s;
+    // fixed point -> float happens as the blur / store passes read the accumulator
+    constexpr float FIX = 0x1p-24f;
+    if constexpr (B > 0) {
+        // horizontal pass over all region rows: four tile columns per work item
+        for (int k = threadIdx.x; k < RH * Q4; k += 256) {
+            const int r = k / Q4;
+            const int c = (k % Q4) * 4;
+            const uint32_t* src = acc + r * RW + c;
+            float vv[4 + 2 * B];
+#pragma unroll
+            for (int q = 0; q < 4 + 2 * B; ++q) vv[q] = (float)src[q] * FIX;
+            float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
+#pragma unroll
+            for (int q = 0; q <= 2 * B; ++q) {
+                const float wq = wb[q];
+                o0 = __builtin_fmaf(wq, vv[q], o0);
+                o1 = __builtin_fmaf(wq, vv[q + 1], o1);
+                o2 = __builtin_fmaf(wq, vv[q + 2], o2);
+                o3 = __builtin_fmaf(wq, vv[q + 3], o3);
+            }
+            *reinterpret_cast<float4*>(tmp + r * TW + c) = make_float4(o0, o1, o2, o3);
         }
         __syncthreads();
     }
 
-    // vertical pass, noise, quantise, store; 4 consecutive pixels per work item
-    const int groups = cfg.tile_h * (TW >> 2);
-    const int64_t plane = (int64_t)P.H * P.W;
-    const int Wq = (P.W + 3) >> 2;
-    for (int gi = threadIdx.x; gi < groups; gi += blockDim.x) {
-        const int r = gi / (TW >> 2);
-        const int c4 = (gi - r * (TW >> 2)) << 2;
-        const int R = ty * cfg.tile_h + r;
+    // vertical pass, noise, codes, store: four consecutive pixels per work item
+    const int64_t plane = (int64_t)pH * pW;
+    const int Wq = (pW + 3) >> 2;
+    const float Lq = a.bits > 0 ? (float)((1u << a.bits) - 1u) : 0.0f;
+#pragma unroll 1
+    for (int gi = threadIdx.x; gi < TH * Q4; gi += 256) {
+        const int r = gi / Q4;
+        const int c4 = (gi % Q4) * 4;
+        const int R = ty * TH + r;
         const int C = tx * TW + c4;
-        if (R >= P.H || C >= P.W) continue;
+        if (R >= pH || C >= pW) continue;
         float o[4];
-        for (int e = 0; e < 4; ++e) {
-            const int c = c4 + e;
-            if (b > 0) {
-                const float* src = tmp + r * TW + c;
-                float s = 0.0f;
-                for (int q = 0; q <= 2 * b; ++q) s = __builtin_fmaf(a.blur_w[q], src[q * TW], s);
-                o[e] = s;
-            } else {
-                o[e] = v[r * RW + c];
+        if constexpr (B > 0) {
+            float4 s4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int q = 0; q <= 2 * B; ++q) {
+                const float wq = wb[q];
+                const float4 t4 = *reinterpret_cast<const float4*>(tmp + (r + q) * TW + c4);
+                s4.x = __builtin_fmaf(wq, t4.x, s4.x);
+                s4.y = __builtin_fmaf(wq, t4.y, s4.y);
+                s4.z = __builtin_fmaf(wq, t4.z, s4.z);
+                s4.w = __builtin_fmaf(wq, t4.w, s4.w);
             }
+            o[0] = s4.x; o[1] = s4.y; o[2] = s4.z; o[3] = s4.w;
+        } else {
+            const uint32_t* src = acc + r * RW + c4;
+            o[0] = (float)src[0] * FIX; o[1] = (float)src[1] * FIX;
+            o[2] = (float)src[2] * FIX; o[3] = (float)src[3] * FIX;
         }
         if (a.noise_sigma > 0.0f) {
-            const u32x4 w = draw((uint32_t)(R * Wq + (C >> 2)), STREAM_NOISE0 + f, P.pair_id, a.seed);
+            const u32x4 w = draw((uint32_t)(R * Wq + (C >> 2)), STREAM_NOISE0 + f, pid, a.seed);
             const uint32_t wa[2] = {w.a, w.c};
             const uint32_t wb[2] = {w.b, w.d};
+#pragma unroll
             for (int h2 = 0; h2 < 2; ++h2) {
                 const float u1 = u24_open0(wa[h2]);
                 const float u2 = u24(wb[h2]);
-                // v_log_f32 is log2; v_sin/v_cos take revolutions
+                // v_log_f32 is log2 (so -2 ln u = -2 ln2 log2 u); v_sin/v_cos take revolutions
                 const float rad = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1));
                 o[2 * h2] = __builtin_fmaf(a.noise_sigma, rad * __builtin_amdgcn_cosf(u2), o[2 * h2]);
                 o[2 * h2 + 1] = __builtin_fmaf(a.noise_sigma, rad * __builtin_amdgcn_sinf(u2), o[2 * h2 + 1]);
             }
         }
-        const int64_t pix = P.image_offset + (int64_t)f * plane + (int64_t)R * P.W + C;
-        const int ne = min(4, P.W - C);
+        const int64_t pix = p_img + (int64_t)f * plane + (int64_t)R * pW + C;
+        const int ne = min(4, pW - C);
         if (a.bits > 0) {
-            const float Lq = (float)((1u << a.bits) - 1u);
-            uint16_t* dst = reinterpret_cast<uint16_t*>(a.images) + pix;
-            for (int e = 0; e < ne; ++e) {
+            uint32_t qv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
                 float t = __builtin_rintf(o[e] * Lq);
                 t = __builtin_fmaxf(t, 0.0f);
                 t = __builtin_fminf(t, Lq);
-                dst[e] = (uint16_t)t;
+                qv[e] = (uint32_t)t;
+            }
+            uint16_t* dst = reinterpret_cast<uint16_t*>(a.images) + pix;
+            if (ne == 4 && ((uintptr_t)dst & 7) == 0) {
+                *reinterpret_cast<uint2*>(dst) = make_uint2(qv[0] | (qv[1] << 16), qv[2] | (qv[3] << 16));
+            } else {
+                for (int e = 0; e < ne; ++e) dst[e] = (uint16_t)qv[e];
             }
         } else {
             float* dst = reinterpret_cast<float*>(a.images) + pix;
-            for (int e = 0; e < ne; ++e) dst[e] = o[e];
+            if (ne == 4 && ((uintptr_t)dst & 15) == 0) {
+                *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+                for (int e = 0; e < ne; ++e) dst[e] = o[e];
+            }
         }
+    }
+}
+
+size_t render_lds_bytes(const RenderConfig& cfg) { return render_lds(cfg).bytes; }
+
+// Tile shapes with a compiled renderer (width x height).
+bool render_shape_supported(int tw, int th)
+{
+    switch (tw * 1000 + th) {
+    case 8008: case 16016: case 32016: case 32032: case 64016: case 64032: case 64064: case 128032:
+        return true;
+    default:
+        return false;
     }
 }
 
 // ------------------------------------------------------------------ launcher
 
-size_t render_lds_bytes(const RenderConfig& cfg)
+template <int TW, int TH>
+static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const RenderArgs& a, const RenderConfig& cfg,
+                                const PairLayout* L, const float4* r0, const float4* r1, const uint32_t* tile_count,
+                                const int64_t* tile_offset, const int32_t* entries, int64_t tiles,
+                                uint32_t* status)
 {
-    const int RW = cfg.tile_w + 2 * cfg.apron;
-    const int RH = cfg.tile_h + 2 * cfg.apron;
-    size_t tables = (size_t)cfg.cap * sizeof(StagedParticle) + 2 * (size_t)cfg.cap * cfg.wmax * sizeof(float);
-    size_t blur = (size_t)RH * cfg.tile_w * sizeof(float);
-    return (size_t)RH * RW * sizeof(uint32_t) + (tables > blur ? tables : blur);
+    EpilogueArgs ea;
+    ea.images = a.images;
+    ea.noise_sigma = a.noise_sigma;
+    ea.bits = a.bits;
+    ea.seed = a.seed;
+    for (int q = 0; q < 7; ++q) ea.blur_w[q] = a.blur_w[q];
+#define SP_B(B_)                                                                                                 \
+    case B_:                                                                                                     \
+        hipLaunchKernelGGL((render_tile<TW, TH, B_>), grid, dim3(256), lds, s, a.pairs, L, a.n_pairs, r0, r1,    \
+                           ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles, status);              \
+        break;
+    switch (cfg.apron) { SP_B(0) SP_B(1) SP_B(2) SP_B(3) default: break; }
+#undef SP_B
 }
 
 hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot, char* ws,
@@ -416,16 +579,23 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
     int64_t* tile_offset = reinterpret_cast<int64_t*>(ws + wl.tile_offset);
     uint32_t* hist = reinterpret_cast<uint32_t*>(ws + wl.hist);
     int32_t* entries = reinterpret_cast<int32_t*>(ws + wl.entries);
+    float4* rec0 = reinterpret_cast<float4*>(ws + wl.records);
+    float4* rec1 = rec0 + tot.n_span;
 
     {
         TimedScope ts("bin_layout", s);
         hipLaunchKernelGGL(bin_layout, dim3(1), dim3(256), 0, s, a.pairs, a.n_pairs, cfg, L, status);
     }
+    if (tot.n_span > 0) {
+        TimedScope ts("prep", s);
+        hipLaunchKernelGGL(prep_records, dim3((unsigned)((tot.n_span + 255) / 256)), dim3(256), 0, s, a.pairs,
+                           a.n_pairs, tot.n_span, a, cfg.d_max, rec0, rec1, status);
+    }
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
     if (tot.chunks > 0) {
         TimedScope ts("bin_count", s);
         hipLaunchKernelGGL(bin_pass<false>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s,
-                           a.pairs, L, a.n_pairs, a, cfg, hist, entries, status);
+                           a.pairs, L, a.n_pairs, rec0, rec1, cfg, hist, entries, (unsigned)tot.chunks);
     }
     {
         TimedScope ts("bin_scan", s);
@@ -435,12 +605,21 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
     if (tot.chunks > 0) {
         TimedScope ts("bin_scatter", s);
         hipLaunchKernelGGL(bin_pass<true>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s,
-                           a.pairs, L, a.n_pairs, a, cfg, hist, entries, status);
+                           a.pairs, L, a.n_pairs, rec0, rec1, cfg, hist, entries, (unsigned)tot.chunks);
     }
     if (tot.tiles > 0) {
         TimedScope ts("render_tile", s);
-        hipLaunchKernelGGL(render_tile, dim3((unsigned)(2 * tot.tiles)), dim3(256), render_lds_bytes(cfg), s,
-                           a.pairs, L, a.n_pairs, a, cfg, tile_count, tile_offset, entries, tot.tiles, status);
+        const size_t lds = render_lds_bytes(cfg);
+        const dim3 grid((unsigned)(2 * tot.tiles));
+#define SP_SHAPE(W_, H_)                                                                                        \
+    if (cfg.tile_w == W_ && cfg.tile_h == H_)                                                                   \
+        launch_render_shape<W_, H_>(grid, lds, s, a, cfg, L, rec0, rec1, tile_count, tile_offset, entries,      \
+                                    tot.tiles, status);                                                         \
+    else
+        SP_SHAPE(8, 8) SP_SHAPE(16, 16) SP_SHAPE(32, 16) SP_SHAPE(32, 32) SP_SHAPE(64, 16) SP_SHAPE(64, 32)
+        SP_SHAPE(64, 64) SP_SHAPE(128, 32)
+        return hipErrorInvalidValue;
+#undef SP_SHAPE
     }
     return hipGetLastError();
 }

@@ -19,16 +19,29 @@ namespace sp {
 
 struct u32x4 { uint32_t a, b, c, d; };
 
+// a ^ b ^ k in one VALU instruction (gfx950's v_bitop3_b32, truth table 0x96:
+// set for an odd number of set inputs), k a wave-uniform key word in an SGPR.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+// The key must be wave-uniform (it is the generator seed everywhere).  The
+// empty asm keeps the ten round keys from being hoisted out of callers' loops
+// as twenty live scalar registers: each round's key is one scalar add.
 __device__ __forceinline__ u32x4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1)
 {
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -56,9 +69,9 @@ constexpr float LN2_HI = (float)(45426.0 / 65536.0);
 constexpr float LN2_LO = (float)(0.69314718055994530942 - 45426.0 / 65536.0);
 constexpr float LOG2E_F = (float)1.44269504088896340736;
 
-__device__ __forceinline__ float expneg(float q)
+// exp(-q) for 0 <= q < 80 (no range check): the polynomial times the exact power 2^-k.
+__device__ __forceinline__ float expneg_lt80(float q)
 {
-    if (!(q < 80.0f)) return 0.0f;
     const float kf = __builtin_rintf(q * LOG2E_F);
     float r = __builtin_fmaf(kf, -LN2_HI, q);
     r = __builtin_fmaf(kf, -LN2_LO, r);
@@ -70,8 +83,13 @@ __device__ __forceinline__ float expneg(float q)
     p = __builtin_fmaf(p, r, 0.5f);
     p = __builtin_fmaf(p, r, -1.0f);
     p = __builtin_fmaf(p, r, 1.0f);
-    const int k = (int)kf;
-    return p * __uint_as_float((uint32_t)(127 - k) << 23);
+    return __builtin_amdgcn_ldexpf(p, -(int)kf);
+}
+
+__device__ __forceinline__ float expneg(float q)
+{
+    if (!(q < 80.0f)) return 0.0f;
+    return expneg_lt80(q);
 }
 
 // ln(u), u a positive normal float: exponent split, mantissa in [sqrt(1/2), sqrt(2)),
@@ -133,13 +151,20 @@ __device__ __forceinline__ bool in_support(int k, float p, float R)
 __device__ __forceinline__ bool support_range(float p, float R, int n, int& lo, int& hi)
 {
     if (!(R > 0.0f) || !__builtin_isfinite(p)) return false;
-    const float a = __builtin_floorf(p - R) - 2.0f;
-    const float b = __builtin_ceilf(p + R) + 2.0f;
-    if (b < 0.0f || a > (float)(n - 1)) return false;
-    int k0 = a < 0.0f ? 0 : (int)a;
-    int k1 = b > (float)(n - 1) ? n - 1 : (int)b;
-    // The float estimate is within a couple of pixels: at most a few iterations.
+    const float a = p - R, b = p + R;
+    if (b < -1.0f || a > (float)n + 1.0f) {
+        // far outside the image: nothing in [0, n); still exact since |dx| > R for every k
+        return false;
+    }
+    // estimates of the first and last pixel with |(k + 1/2) - p| <= R, then exact
+    // correction by re-testing the binary32 predicate (monotone in k)
+    int k0 = (int)__builtin_ceilf(a - 0.5f);
+    int k1 = (int)__builtin_floorf(b - 0.5f);
+    k0 = k0 < 0 ? 0 : k0;
+    k1 = k1 > n - 1 ? n - 1 : k1;
+    while (k0 > 0 && in_support(k0 - 1, p, R)) --k0;
     while (k0 <= k1 && !in_support(k0, p, R)) ++k0;
+    while (k1 < n - 1 && in_support(k1 + 1, p, R)) ++k1;
     while (k1 >= k0 && !in_support(k1, p, R)) --k1;
     if (k0 > k1) return false;
     lo = k0;
@@ -147,17 +172,23 @@ __device__ __forceinline__ bool support_range(float p, float R, int n, int& lo, 
     return true;
 }
 
-__device__ __forceinline__ uint32_t quant24(float t)
-{
-    // t already carries the 2^24 scale; truncate, saturate, NaN -> 0.
-    if (!(t > 0.0f)) return 0u;
-    if (t >= 4294967296.0f) return 0xffffffffu;
-    return (uint32_t)t;
-}
+// Fixed-point scale of a particle's peak: 2^24 A, capped at 2^32 - 256 so that
+// every product (Af gy) gx with gx, gy in [0, 1] truncates into a uint32.
+__device__ __forceinline__ float fixed_peak(float A) { return __builtin_fminf(A * 16777216.0f, 4294967040.0f); }
 
 __device__ __forceinline__ bool particle_valid(float x, float y, float d, float I0)
 {
     return (I0 > 0.0f) && (d > 0.0f) && __builtin_isfinite(x) && __builtin_isfinite(y);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; renumber them so that each
+// XCD works on one contiguous range of the logical index space (neighbouring
+// work shares data, and each XCD has its own L2).
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned b, unsigned n)
+{
+    const unsigned xcd = b & 7u, slot = b >> 3;
+    const unsigned q = n >> 3, rem = n & 7u;
+    return xcd < rem ? xcd * (q + 1) + slot : rem * (q + 1) + (xcd - rem) * q + slot;
 }
 
 // Pair lookup: the pair whose particle range [offset, offset + n_max) holds g.

@@ -38,8 +38,10 @@ struct PairLayout {
 
 struct RenderConfig {
     int tile_w, tile_h, chunk, cap;
+    int log_tw, log_th;     // tile sizes are powers of two
     int apron;              // blur radius b
     int wmax;               // largest per-particle patch side the LDS tables hold
+    int wm4;                // wmax rounded up to a multiple of 4 (row stride of the tables)
     int kx, ky;             // bound on tiles touched per particle per axis
     float d_max;
 };
@@ -62,6 +64,7 @@ struct WorkspaceLayout {
     size_t tile_offset;     // int64  [2 * tiles]
     size_t hist;            // uint32 [hist]
     size_t entries;         // int32  [entries]
+    size_t records;         // float4 [2 * n_span] per-frame particle records
     size_t grad_img;        // float  (backward only) dL/dI images
     size_t x2;              // float  (backward only) recomputed frame-2 positions
     size_t y2;
@@ -93,9 +96,22 @@ struct RenderArgs {
     float blur_w[7];
 };
 
+// What the tile renderer's epilogue needs (kept small: kernel arguments live in SGPRs).
+struct EpilogueArgs {
+    void* images;
+    uint64_t seed;
+    float noise_sigma;
+    int bits;
+    float blur_w[7];
+};
+
 size_t render_lds_bytes(const RenderConfig& cfg);
+bool render_shape_supported(int tile_w, int tile_h);
 
 hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot,
                          char* ws, const WorkspaceLayout& wl, hipStream_t s);
+
+// Compute units of the current device (cached per device).
+int device_cu_count();
 
 }  // namespace sp

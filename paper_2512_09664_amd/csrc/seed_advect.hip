@@ -148,22 +148,88 @@ __device__ __forceinline__ float2 integrate(const FlowView& fv, float px, float 
     return make_float2(px, py);
 }
 
+// N particles per thread, integrated in lockstep: each substep's bilinear
+// samples are chains of dependent L2 reads, so independent particles in one
+// thread overlap those latencies.
+template <int N>
+__device__ __forceinline__ void integrate_n(const FlowView* fv, float* px, float* py, float dt, int substeps,
+                                            int integrator)
+{
+    const float h = dt / (float)substeps;
+    const float hh = h * 0.5f;
+    for (int s = 0; s < substeps; ++s) {
+        if (integrator == SP_EULER) {
+            float2 u[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) u[q] = sample_flow(fv[q], px[q], py[q]);
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                px[q] = __builtin_fmaf(h, u[q].x, px[q]);
+                py[q] = __builtin_fmaf(h, u[q].y, py[q]);
+            }
+        } else {
+            float2 k1[N], k2[N], k3[N], k4[N];
+#pragma unroll
+            for (int q = 0; q < N; ++q) k1[q] = sample_flow(fv[q], px[q], py[q]);
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                k2[q] = sample_flow(fv[q], __builtin_fmaf(hh, k1[q].x, px[q]), __builtin_fmaf(hh, k1[q].y, py[q]));
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                k3[q] = sample_flow(fv[q], __builtin_fmaf(hh, k2[q].x, px[q]), __builtin_fmaf(hh, k2[q].y, py[q]));
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                k4[q] = sample_flow(fv[q], __builtin_fmaf(h, k3[q].x, px[q]), __builtin_fmaf(h, k3[q].y, py[q]));
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                const float su = ((k1[q].x + 2.0f * k2[q].x) + 2.0f * k3[q].x) + k4[q].x;
+                const float sv = ((k1[q].y + 2.0f * k2[q].y) + 2.0f * k3[q].y) + k4[q].y;
+                px[q] = __builtin_fmaf(h, su / 6.0f, px[q]);
+                py[q] = __builtin_fmaf(h, sv / 6.0f, py[q]);
+            }
+        }
+    }
+}
+
+constexpr int ADVECT_ILP = 2;
+
 __global__ void __launch_bounds__(256)
 advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span,
               const float* __restrict__ flow, synthpix_advect_params ap,
               const float* __restrict__ x1, const float* __restrict__ y1,
               float* __restrict__ x2, float* __restrict__ y2)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_span) return;
-    const int p = find_pair_by_particle(pairs, n_pairs, g);
-    const synthpix_pair P = pairs[p];
-    const int64_t i = g - P.particle_offset;
-    if (i < 0 || i >= P.n_max) return;
-    const FlowView fv = flow_view(P, flow);
-    const float2 r = integrate(fv, x1[g], y1[g], ap.dt, ap.substeps, ap.integrator);
-    x2[g] = r.x;
-    y2[g] = r.y;
+    // consecutive particle blocks (same pair, same flow grid) stay on one XCD
+    const int64_t base = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * (256 * ADVECT_ILP) + threadIdx.x;
+    FlowView fv[ADVECT_ILP];
+    float px[ADVECT_ILP], py[ADVECT_ILP];
+    bool live[ADVECT_ILP];
+#pragma unroll
+    for (int q = 0; q < ADVECT_ILP; ++q) {
+        const int64_t g = base + 256 * q;
+        live[q] = false;
+        px[q] = py[q] = 0.0f;
+        fv[q] = FlowView{reinterpret_cast<const float2*>(flow), 2, 2, 1.0f, 1.0f};
+        if (g < n_span) {
+            const int p = find_pair_by_particle(pairs, n_pairs, g);
+            const synthpix_pair P = pairs[p];
+            const int64_t i = g - P.particle_offset;
+            if (i >= 0 && i < P.n_max) {
+                live[q] = true;
+                fv[q] = flow_view(P, flow);
+                px[q] = x1[g];
+                py[q] = y1[g];
+            }
+        }
+    }
+    integrate_n<ADVECT_ILP>(fv, px, py, ap.dt, ap.substeps, ap.integrator);
+#pragma unroll
+    for (int q = 0; q < ADVECT_ILP; ++q) {
+        if (live[q]) {
+            x2[base + 256 * q] = px[q];
+            y2[base + 256 * q] = py[q];
+        }
+    }
 }
 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
@@ -187,7 +253,7 @@ hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_
                          float* y2, hipStream_t s)
 {
     if (n_span <= 0) return hipSuccess;
-    const int64_t blocks = (n_span + 255) / 256;
+    const int64_t blocks = (n_span + 256 * ADVECT_ILP - 1) / (256 * ADVECT_ILP);
     TimedScope ts("advect", s);
     hipLaunchKernelGGL(advect_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
                        flow, ap, x1, y1, x2, y2);

@@ -82,7 +82,7 @@ def test_workspace_size_and_validation(L):
     for kw in bad:
         assert lib.synthpix_workspace_size(pairs, 2, ctypes.byref(_rp(L, **kw)), None, 0,
                                            ctypes.byref(n)) == L.SP_ERR_INVALID_ARG, kw
-    t = L.Tiling(6, 32, 4096, 128)
+    t = L.Tiling(24, 32, 4096, 128)
     assert lib.synthpix_workspace_size(pairs, 2, ctypes.byref(_rp(L)), ctypes.byref(t), 0,
                                        ctypes.byref(n)) == L.SP_ERR_INVALID_ARG
     big = _pairs(L, [(16384, 16384, 64, 64, 10)])

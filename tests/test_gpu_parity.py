@@ -124,7 +124,7 @@ def _render_gpu(b, arrs, rp, tile=None, workspace=None):
     return gu.to_np(img)
 
 
-TILINGS = [None, (8, 8, 256, 32), (64, 32, 256, 64), (128, 32, 16384, 128), (16, 24, 512, 96)]
+TILINGS = [None, (8, 8, 256, 32), (64, 32, 256, 64), (128, 32, 16384, 128), (32, 16, 512, 96)]
 
 
 @pytest.mark.parametrize("tile", TILINGS)
@@ -175,7 +175,7 @@ def test_tiling_and_batching_do_not_change_bits():
         o += 2 * H * W
 
 
-@pytest.mark.parametrize("tile", [None, (8, 16, 256, 32)])
+@pytest.mark.parametrize("tile", [None, (16, 16, 256, 32)])
 def test_bins_match_oracle(tile):
     sizes = [(64, 96), (37, 53)]
     arrs, n_max = _render_case(41, sizes, 300)
@@ -185,7 +185,8 @@ def test_bins_match_oracle(tile):
     ws = sp.alloc_workspace(b, rp, tl)
     _render_gpu(b, arrs, rp, tl, workspace=ws)
     count, offset, entries = (gu.to_np(t) for t in sp.bin_views(b, rp, tl, ws))
-    tw, th = (tile[0], tile[1]) if tile else (32, 32)
+    dt_ = sp.default_tiling(b, rp)
+    tw, th = (tile[0], tile[1]) if tile else (dt_.tile_w, dt_.tile_h)
     tbase = 0
     po = 0
     for p, (H, W) in enumerate(sizes):

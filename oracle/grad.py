@@ -44,26 +44,36 @@ def forward_pair(x1, y1, z, d, I0, s, flow, H, W, dt=1.0, substeps=1, integrator
 
 def _particle_sums(x, y, d, A, e, cutoff):
     """Per particle: S0 = sum e G, Sx = sum e G dx, Sy = sum e G dy,
-    Sr = sum e G (dx^2 + dy^2) over its (cut-off) support, G unscaled."""
+    Sr = sum e G (dx^2 + dy^2) over its (cut-off) support, G unscaled.
+
+    With the cutoff, G vanishes outside the particle's square patch of half
+    side 1.5 d (Section 2, "Efficient rasterization"), so only the image
+    window around the patch is visited."""
     H, W = e.shape
     n = len(x)
     S = np.zeros((4, n))
-    cx = np.arange(W, dtype=np.float64) + 0.5
-    cy = np.arange(H, dtype=np.float64) + 0.5
     for i in range(n):
         if not (A[i] != 0 and d[i] > 0):
             continue
-        dx = cx - x[i]
-        dy = cy - y[i]
+        c_lo, c_hi, r_lo, r_hi = 0, W, 0, H
+        if cutoff:
+            R = 1.5 * d[i]
+            c_lo = max(int(np.floor(x[i] - R - 0.5)), 0)
+            c_hi = min(int(np.ceil(x[i] + R - 0.5)) + 1, W)
+            r_lo = max(int(np.floor(y[i] - R - 0.5)), 0)
+            r_hi = min(int(np.ceil(y[i] + R - 0.5)) + 1, H)
+            if c_lo >= c_hi or r_lo >= r_hi:
+                continue
+        dx = np.arange(c_lo, c_hi, dtype=np.float64) + 0.5 - x[i]
+        dy = np.arange(r_lo, r_hi, dtype=np.float64) + 0.5 - y[i]
         kap = 8.0 / (d[i] * d[i])
         gx = np.exp(-kap * dx * dx)
         gy = np.exp(-kap * dy * dy)
         if cutoff:
-            R = 1.5 * d[i]
             gx = gx * (np.abs(dx) <= R)
             gy = gy * (np.abs(dy) <= R)
         G = np.outer(gy, gx)
-        eG = e * G
+        eG = e[r_lo:r_hi, c_lo:c_hi] * G
         S[0, i] = eG.sum()
         S[1, i] = (eG * dx[None, :]).sum()
         S[2, i] = (eG * dy[:, None]).sum()

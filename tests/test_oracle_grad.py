@@ -145,3 +145,22 @@ def test_masked_particles_get_zero_gradient():
     g = gr.backward_pair(x, y, np.zeros(2), np.array([2.0, 2.0]), np.array([0.0, 1.0]), 0.5,
                          np.zeros((4, 4, 2)), 16, 16, np.ones((2, 16, 16)))
     assert g["x1"][0] == 0 and g["d"][0] == 0 and g["I0"][0] == 0 and g["I0"][1] > 0
+
+
+@pytest.mark.parametrize("integ,n_sub", [("euler", 1), ("rk4", 4)])
+def test_cutoff_gradient_matches_smooth_gradient(integ, n_sub):
+    """The patch cutoff at |dx|, |dy| <= 1.5 d drops terms of at most exp(-18)
+    of the peak, so the windowed (cut-off) gradient equals the full-support one
+    to ~1e-7 of its scale; this also pins the windowed sums to the FD-checked
+    full ones."""
+    x, y, z, d, I0, s, flow, T = _case(5 + n_sub, integ, n_sub)
+    kw = dict(dt=1.0, substeps=n_sub, integrator=integ, w_blur=ep.blur_weights(1, 0.7))
+    J = gr.forward_pair(x, y, z, d, I0, s, flow, H, W, cutoff=False, **kw)
+    gJ = 2 * (J - T) / J.size
+    g_full = gr.backward_pair(x, y, z, d, I0, s, flow, H, W, gJ, cutoff=False, **kw)
+    g_cut = gr.backward_pair(x, y, z, d, I0, s, flow, H, W, gJ, cutoff=True, **kw)
+    for key in ("x1", "y1", "z", "d", "I0", "flow"):
+        scale = np.max(np.abs(g_full[key]))
+        assert scale > 0
+        assert np.max(np.abs(g_cut[key] - g_full[key])) <= 1e-6 * scale, key
+    assert abs(g_cut["s"] - g_full["s"]) <= 1e-6 * abs(g_full["s"])

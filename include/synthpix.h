@@ -239,6 +239,46 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host,
                                               float* g_I0, float* g_sheet, float* g_flow,
                                               void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------- batched, captured form */
+
+/* Device buffers of one batch, used by every launch of a plan. */
+typedef struct {
+    const float* flow;          /* every pair's flow grid at pair.flow_offset               */
+    float *x1, *y1, *x2, *y2;   /* particle positions of frame 1 and frame 2                */
+    float *z, *d, *I0;          /* per-particle out-of-plane position, diameter, intensity  */
+    void* images;               /* [pair][frame][H][W], float or uint16 per rp->bits        */
+    int32_t* n_active;          /* optional per-pair outputs of the seed step (may be NULL) */
+    double* ppp;
+} synthpix_batch_io;
+
+typedef struct synthpix_plan synthpix_plan;
+
+/* Build a plan for a fixed batch signature (pair table, parameters, buffers):
+ * copies the pair table to plan-owned device memory, sizes and allocates the
+ * render workspace, and, if `autotune` != 0, times every compiled tiling
+ * candidate (tile shape x LDS particle capacity) on this batch on `stream`
+ * and keeps the fastest (all candidates give bit-identical images).  The
+ * whole path -- seed, advect, bin, render, epilogue -- is then captured once
+ * into a hipGraph.  This call allocates device memory and synchronises
+ * `stream`; it is the set-up call, not the hot path.
+ * advance_pair_ids != 0: every launch moves the plan's pair ids on by n_pairs
+ * after rendering, so launch k draws the pairs with ids pair_id + k * n_pairs. */
+synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_pairs,
+                                     const synthpix_seed_params* sp, uint64_t seed,
+                                     const synthpix_advect_params* ap, const synthpix_render_params* rp,
+                                     const synthpix_batch_io* io, int32_t autotune, int32_t advance_pair_ids,
+                                     void* stream, synthpix_plan** out);
+
+/* Replay the captured graph on `stream` (asynchronous; no host work beyond the
+ * graph launch, no allocation). */
+synthpix_status synthpix_plan_launch(synthpix_plan* plan, void* stream);
+
+/* The tiling the plan runs with (after autotuning). */
+synthpix_status synthpix_plan_tiling(const synthpix_plan* plan, synthpix_tiling* out);
+
+/* Release the plan's graph, workspace and device pair table. */
+synthpix_status synthpix_plan_destroy(synthpix_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,13 @@ class BinViews(ctypes.Structure):
                 ("tiles", ctypes.c_int64)]
 
 
+class BatchIO(ctypes.Structure):
+    _fields_ = [("flow", ctypes.c_void_p), ("x1", ctypes.c_void_p), ("y1", ctypes.c_void_p),
+                ("x2", ctypes.c_void_p), ("y2", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("d", ctypes.c_void_p), ("I0", ctypes.c_void_p), ("images", ctypes.c_void_p),
+                ("n_active", ctypes.c_void_p), ("ppp", ctypes.c_void_p)]
+
+
 assert ctypes.sizeof(Pair) == 56
 
 _P = ctypes.c_void_p
@@ -96,6 +103,12 @@ SIGNATURES = {
     "synthpix_render_pair_backward": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P,
                                       ctypes.POINTER(RenderParams), _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P],
+    "synthpix_plan_create": [_PP, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.c_uint64,
+                             ctypes.POINTER(AdvectParams), ctypes.POINTER(RenderParams), ctypes.POINTER(BatchIO),
+                             ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)],
+    "synthpix_plan_launch": [_P, _P],
+    "synthpix_plan_tiling": [_P, ctypes.POINTER(Tiling)],
+    "synthpix_plan_destroy": [_P],
 }
 _RESTYPES = {"synthpix_version": ctypes.c_int32, "synthpix_last_error": ctypes.c_char_p}
 

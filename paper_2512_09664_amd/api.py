@@ -250,3 +250,83 @@ def split_images(batch: PairBatch, images: torch.Tensor):
         out.append(images[o:o + 2 * H * W].view(2, H, W))
         o += 2 * H * W
     return out
+
+
+class Plan:
+    """A batch signature captured once (``synthpix_plan_create``) and replayed
+    as one HIP graph per call (``synthpix_plan_launch``).
+
+    ``io`` holds the device tensors every launch reads and writes: flow, x1,
+    y1, x2, y2, z, d, I0, images and optionally n_active, ppp.  The tensors
+    must stay alive (and unmoved) as long as the plan does.
+    """
+
+    def __init__(self, batch: PairBatch, sp, seed_value: int, ap, rp, io: dict, autotune: bool = False,
+                 advance_pair_ids: bool = False):
+        _need_cuda(*(io[k] for k in ("flow", "x1", "y1", "x2", "y2", "z", "d", "I0", "images")))
+        self.io = dict(io)
+        b = L.BatchIO()
+        for k in ("flow", "x1", "y1", "x2", "y2", "z", "d", "I0", "images", "n_active", "ppp"):
+            t = io.get(k)
+            setattr(b, k, t.data_ptr() if t is not None else None)
+        self._b = b
+        h = ctypes.c_void_p(None)
+        L.check(L.load().synthpix_plan_create(batch.host_ptr, batch.n_pairs, ctypes.byref(sp), int(seed_value),
+                                              ctypes.byref(ap), ctypes.byref(rp), ctypes.byref(b),
+                                              1 if autotune else 0, 1 if advance_pair_ids else 0, _stream(),
+                                              ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def tiling(self):
+        t = L.Tiling()
+        L.check(L.load().synthpix_plan_tiling(self._h, ctypes.byref(t)))
+        return t
+
+    def launch(self):
+        L.check(L.load().synthpix_plan_launch(self._h, _stream()))
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            L.load().synthpix_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _RenderImages(torch.autograd.Function):
+    """advect + render as one differentiable op: inputs flow, x1, y1, z, d, I0
+    and the sheet width; output the float images.  The backward recomputes
+    everything from the saved inputs (``synthpix_render_pair_backward``)."""
+
+    @staticmethod
+    def forward(ctx, flow, x1, y1, z, d, I0, sheet, batch, rp, tile):
+        if rp.bits != 0:
+            raise ValueError("differentiable rendering needs float images (bits = 0)")
+        rp2 = L.RenderParams.from_buffer_copy(rp)
+        rp2.sheet_sigma = float(sheet)
+        x2, y2 = advect(batch, flow, rp2.advect, x1, y1)
+        img = render_pair(batch, x1, y1, x2, y2, z, d, I0, rp2, tile)
+        ctx.save_for_backward(flow, x1, y1, z, d, I0, sheet)
+        ctx.batch, ctx.rp, ctx.tile = batch, rp2, tile
+        return img
+
+    @staticmethod
+    def backward(ctx, grad):
+        flow, x1, y1, z, d, I0, sheet = ctx.saved_tensors
+        g = render_pair_backward(ctx.batch, flow, x1, y1, z, d, I0, ctx.rp, grad.contiguous(), ctx.tile)
+        g_sheet = g["sheet"].sum().to(sheet.dtype).reshape(sheet.shape)
+        return g["flow"], g["x1"], g["y1"], g["z"], g["d"], g["I0"], g_sheet, None, None, None
+
+
+def render_images(batch: PairBatch, flow, x1, y1, z, d, I0, sheet, rp, tile=None):
+    """Differentiable float images of every pair (autograd through the HIP
+    backward).  ``sheet`` is a 0-d tensor holding the sheet width; ``rp``
+    supplies everything else (its advect member sets the integrator)."""
+    if not torch.is_tensor(sheet):
+        sheet = torch.tensor(float(sheet), dtype=torch.float32, device=x1.device)
+    return _RenderImages.apply(flow, x1, y1, z, d, I0, sheet, batch, rp, tile)

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "launch.hpp"
 #include "synthpix.h"
@@ -171,16 +172,79 @@ sp::WorkspaceLayout workspace_layout(int32_t n_pairs, const sp::BatchTotals& T, 
     w.hist = o; o = align256(o + sizeof(uint32_t) * (size_t)T.hist);
     w.entries = o; o = align256(o + sizeof(int32_t) * (size_t)T.entries);
     w.records = o; o = align256(o + 2 * 16 * (size_t)T.n_span);
-    if (backward) {
-        size_t px = 0;
-        for (int32_t p = 0; p < n_pairs; ++p) px += 2 * (size_t)ph[p].H * ph[p].W;
-        w.grad_img = o; o = align256(o + sizeof(float) * px);
-        w.x2 = o; o = align256(o + sizeof(float) * (size_t)T.n_span);
-        w.y2 = o; o = align256(o + sizeof(float) * (size_t)T.n_span);
-        w.gpart = o; o = align256(o + sizeof(float) * 8 * (size_t)T.n_span);
-    }
+    (void)backward;
+    (void)ph;
     w.total = o;
     return w;
+}
+
+// End of the furthest pair grid in the flow array (floats).
+int64_t flow_span(const synthpix_pair* ph, int32_t n_pairs)
+{
+    int64_t e = 0;
+    for (int32_t p = 0; p < n_pairs; ++p)
+        e = std::max<int64_t>(e, ph[p].flow_offset + 2 * (int64_t)ph[p].Gh * ph[p].Gw);
+    return e;
+}
+
+// Backward workspace: particle-major, no bins.
+struct BwdLayout {
+    size_t status, kmax, x2, y2, gx2, gy2, sheet, fixed, total;
+};
+
+BwdLayout bwd_layout(int64_t n_span, int64_t n_flow)
+{
+    BwdLayout w{};
+    size_t o = 0;
+    const size_t nf = sizeof(float) * (size_t)n_span;
+    w.status = o; o = align256(o + 16);
+    w.kmax = o; o = align256(o + 4);
+    w.x2 = o; o = align256(o + nf);
+    w.y2 = o; o = align256(o + nf);
+    w.gx2 = o; o = align256(o + nf);
+    w.gy2 = o; o = align256(o + nf);
+    w.sheet = o; o = align256(o + nf);
+    w.fixed = o; o = align256(o + sizeof(uint64_t) * (size_t)n_flow);
+    w.total = o;
+    return w;
+}
+
+// ceil(log2(samples)) for the fixed-point scale of the flow gradient.
+int sample_exponent(int64_t n_span, const synthpix_advect_params& ap)
+{
+    const double n = (double)std::max<int64_t>(n_span, 1) * ap.substeps * (ap.integrator == SP_RK4 ? 4 : 1);
+    int e = 0;
+    while (std::ldexp(1.0, e) < n) ++e;
+    return e;
+}
+
+synthpix_status check_advect_params(const synthpix_advect_params* ap)
+{
+    if (!ap) return fail(SP_ERR_INVALID_ARG, "advect params must be non-NULL");
+    if (!std::isfinite(ap->dt)) return fail(SP_ERR_INVALID_ARG, "dt must be finite");
+    if (ap->substeps < 1 || ap->substeps > 1024) return fail(SP_ERR_INVALID_ARG, "substeps must be in [1, 1024]");
+    if (ap->integrator != SP_EULER && ap->integrator != SP_RK4)
+        return fail(SP_ERR_INVALID_ARG, "unknown integrator %d", ap->integrator);
+    return SP_OK;
+}
+
+hipError_t enqueue_render(const synthpix_pair* pairs_dev, int32_t n_pairs, const sp::RenderConfig& cfg,
+                          const sp::BatchTotals& T, const sp::WorkspaceLayout& wl, const float* x1, const float* y1,
+                          const float* x2, const float* y2, const float* z, const float* d, const float* I0,
+                          const synthpix_render_params& rp, void* images, void* workspace, hipStream_t stream)
+{
+    sp::RenderArgs a{};
+    a.pairs = pairs_dev;
+    a.n_pairs = n_pairs;
+    a.x[0] = x1; a.y[0] = y1; a.x[1] = x2; a.y[1] = y2;
+    a.z = z; a.d = d; a.I0 = I0;
+    a.images = images;
+    a.sheet_sigma = rp.sheet_sigma;
+    a.noise_sigma = rp.noise_sigma;
+    a.bits = rp.bits;
+    a.seed = rp.seed;
+    blur_taps(rp.blur_radius, rp.blur_sigma, a.blur_w);
+    return sp::launch_render(a, cfg, T, static_cast<char*>(workspace), wl, stream);
 }
 
 synthpix_tiling default_tiling()
@@ -232,10 +296,14 @@ synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t
     if ((st = check_render_params(rp))) return st;
     const synthpix_tiling t = tiling ? *tiling : default_tiling();
     if ((st = check_tiling(t))) return st;
+    if (backward) {
+        *bytes_out = bwd_layout(span, flow_span(pairs_host, n_pairs)).total;
+        return SP_OK;
+    }
     const sp::RenderConfig cfg = make_config(*rp, t);
     sp::BatchTotals T;
     if ((st = batch_totals(pairs_host, n_pairs, cfg, &T))) return st;
-    *bytes_out = workspace_layout(n_pairs, T, backward ? 1 : 0, pairs_host).total;
+    *bytes_out = workspace_layout(n_pairs, T, 0, pairs_host).total;
     return SP_OK;
 }
 
@@ -329,11 +397,7 @@ synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_
     int64_t span;
     synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
     if (st) return st;
-    if (!ap) return fail(SP_ERR_INVALID_ARG, "advect params must be non-NULL");
-    if (!std::isfinite(ap->dt)) return fail(SP_ERR_INVALID_ARG, "dt must be finite");
-    if (ap->substeps < 1 || ap->substeps > 1024) return fail(SP_ERR_INVALID_ARG, "substeps must be in [1, 1024]");
-    if (ap->integrator != SP_EULER && ap->integrator != SP_RK4)
-        return fail(SP_ERR_INVALID_ARG, "unknown integrator %d", ap->integrator);
+    if ((st = check_advect_params(ap))) return st;
     if (!flow || !aligned(flow, 8)) return fail(SP_ERR_INVALID_ARG, "flow must be a non-NULL 8-byte aligned pointer");
     if (!dev_ptr_ok(x1) || !dev_ptr_ok(y1) || !dev_ptr_ok(x2) || !dev_ptr_ok(y2))
         return fail(SP_ERR_INVALID_ARG, "x1, y1, x2, y2 must be non-NULL, 4-byte aligned device pointers");
@@ -370,18 +434,8 @@ synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synt
     if (sp::render_lds_bytes(cfg) > 160 * 1024)
         return fail(SP_ERR_UNSUPPORTED, "tiling needs %zu bytes of LDS per workgroup (max 163840)",
                     sp::render_lds_bytes(cfg));
-    sp::RenderArgs a{};
-    a.pairs = pairs_dev;
-    a.n_pairs = n_pairs;
-    a.x[0] = x1; a.y[0] = y1; a.x[1] = x2; a.y[1] = y2;
-    a.z = z; a.d = d; a.I0 = I0;
-    a.images = images;
-    a.sheet_sigma = rp->sheet_sigma;
-    a.noise_sigma = rp->noise_sigma;
-    a.bits = rp->bits;
-    a.seed = rp->seed;
-    blur_taps(rp->blur_radius, rp->blur_sigma, a.blur_w);
-    const hipError_t e = sp::launch_render(a, cfg, T, static_cast<char*>(workspace), wl, as_stream(stream));
+    const hipError_t e = enqueue_render(pairs_dev, n_pairs, cfg, T, wl, x1, y1, x2, y2, z, d, I0, *rp, images,
+                                        workspace, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return SP_OK;
 }
@@ -394,10 +448,273 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
                                               float* g_d, float* g_I0, float* g_sheet, float* g_flow,
                                               void* workspace, size_t ws_bytes, void* stream)
 {
-    (void)pairs_host; (void)pairs_dev; (void)n_pairs; (void)tiling; (void)flow; (void)x1; (void)y1; (void)z;
-    (void)d; (void)I0; (void)rp; (void)grad_images; (void)g_x1; (void)g_y1; (void)g_z; (void)g_d; (void)g_I0;
-    (void)g_sheet; (void)g_flow; (void)workspace; (void)ws_bytes; (void)stream;
-    return fail(SP_ERR_UNSUPPORTED, "backward not built yet");
+    int64_t span;
+    synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
+    if (st) return st;
+    if ((st = check_render_params(rp))) return st;
+    if (tiling && (st = check_tiling(*tiling))) return st;
+    if (rp->bits != 0) return fail(SP_ERR_UNSUPPORTED, "the backward differentiates float images (bits must be 0)");
+    if ((st = check_advect_params(&rp->advect))) return st;
+    if (!flow || !aligned(flow, 8)) return fail(SP_ERR_INVALID_ARG, "flow must be a non-NULL 8-byte aligned pointer");
+    if (!dev_ptr_ok(x1) || !dev_ptr_ok(y1) || !dev_ptr_ok(z) || !dev_ptr_ok(d) || !dev_ptr_ok(I0) ||
+        !dev_ptr_ok(grad_images))
+        return fail(SP_ERR_INVALID_ARG, "inputs must be non-NULL, 4-byte aligned device pointers");
+    if (!dev_ptr_ok(g_x1) || !dev_ptr_ok(g_y1) || !dev_ptr_ok(g_z) || !dev_ptr_ok(g_d) || !dev_ptr_ok(g_I0) ||
+        !dev_ptr_ok(g_sheet) || !dev_ptr_ok(g_flow))
+        return fail(SP_ERR_INVALID_ARG, "gradient outputs must be non-NULL, 4-byte aligned device pointers");
+    const int64_t n_flow = flow_span(pairs_host, n_pairs);
+    const BwdLayout wl = bwd_layout(span, n_flow);
+    if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < wl.total)
+        return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, wl.total);
+    char* ws = static_cast<char*>(workspace);
+    sp::BwdArgs a{};
+    a.pairs = pairs_dev;
+    a.n_pairs = n_pairs;
+    a.flow = flow;
+    a.x1 = x1;
+    a.y1 = y1;
+    a.x2 = reinterpret_cast<float*>(ws + wl.x2);
+    a.y2 = reinterpret_cast<float*>(ws + wl.y2);
+    a.z = z;
+    a.d = d;
+    a.I0 = I0;
+    a.grad = grad_images;
+    a.g_x1 = g_x1;
+    a.g_y1 = g_y1;
+    a.g_z = g_z;
+    a.g_d = g_d;
+    a.g_I0 = g_I0;
+    a.g_sheet = g_sheet;
+    a.g_flow = g_flow;
+    a.gx2 = reinterpret_cast<float*>(ws + wl.gx2);
+    a.gy2 = reinterpret_cast<float*>(ws + wl.gy2);
+    a.sheet = reinterpret_cast<float*>(ws + wl.sheet);
+    a.fixed = reinterpret_cast<unsigned long long*>(ws + wl.fixed);
+    a.kmax_bits = reinterpret_cast<uint32_t*>(ws + wl.kmax);
+    a.status = reinterpret_cast<uint32_t*>(ws + wl.status);
+    a.sheet_sigma = rp->sheet_sigma;
+    a.d_max = rp->d_max;
+    blur_taps(rp->blur_radius, rp->blur_sigma, a.blur_w);
+    const hipError_t e = sp::launch_backward(a, span, n_flow, rp->advect, rp->blur_radius,
+                                             sample_exponent(span, rp->advect), as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return SP_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plans
+
+struct synthpix_plan {
+    int device = 0;
+    int32_t n_pairs = 0;
+    std::vector<synthpix_pair> pairs_host;
+    synthpix_pair* pairs_dev = nullptr;
+    synthpix_seed_params sp{};
+    uint64_t seed = 0;
+    synthpix_advect_params ap{};
+    synthpix_render_params rp{};
+    synthpix_batch_io io{};
+    synthpix_tiling tiling{};
+    int advance = 0;
+    int64_t span = 0;
+    void* workspace = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// The whole path for one batch on `s`.
+hipError_t enqueue_batch(synthpix_plan* P, const synthpix_tiling& t, hipStream_t s, bool with_advance)
+{
+    hipError_t e = sp::launch_seed(P->pairs_dev, P->n_pairs, P->span, P->sp, P->seed, P->io.x1, P->io.y1, P->io.z,
+                                   P->io.d, P->io.I0, P->io.n_active, P->io.ppp, s);
+    if (e != hipSuccess) return e;
+    e = sp::launch_advect(P->pairs_dev, P->n_pairs, P->span, P->io.flow, P->ap, P->io.x1, P->io.y1, P->io.x2,
+                          P->io.y2, s);
+    if (e != hipSuccess) return e;
+    const sp::RenderConfig cfg = make_config(P->rp, t);
+    sp::BatchTotals T;
+    if (batch_totals(P->pairs_host.data(), P->n_pairs, cfg, &T) != SP_OK) return hipErrorInvalidValue;
+    const sp::WorkspaceLayout wl = workspace_layout(P->n_pairs, T, 0, P->pairs_host.data());
+    e = enqueue_render(P->pairs_dev, P->n_pairs, cfg, T, wl, P->io.x1, P->io.y1, P->io.x2, P->io.y2, P->io.z,
+                       P->io.d, P->io.I0, P->rp, P->io.images, P->workspace, s);
+    if (e != hipSuccess) return e;
+    if (with_advance && P->advance) e = sp::launch_advance(P->pairs_dev, P->n_pairs, (uint64_t)P->n_pairs, s);
+    return e;
+}
+
+// Every compiled tiling that fits this batch's parameters, default first.
+std::vector<synthpix_tiling> tiling_candidates(const synthpix_render_params& rp)
+{
+    std::vector<synthpix_tiling> out;
+    out.push_back(default_tiling());
+    const int shapes[][2] = {{32, 32}, {64, 32}, {64, 64}, {128, 32}, {32, 16}, {64, 16}};
+    const int caps[] = {32, 64, 128};
+    for (const auto& sh : shapes)
+        for (int cap : caps) {
+            synthpix_tiling t{sh[0], sh[1], 4096, cap};
+            if (t.tile_w == out[0].tile_w && t.tile_h == out[0].tile_h && t.cap == out[0].cap) continue;
+            if (sp::render_lds_bytes(make_config(rp, t)) > 160 * 1024) continue;
+            out.push_back(t);
+        }
+    return out;
+}
+
+void plan_free(synthpix_plan* P)
+{
+    if (!P) return;
+    if (P->exec) hipGraphExecDestroy(P->exec);
+    if (P->graph) hipGraphDestroy(P->graph);
+    if (P->capture) hipStreamDestroy(P->capture);
+    if (P->workspace) hipFree(P->workspace);
+    if (P->pairs_dev) hipFree(P->pairs_dev);
+    delete P;
+}
+
+}  // namespace
+
+extern "C" {
+
+synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_pairs,
+                                     const synthpix_seed_params* sp_, uint64_t seed,
+                                     const synthpix_advect_params* ap, const synthpix_render_params* rp,
+                                     const synthpix_batch_io* io, int32_t autotune, int32_t advance_pair_ids,
+                                     void* stream, synthpix_plan** out)
+{
+    if (!out) return fail(SP_ERR_INVALID_ARG, "out must be non-NULL");
+    *out = nullptr;
+    int64_t span;
+    synthpix_status st = check_pairs(pairs_host, pairs_host, n_pairs, &span);
+    if (st) return st;
+    if (!sp_ || !ap || !rp || !io) return fail(SP_ERR_INVALID_ARG, "parameter structs and io must be non-NULL");
+    if ((st = check_render_params(rp))) return st;
+    if (!io->flow || !dev_ptr_ok(io->x1) || !dev_ptr_ok(io->y1) || !dev_ptr_ok(io->x2) || !dev_ptr_ok(io->y2) ||
+        !dev_ptr_ok(io->z) || !dev_ptr_ok(io->d) || !dev_ptr_ok(io->I0) || !io->images)
+        return fail(SP_ERR_INVALID_ARG, "io buffers must be non-NULL, aligned device pointers");
+    const synthpix_tiling t0 = default_tiling();
+    {
+        sp::BatchTotals T;
+        if ((st = batch_totals(pairs_host, n_pairs, make_config(*rp, t0), &T))) return st;
+    }
+    synthpix_plan* P = new synthpix_plan();
+    P->n_pairs = n_pairs;
+    P->pairs_host.assign(pairs_host, pairs_host + n_pairs);
+    P->sp = *sp_;
+    P->seed = seed;
+    P->ap = *ap;
+    P->rp = *rp;
+    P->io = *io;
+    P->advance = advance_pair_ids ? 1 : 0;
+    P->span = span;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipGetDevice(&P->device);
+    if (e == hipSuccess) e = hipMalloc(&P->pairs_dev, sizeof(synthpix_pair) * (size_t)n_pairs);
+    if (e == hipSuccess)
+        e = hipMemcpy(P->pairs_dev, pairs_host, sizeof(synthpix_pair) * (size_t)n_pairs, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return hip_fail(e, "plan set-up");
+    }
+    // workspace for the largest candidate
+    std::vector<synthpix_tiling> cands = autotune ? tiling_candidates(*rp) : std::vector<synthpix_tiling>{t0};
+    size_t ws = 0;
+    std::vector<synthpix_tiling> ok;
+    for (const auto& t : cands) {
+        sp::BatchTotals T;
+        if (batch_totals(pairs_host, n_pairs, make_config(*rp, t), &T) != SP_OK) continue;
+        ws = std::max(ws, workspace_layout(n_pairs, T, 0, pairs_host).total);
+        ok.push_back(t);
+    }
+    g_err.clear();
+    if (ok.empty()) {
+        plan_free(P);
+        return fail(SP_ERR_UNSUPPORTED, "no tiling fits this batch");
+    }
+    e = hipMalloc(&P->workspace, ws);
+    P->ws_bytes = ws;
+    if (e != hipSuccess) {
+        plan_free(P);
+        return hip_fail(e, "plan workspace");
+    }
+    P->tiling = ok[0];
+    if (ok.size() > 1) {
+        // time each candidate's render of this batch (seed/advect once, render warm-up + 3 runs)
+        e = enqueue_batch(P, ok[0], s, false);
+        hipEvent_t a = nullptr, b = nullptr;
+        if (e == hipSuccess) e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        float best = 1e30f;
+        for (size_t i = 0; i < ok.size() && e == hipSuccess; ++i) {
+            const sp::RenderConfig cfg = make_config(*rp, ok[i]);
+            sp::BatchTotals T;
+            batch_totals(pairs_host, n_pairs, cfg, &T);
+            const sp::WorkspaceLayout wl = workspace_layout(n_pairs, T, 0, pairs_host);
+            auto run = [&]() {
+                return enqueue_render(P->pairs_dev, n_pairs, cfg, T, wl, io->x1, io->y1, io->x2, io->y2, io->z,
+                                      io->d, io->I0, *rp, io->images, P->workspace, s);
+            };
+            e = run();
+            if (e == hipSuccess) e = hipEventRecord(a, s);
+            for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                P->tiling = ok[i];
+            }
+        }
+        if (a) hipEventDestroy(a);
+        if (b) hipEventDestroy(b);
+        if (e != hipSuccess) {
+            plan_free(P);
+            return hip_fail(e, "autotuning");
+        }
+    }
+    // capture the whole path once
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(P->capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t ee = enqueue_batch(P, P->tiling, P->capture, true);
+        e = hipStreamEndCapture(P->capture, &P->graph);
+        if (ee != hipSuccess) e = ee;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        plan_free(P);
+        return hip_fail(e, "graph capture");
+    }
+    *out = P;
+    return SP_OK;
+}
+
+synthpix_status synthpix_plan_launch(synthpix_plan* plan, void* stream)
+{
+    if (!plan || !plan->exec) return fail(SP_ERR_INVALID_ARG, "plan must be a created plan");
+    const hipError_t e = hipGraphLaunch(plan->exec, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return SP_OK;
+}
+
+synthpix_status synthpix_plan_tiling(const synthpix_plan* plan, synthpix_tiling* out)
+{
+    if (!plan || !out) return fail(SP_ERR_INVALID_ARG, "plan and out must be non-NULL");
+    *out = plan->tiling;
+    return SP_OK;
+}
+
+synthpix_status synthpix_plan_destroy(synthpix_plan* plan)
+{
+    plan_free(plan);
+    return SP_OK;
 }
 
 }  // extern "C"

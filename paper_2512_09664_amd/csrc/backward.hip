@@ -1,0 +1,532 @@
+// Adjoint of advect -> render -> blur (gfx950): given dL/dJ of the float images,
+// the gradients with respect to frame-1 positions, z, d, I0, each pair's sheet
+// width and each pair's flow grid.
+//
+// Render adjoint (Eq. 1 with sigma = d/4 and peak A = I0 exp(-z^2 / (2 s^2))):
+// every particle's footprint is separable, t = A gx(c) gy(r), so with the
+// zero-padded blur B (also separable) the four per-particle sums the chain rule
+// needs,
+//     S0 = sum_q e_q G_q,  Sx = sum e G dx,  Sy = sum e G dy,  Sr = sum e G (dx^2 + dy^2),
+// e = B^T dL/dJ, equal sum_q (dL/dJ)_q Ty_j(r) Tx_k(c) with 1-D tables
+// Tx_k = w * (gx dx^k) (the blur folded into the particle's factor tables).
+// The gather is particle-major: 16 lanes per particle read their patch rows
+// of dL/dJ with coalesced loads; nothing is scattered, no partial sums cross
+// tiles.
+//
+// Flow adjoint: a reverse sweep through the recomputed Euler / RK4 substeps
+// (checkpointed every ceil(substeps / 32) substeps).  Each bilinear sample
+// passes its upstream gradient to its four grid nodes; consecutive samples in
+// one cell are merged per particle, and node sums are accumulated in 64-bit
+// fixed point, so the result does not depend on the order of the additions.
+// The fixed-point scale is a power of two set from the largest upstream value
+// (found by a first sweep) and the sample count, so no sum can overflow.
+#include "device_math.hpp"
+#include "flow.hpp"
+#include "launch.hpp"
+
+namespace sp {
+
+constexpr int BG = 16;             // lanes per particle in the gather
+constexpr int BPW = 256 / BG;      // particles per workgroup
+constexpr int BT = 64;             // table slots: support (<= 3 d_max + 2) + 4 b zero padding
+
+struct GatherLds {
+    float rx[BPW][3][BT];          // raw column factors gx dx^k, k = 0, 1, 2 (slot = c - c0 + 2b)
+    float ry[BPW][3][BT];
+    float tx[BPW][3][BT];          // blurred column tables (slot = q - c0 + b)
+    float4 ty[BPW][BT];            // blurred row tables (Ty0, Ty1, Ty2, 0)
+};
+
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int m = BG / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, BG);
+    return v;
+}
+
+template <int B>
+__global__ void __launch_bounds__(256)
+bwd_gather(BwdArgs a, int64_t n_span)
+{
+    __shared__ GatherLds S;
+    const int grp = threadIdx.x / BG, lane = threadIdx.x % BG;
+    const int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * BPW + grp;
+
+    bool in_pair = false, valid = false;
+    int H = 1, W = 1;
+    int64_t img = 0;
+    float z = 0.0f, d = 1.0f, I0 = 0.0f;
+    if (g < n_span) {
+        const int p = find_pair_by_particle(a.pairs, a.n_pairs, g);
+        const synthpix_pair P = a.pairs[p];
+        const int64_t i = g - P.particle_offset;
+        if (i >= 0 && i < P.n_max) {
+            in_pair = true;
+            H = P.H;
+            W = P.W;
+            img = P.image_offset;
+            z = a.z[g];
+            d = a.d[g];
+            I0 = a.I0[g];
+            valid = (I0 > 0.0f) && (d > 0.0f);
+            if (valid && !(d <= a.d_max)) {
+                if (lane == 0) atomicOr(a.status, SP_STATUS_D_ABOVE_MAX);
+                valid = false;
+            }
+        }
+    }
+    const float kap = 8.0f / (d * d);
+    const float R = 1.5f * d;
+    float sum0 = 0.0f, sumr = 0.0f, sx[2] = {0.0f, 0.0f}, sy[2] = {0.0f, 0.0f};
+
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        float x = 0.0f, y = 0.0f;
+        if (in_pair) {
+            x = f ? a.x2[g] : a.x1[g];
+            y = f ? a.y2[g] : a.y1[g];
+        }
+        int c0 = 0, c1 = -1, r0 = 0, r1 = -1;
+        bool on = valid && __builtin_isfinite(x) && __builtin_isfinite(y);
+        on = on && support_range(x, R, W, c0, c1);
+        on = on && support_range(y, R, H, r0, r1);
+
+        // raw factor tables; every slot is written (zeros outside the support)
+#pragma unroll
+        for (int m = 0; m < BT / BG; ++m) {
+            const int slot = lane + BG * m;
+            const int c = c0 - 2 * B + slot;
+            float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+            if (on && c >= c0 && c <= c1) {
+                const float dx = ((float)c + 0.5f) - x;
+                v0 = expneg(kap * (dx * dx));
+                v1 = v0 * dx;
+                v2 = v1 * dx;
+            }
+            S.rx[grp][0][slot] = v0;
+            S.rx[grp][1][slot] = v1;
+            S.rx[grp][2][slot] = v2;
+            const int r = r0 - 2 * B + slot;
+            float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+            if (on && r >= r0 && r <= r1) {
+                const float dy = ((float)r + 0.5f) - y;
+                u0 = expneg(kap * (dy * dy));
+                u1 = u0 * dy;
+                u2 = u1 * dy;
+            }
+            if (B == 0) {
+                S.ty[grp][slot] = make_float4(u0, u1, u2, 0.0f);
+            } else {
+                S.ry[grp][0][slot] = u0;
+                S.ry[grp][1][slot] = u1;
+                S.ry[grp][2][slot] = u2;
+            }
+        }
+        __syncthreads();
+        if (B > 0) {
+            // table slot t is pixel c0 - b + t; raw slot t + 2b - k' holds pixel q - (k' - b)
+#pragma unroll
+            for (int m = 0; m < BT / BG; ++m) {
+                const int t = lane + BG * m;
+                if (t < BT - 2 * B) {
+                    float X[3] = {0.0f, 0.0f, 0.0f}, Y[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int k = 0; k <= 2 * B; ++k) {
+                        const float w = a.blur_w[k];
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            X[j] = __builtin_fmaf(w, S.rx[grp][j][t + 2 * B - k], X[j]);
+                            Y[j] = __builtin_fmaf(w, S.ry[grp][j][t + 2 * B - k], Y[j]);
+                        }
+                    }
+                    S.tx[grp][0][t] = X[0];
+                    S.tx[grp][1][t] = X[1];
+                    S.tx[grp][2][t] = X[2];
+                    S.ty[grp][t] = make_float4(Y[0], Y[1], Y[2], 0.0f);
+                }
+            }
+            __syncthreads();
+        }
+
+        // gather: sum_q (dL/dJ)_q Ty(r) Tx(c) over the blurred support, inside the image
+        float s0 = 0.0f, s_x = 0.0f, s_y = 0.0f, s_r = 0.0f;
+        if (on) {
+            const int nt = (c1 - c0 + 1) + 2 * B, nu = (r1 - r0 + 1) + 2 * B;
+            const int tlo = B - c0 > 0 ? B - c0 : 0;
+            const int thi = nt < W - c0 + B ? nt : W - c0 + B;
+            const int ulo = B - r0 > 0 ? B - r0 : 0;
+            const int uhi = nu < H - r0 + B ? nu : H - r0 + B;
+            const float* __restrict__ gimg = a.grad + img + (int64_t)f * H * W;
+            const float(*T)[BT] = B > 0 ? S.tx[grp] : S.rx[grp];
+            for (int t = tlo + lane; t < thi; t += BG) {
+                const float X0 = T[0][t], X1 = T[1][t], X2 = T[2][t];
+                const float* __restrict__ col = gimg + (int64_t)(r0 - B) * W + (c0 - B + t);
+                for (int u = ulo; u < uhi; ++u) {
+                    const float e = col[(int64_t)u * W];
+                    const float4 ty = S.ty[grp][u];
+                    const float a0 = ty.x * e, a1 = ty.y * e, a2 = ty.z * e;
+                    s0 = __builtin_fmaf(a0, X0, s0);
+                    s_x = __builtin_fmaf(a0, X1, s_x);
+                    s_y = __builtin_fmaf(a1, X0, s_y);
+                    s_r = __builtin_fmaf(a0, X2, s_r);
+                    s_r = __builtin_fmaf(a2, X0, s_r);
+                }
+            }
+        }
+        sum0 += group_sum(s0);
+        sx[f] = group_sum(s_x);
+        sy[f] = group_sum(s_y);
+        sumr += group_sum(s_r);
+        __syncthreads();
+    }
+
+    if (!in_pair || lane != 0) return;
+    float gx1 = 0.0f, gy1 = 0.0f, gx2 = 0.0f, gy2 = 0.0f, gd = 0.0f, gz = 0.0f, gI0 = 0.0f, sheet = 0.0f;
+    if (valid) {
+        const float s = a.sheet_sigma;
+        const float Sz = expneg((z * z) * (0.5f / (s * s)));
+        const float A = I0 * Sz;
+        const float k2 = 2.0f * kap;                // d/dx of -kap dx^2 is 2 kap dx
+        gx1 = A * k2 * sx[0];
+        gy1 = A * k2 * sy[0];
+        gx2 = A * k2 * sx[1];
+        gy2 = A * k2 * sy[1];
+        gd = A * (k2 / d) * sumr;                   // d kap / d d = -2 kap / d
+        gI0 = sum0 * Sz;
+        gz = sum0 * A * (-z / (s * s));
+        sheet = sum0 * A * ((z * z) / (s * s * s));
+    }
+    a.g_x1[g] = gx1;
+    a.g_y1[g] = gy1;
+    a.g_z[g] = gz;
+    a.g_d[g] = gd;
+    a.g_I0[g] = gI0;
+    a.gx2[g] = gx2;
+    a.gy2[g] = gy2;
+    a.sheet[g] = sheet;
+}
+
+// ------------------------------------------------------------------ flow adjoint
+
+struct Sample {
+    float2 val;
+    float2 jx, jy;        // dU/dpx, dU/dpy (zero along clamped axes)
+    int i0, j0;
+    float fx, fy;
+};
+
+// Value bit-identical to sample_flow, plus Jacobian and node weights.
+__device__ __forceinline__ Sample sample_jac(const FlowView& fv, float px, float py)
+{
+    Sample o;
+    const float gxr = px * fv.sx - 0.5f;
+    const float gyr = py * fv.sy - 0.5f;
+    const float gx = __builtin_fminf(__builtin_fmaxf(gxr, 0.0f), (float)(fv.Gw - 1));
+    const float gy = __builtin_fminf(__builtin_fmaxf(gyr, 0.0f), (float)(fv.Gh - 1));
+    int j0 = (int)__builtin_floorf(gx);
+    int i0 = (int)__builtin_floorf(gy);
+    j0 = j0 > fv.Gw - 2 ? fv.Gw - 2 : j0;
+    i0 = i0 > fv.Gh - 2 ? fv.Gh - 2 : i0;
+    const float fx = gx - (float)j0;
+    const float fy = gy - (float)i0;
+    const float2* row0 = fv.F + (size_t)i0 * fv.Gw + j0;
+    const float2* row1 = row0 + fv.Gw;
+    const float2 A = row0[0], Bn = row0[1], C = row1[0], E = row1[1];
+    {
+        const float top = __builtin_fmaf(fx, Bn.x - A.x, A.x);
+        const float bot = __builtin_fmaf(fx, E.x - C.x, C.x);
+        o.val.x = __builtin_fmaf(fy, bot - top, top);
+    }
+    {
+        const float top = __builtin_fmaf(fx, Bn.y - A.y, A.y);
+        const float bot = __builtin_fmaf(fx, E.y - C.y, C.y);
+        o.val.y = __builtin_fmaf(fy, bot - top, top);
+    }
+    const float inx = (gxr > 0.0f && gxr < (float)(fv.Gw - 1)) ? fv.sx : 0.0f;
+    const float iny = (gyr > 0.0f && gyr < (float)(fv.Gh - 1)) ? fv.sy : 0.0f;
+    o.jx.x = ((1.0f - fy) * (Bn.x - A.x) + fy * (E.x - C.x)) * inx;
+    o.jx.y = ((1.0f - fy) * (Bn.y - A.y) + fy * (E.y - C.y)) * inx;
+    o.jy.x = ((1.0f - fx) * (C.x - A.x) + fx * (E.x - Bn.x)) * iny;
+    o.jy.y = ((1.0f - fx) * (C.y - A.y) + fx * (E.y - Bn.y)) * iny;
+    o.i0 = i0;
+    o.j0 = j0;
+    o.fx = fx;
+    o.fy = fy;
+    return o;
+}
+
+// Per-particle accumulation of node contributions, merged while consecutive
+// samples stay in one grid cell.
+template <bool SCATTER>
+struct NodeRun {
+    int cell = -1, i0 = 0, j0 = 0;
+    float acc[8];
+    float kmax = 0.0f;
+    unsigned long long* fixed;
+    int64_t base;         // element offset of the pair's grid
+    int Gw;
+    double scale;
+
+    __device__ void flush()
+    {
+        if (!SCATTER || cell < 0) return;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int64_t e = base + 2 * ((int64_t)(i0 + (n >> 1)) * Gw + (j0 + (n & 1)));
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float v = acc[2 * n + c];
+                if (v != 0.0f) {
+                    const long long q = (long long)__builtin_rint((double)v * scale);
+                    atomicAdd(fixed + e + c, (unsigned long long)q);
+                }
+            }
+        }
+    }
+
+    __device__ void add(const Sample& s, float ku, float kv)
+    {
+        kmax = __builtin_fmaxf(kmax, __builtin_fmaxf(__builtin_fabsf(ku), __builtin_fabsf(kv)));
+        if (!SCATTER) return;
+        const int key = s.i0 * Gw + s.j0;
+        if (key != cell) {
+            flush();
+            cell = key;
+            i0 = s.i0;
+            j0 = s.j0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
+        }
+        const float w[4] = {(1.0f - s.fx) * (1.0f - s.fy), s.fx * (1.0f - s.fy), (1.0f - s.fx) * s.fy, s.fx * s.fy};
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            acc[2 * n] = __builtin_fmaf(w[n], ku, acc[2 * n]);
+            acc[2 * n + 1] = __builtin_fmaf(w[n], kv, acc[2 * n + 1]);
+        }
+    }
+};
+
+// Back-propagate one sample with upstream (ku, kv); returns J^T k in (bx, by).
+template <bool SCATTER>
+__device__ __forceinline__ void stage_back(const FlowView& fv, NodeRun<SCATTER>& run, float px, float py, float ku,
+                                           float kv, float& bx, float& by)
+{
+    const Sample s = sample_jac(fv, px, py);
+    run.add(s, ku, kv);
+    bx = s.jx.x * ku + s.jx.y * kv;
+    by = s.jy.x * ku + s.jy.y * kv;
+}
+
+template <bool SCATTER>
+__device__ __forceinline__ void substep_adjoint(const FlowView& fv, NodeRun<SCATTER>& run, float px, float py,
+                                                float h, float hh, int integrator, float& gpx, float& gpy)
+{
+    float bx, by;
+    if (integrator == SP_EULER) {
+        stage_back(fv, run, px, py, h * gpx, h * gpy, bx, by);
+        gpx += bx;
+        gpy += by;
+        return;
+    }
+    const float2 k1 = sample_flow(fv, px, py);
+    const float p2x = __builtin_fmaf(hh, k1.x, px), p2y = __builtin_fmaf(hh, k1.y, py);
+    const float2 k2 = sample_flow(fv, p2x, p2y);
+    const float p3x = __builtin_fmaf(hh, k2.x, px), p3y = __builtin_fmaf(hh, k2.y, py);
+    const float2 k3 = sample_flow(fv, p3x, p3y);
+    const float p4x = __builtin_fmaf(h, k3.x, px), p4y = __builtin_fmaf(h, k3.y, py);
+    const float c = h / 6.0f;
+    float b4x, b4y, b3x, b3y, b2x, b2y, b1x, b1y;
+    stage_back(fv, run, p4x, p4y, c * gpx, c * gpy, b4x, b4y);
+    stage_back(fv, run, p3x, p3y, 2.0f * c * gpx + h * b4x, 2.0f * c * gpy + h * b4y, b3x, b3y);
+    stage_back(fv, run, p2x, p2y, 2.0f * c * gpx + hh * b3x, 2.0f * c * gpy + hh * b3y, b2x, b2y);
+    stage_back(fv, run, px, py, c * gpx + hh * b2x, c * gpy + hh * b2y, b1x, b1y);
+    gpx += ((b1x + b2x) + b3x) + b4x;
+    gpy += ((b1y + b2y) + b3y) + b4y;
+}
+
+constexpr int CKPT = 32;
+
+// SCATTER = false: the sweep's largest upstream value (into kmax_bits) and the
+// final position gradient (added to g_x1, g_y1).  SCATTER = true: the same
+// sweep again, node sums into the fixed-point grid.
+template <bool SCATTER>
+__global__ void __launch_bounds__(256)
+bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap, int en)
+{
+    const int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    NodeRun<SCATTER> run;
+    run.fixed = a.fixed;
+    run.base = 0;
+    run.Gw = 2;
+    run.scale = 0.0;
+    bool live = false;
+    FlowView fv{reinterpret_cast<const float2*>(a.flow), 2, 2, 1.0f, 1.0f};
+    float gpx = 0.0f, gpy = 0.0f, px = 0.0f, py = 0.0f;
+    if (g < n_span) {
+        const int p = find_pair_by_particle(a.pairs, a.n_pairs, g);
+        const synthpix_pair P = a.pairs[p];
+        const int64_t i = g - P.particle_offset;
+        if (i >= 0 && i < P.n_max) {
+            gpx = a.gx2[g];
+            gpy = a.gy2[g];
+            px = a.x1[g];
+            py = a.y1[g];
+            live = (gpx != 0.0f || gpy != 0.0f) && __builtin_isfinite(px) && __builtin_isfinite(py);
+            fv = flow_view(P, a.flow);
+            run.base = P.flow_offset;
+            run.Gw = P.Gw;
+        }
+    }
+    if (SCATTER) {
+        const float M = __uint_as_float(*a.kmax_bits);
+        if (!(M > 0.0f) || !__builtin_isfinite(M)) return;
+        int em;
+        (void)__builtin_frexpf(M, &em);
+        run.scale = __builtin_ldexp(1.0, 61 - em - en);
+    }
+    if (live) {
+        const int S = ap.substeps;
+        const float h = ap.dt / (float)S;
+        const float hh = h * 0.5f;
+        const int L = (S + CKPT - 1) / CKPT;
+        const int nseg = (S + L - 1) / L;
+        float cpx[CKPT], cpy[CKPT];
+        float qx = px, qy = py;
+        for (int s = 0; s < S; ++s) {
+            if (s % L == 0) {
+                cpx[s / L] = qx;
+                cpy[s / L] = qy;
+            }
+            if (s + 1 < S) substep(fv, qx, qy, h, hh, ap.integrator);
+        }
+        float spx[CKPT], spy[CKPT];
+        for (int seg = nseg - 1; seg >= 0; --seg) {
+            const int s0 = seg * L;
+            const int len = (S - s0) < L ? (S - s0) : L;
+            spx[0] = cpx[seg];
+            spy[0] = cpy[seg];
+            for (int k = 1; k < len; ++k) {
+                float tx = spx[k - 1], ty = spy[k - 1];
+                substep(fv, tx, ty, h, hh, ap.integrator);
+                spx[k] = tx;
+                spy[k] = ty;
+            }
+            for (int k = len - 1; k >= 0; --k)
+                substep_adjoint<SCATTER>(fv, run, spx[k], spy[k], h, hh, ap.integrator, gpx, gpy);
+        }
+        run.flush();
+        if (!SCATTER) {
+            a.g_x1[g] += gpx;
+            a.g_y1[g] += gpy;
+        }
+    }
+    if (!SCATTER) {
+        // block maximum of the upstream magnitudes, one atomic per block (float bits of
+        // non-negative values order like unsigned integers)
+        float m = run.kmax;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) m = __builtin_fmaxf(m, __shfl_xor(m, o, 64));
+        __shared__ float wmax[4];
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const float b = __builtin_fmaxf(__builtin_fmaxf(wmax[0], wmax[1]), __builtin_fmaxf(wmax[2], wmax[3]));
+            if (b != 0.0f) atomicMax(a.kmax_bits, __float_as_uint(b));
+        }
+    }
+}
+
+__global__ void bwd_init(unsigned long long* __restrict__ fixed, int64_t n, uint32_t* __restrict__ status,
+                         uint32_t* __restrict__ kmax_bits)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        status[0] = 0u;
+        status[1] = 0u;
+        status[2] = 0u;
+        status[3] = 0u;
+        *kmax_bits = 0u;
+    }
+    for (int64_t k = t; k < n; k += (int64_t)gridDim.x * blockDim.x) fixed[k] = 0ull;
+}
+
+__global__ void bwd_flow_finish(const unsigned long long* __restrict__ fixed, int64_t n,
+                                const uint32_t* __restrict__ kmax_bits, int en, float* __restrict__ g_flow)
+{
+    const float M = __uint_as_float(*kmax_bits);
+    double inv = 0.0;
+    float fill = 0.0f;
+    if (M > 0.0f && __builtin_isfinite(M)) {
+        int em;
+        (void)__builtin_frexpf(M, &em);
+        inv = __builtin_ldexp(1.0, -(61 - em - en));
+    } else if (!(M == 0.0f)) {
+        fill = __builtin_nanf("");
+    }
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        g_flow[k] = inv != 0.0 ? (float)((double)(long long)fixed[k] * inv) : fill;
+}
+
+// Per-pair sum of the sheet-width terms, in float64, in a fixed order.
+__global__ void __launch_bounds__(256)
+bwd_sheet(const synthpix_pair* __restrict__ pairs, const float* __restrict__ sheet, float* __restrict__ g_sheet)
+{
+    const synthpix_pair P = pairs[blockIdx.x];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < P.n_max; i += 256) s += (double)sheet[P.particle_offset + i];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g_sheet[blockIdx.x] = (float)red[0];
+}
+
+hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, const synthpix_advect_params& ap,
+                           int blur, int en, hipStream_t s)
+{
+    {
+        TimedScope ts("bwd_init", s);
+        const int64_t blocks = std::min<int64_t>((n_flow + 255) / 256 + 1, 4096);
+        hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.status,
+                           a.kmax_bits);
+    }
+    if (n_span > 0) {
+        hipError_t e = launch_advect(a.pairs, a.n_pairs, n_span, a.flow, ap, a.x1, a.y1, a.x2, a.y2, s);
+        if (e != hipSuccess) return e;
+        const unsigned gb = (unsigned)((n_span + BPW - 1) / BPW);
+        {
+            TimedScope ts("bwd_gather", s);
+            switch (blur) {
+            case 0: hipLaunchKernelGGL(bwd_gather<0>, dim3(gb), dim3(256), 0, s, a, n_span); break;
+            case 1: hipLaunchKernelGGL(bwd_gather<1>, dim3(gb), dim3(256), 0, s, a, n_span); break;
+            case 2: hipLaunchKernelGGL(bwd_gather<2>, dim3(gb), dim3(256), 0, s, a, n_span); break;
+            default: hipLaunchKernelGGL(bwd_gather<3>, dim3(gb), dim3(256), 0, s, a, n_span); break;
+            }
+        }
+        const unsigned ab = (unsigned)((n_span + 255) / 256);
+        {
+            TimedScope ts("bwd_advect_max", s);
+            hipLaunchKernelGGL(bwd_advect<false>, dim3(ab), dim3(256), 0, s, a, n_span, ap, en);
+        }
+        {
+            TimedScope ts("bwd_advect_scatter", s);
+            hipLaunchKernelGGL(bwd_advect<true>, dim3(ab), dim3(256), 0, s, a, n_span, ap, en);
+        }
+    }
+    {
+        TimedScope ts("bwd_flow", s);
+        const int64_t blocks = std::min<int64_t>((n_flow + 255) / 256 + 1, 8192);
+        hipLaunchKernelGGL(bwd_flow_finish, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.kmax_bits,
+                           en, a.g_flow);
+    }
+    {
+        TimedScope ts("bwd_sheet", s);
+        hipLaunchKernelGGL(bwd_sheet, dim3((unsigned)a.n_pairs), dim3(256), 0, s, a.pairs, a.sheet, a.g_sheet);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sp

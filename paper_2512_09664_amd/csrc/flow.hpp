@@ -1,0 +1,79 @@
+// Bilinear sampling of a pair's cell-centred flow grid (shared by the
+// advection kernel and its adjoint).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "synthpix.h"
+
+namespace sp {
+
+struct FlowView {
+    const float2* __restrict__ F;
+    int Gh, Gw;
+    float sx, sy;      // Gw / W, Gh / H (correctly rounded)
+};
+
+__device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, float py)
+{
+    float gx = px * fv.sx - 0.5f;
+    float gy = py * fv.sy - 0.5f;
+    gx = __builtin_fminf(__builtin_fmaxf(gx, 0.0f), (float)(fv.Gw - 1));
+    gy = __builtin_fminf(__builtin_fmaxf(gy, 0.0f), (float)(fv.Gh - 1));
+    int j0 = (int)__builtin_floorf(gx);
+    int i0 = (int)__builtin_floorf(gy);
+    j0 = j0 > fv.Gw - 2 ? fv.Gw - 2 : j0;
+    i0 = i0 > fv.Gh - 2 ? fv.Gh - 2 : i0;
+    const float fx = gx - (float)j0;
+    const float fy = gy - (float)i0;
+    const float2* row0 = fv.F + (size_t)i0 * fv.Gw + j0;
+    const float2* row1 = row0 + fv.Gw;
+    const float2 a = row0[0], b = row0[1], c = row1[0], e = row1[1];
+    float2 out;
+    {
+        const float top = __builtin_fmaf(fx, b.x - a.x, a.x);
+        const float bot = __builtin_fmaf(fx, e.x - c.x, c.x);
+        out.x = __builtin_fmaf(fy, bot - top, top);
+    }
+    {
+        const float top = __builtin_fmaf(fx, b.y - a.y, a.y);
+        const float bot = __builtin_fmaf(fx, e.y - c.y, c.y);
+        out.y = __builtin_fmaf(fy, bot - top, top);
+    }
+    return out;
+}
+
+__device__ __forceinline__ FlowView flow_view(const synthpix_pair& P, const float* flow)
+{
+    FlowView fv;
+    fv.F = reinterpret_cast<const float2*>(flow + P.flow_offset);
+    fv.Gh = P.Gh;
+    fv.Gw = P.Gw;
+    fv.sx = (float)P.Gw / (float)P.W;
+    fv.sy = (float)P.Gh / (float)P.H;
+    return fv;
+}
+
+// One substep of the frozen-field integrator, the same operations in the same
+// order as the advection kernel: Euler p = fma(h, u, p); RK4 stages at
+// fma(h/2, k, p) and fma(h, k3, p), update fma(h, (((k1 + 2 k2) + 2 k3) + k4) / 6, p).
+__device__ __forceinline__ void substep(const FlowView& fv, float& px, float& py, float h, float hh, int integrator)
+{
+    if (integrator == SP_EULER) {
+        const float2 u = sample_flow(fv, px, py);
+        px = __builtin_fmaf(h, u.x, px);
+        py = __builtin_fmaf(h, u.y, py);
+        return;
+    }
+    const float2 k1 = sample_flow(fv, px, py);
+    const float2 k2 = sample_flow(fv, __builtin_fmaf(hh, k1.x, px), __builtin_fmaf(hh, k1.y, py));
+    const float2 k3 = sample_flow(fv, __builtin_fmaf(hh, k2.x, px), __builtin_fmaf(hh, k2.y, py));
+    const float2 k4 = sample_flow(fv, __builtin_fmaf(h, k3.x, px), __builtin_fmaf(h, k3.y, py));
+    const float su = ((k1.x + 2.0f * k2.x) + 2.0f * k3.x) + k4.x;
+    const float sv = ((k1.y + 2.0f * k2.y) + 2.0f * k3.y) + k4.y;
+    px = __builtin_fmaf(h, su / 6.0f, px);
+    py = __builtin_fmaf(h, sv / 6.0f, py);
+}
+
+}  // namespace sp

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "synthpix.h"
 
 namespace sp {
@@ -65,16 +67,14 @@ struct WorkspaceLayout {
     size_t hist;            // uint32 [hist]
     size_t entries;         // int32  [entries]
     size_t records;         // float4 [2 * n_span] per-frame particle records
-    size_t grad_img;        // float  (backward only) dL/dI images
-    size_t x2;              // float  (backward only) recomputed frame-2 positions
-    size_t y2;
-    size_t gpart;           // float  (backward only) per particle partial sums
     size_t total;
 };
 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
                        const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
                        float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s);
+
+hipError_t launch_advance(synthpix_pair* pairs_dev, int n_pairs, uint64_t step, hipStream_t s);
 
 hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
                          const synthpix_advect_params& ap, const float* x1, const float* y1, float* x2,
@@ -110,6 +110,40 @@ bool render_shape_supported(int tile_w, int tile_h);
 
 hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot,
                          char* ws, const WorkspaceLayout& wl, hipStream_t s);
+
+// Everything the backward kernels read and write.
+struct BwdArgs {
+    const synthpix_pair* pairs;
+    int n_pairs;
+    const float* flow;
+    const float* x1;
+    const float* y1;
+    float* x2;                   // recomputed frame-2 positions (workspace)
+    float* y2;
+    const float* z;
+    const float* d;
+    const float* I0;
+    const float* grad;           // dL/dJ, the images' layout
+    float* g_x1;
+    float* g_y1;
+    float* g_z;
+    float* g_d;
+    float* g_I0;
+    float* g_sheet;
+    float* g_flow;
+    float* gx2;                  // dL/dx2, dL/dy2 (workspace)
+    float* gy2;
+    float* sheet;                // per-particle sheet-width terms (workspace)
+    unsigned long long* fixed;   // fixed-point flow-gradient sums (workspace, flow layout)
+    uint32_t* kmax_bits;
+    uint32_t* status;
+    float sheet_sigma;
+    float d_max;
+    float blur_w[7];
+};
+
+hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, const synthpix_advect_params& ap,
+                           int blur, int en, hipStream_t s);
 
 // Compute units of the current device (cached per device).
 int device_cu_count();

@@ -10,6 +10,7 @@
 // One thread per particle; SoA float stores are fully coalesced.  Both kernels
 // are bound by Philox / interpolation arithmetic, not by memory.
 #include "device_math.hpp"
+#include "flow.hpp"
 #include "launch.hpp"
 
 namespace sp {
@@ -75,52 +76,6 @@ seed_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span
 }
 
 // Bilinear sample of the pair's (u, v) grid at image position (px, py).
-struct FlowView {
-    const float2* __restrict__ F;
-    int Gh, Gw;
-    float sx, sy;      // Gw / W, Gh / H (correctly rounded)
-};
-
-__device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, float py)
-{
-    float gx = px * fv.sx - 0.5f;
-    float gy = py * fv.sy - 0.5f;
-    gx = __builtin_fminf(__builtin_fmaxf(gx, 0.0f), (float)(fv.Gw - 1));
-    gy = __builtin_fminf(__builtin_fmaxf(gy, 0.0f), (float)(fv.Gh - 1));
-    int j0 = (int)__builtin_floorf(gx);
-    int i0 = (int)__builtin_floorf(gy);
-    j0 = j0 > fv.Gw - 2 ? fv.Gw - 2 : j0;
-    i0 = i0 > fv.Gh - 2 ? fv.Gh - 2 : i0;
-    const float fx = gx - (float)j0;
-    const float fy = gy - (float)i0;
-    const float2* row0 = fv.F + (size_t)i0 * fv.Gw + j0;
-    const float2* row1 = row0 + fv.Gw;
-    const float2 a = row0[0], b = row0[1], c = row1[0], e = row1[1];
-    float2 out;
-    {
-        const float top = __builtin_fmaf(fx, b.x - a.x, a.x);
-        const float bot = __builtin_fmaf(fx, e.x - c.x, c.x);
-        out.x = __builtin_fmaf(fy, bot - top, top);
-    }
-    {
-        const float top = __builtin_fmaf(fx, b.y - a.y, a.y);
-        const float bot = __builtin_fmaf(fx, e.y - c.y, c.y);
-        out.y = __builtin_fmaf(fy, bot - top, top);
-    }
-    return out;
-}
-
-__device__ __forceinline__ FlowView flow_view(const synthpix_pair& P, const float* flow)
-{
-    FlowView fv;
-    fv.F = reinterpret_cast<const float2*>(flow + P.flow_offset);
-    fv.Gh = P.Gh;
-    fv.Gw = P.Gw;
-    fv.sx = (float)P.Gw / (float)P.W;
-    fv.sy = (float)P.Gh / (float)P.H;
-    return fv;
-}
-
 // One frozen-field substep sequence; the update order is fixed (see the
 // reference arithmetic): Euler p = fma(h, u, p); RK4 stages at fma(h/2, k, p)
 // and fma(h, k3, p), update p = fma(h, (((k1 + 2 k2) + 2 k3) + k4) / 6, p).
@@ -230,6 +185,21 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
             y2[base + 256 * q] = py[q];
         }
     }
+}
+
+// Moves a batch's pair table on to the next batch of the same shape: every
+// pair_id grows by `step` (the batch size), so replays draw fresh particles.
+__global__ void advance_pair_ids(synthpix_pair* __restrict__ pairs, int n_pairs, uint64_t step)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n_pairs) pairs[p].pair_id += step;
+}
+
+hipError_t launch_advance(synthpix_pair* pairs_dev, int n_pairs, uint64_t step, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_pair_ids, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, pairs_dev,
+                       n_pairs, step);
+    return hipGetLastError();
 }
 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,

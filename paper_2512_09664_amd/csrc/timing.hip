@@ -41,6 +41,8 @@ TimedScope::TimedScope(const char* name, hipStream_t s) : name_(name), stream_(s
 {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     start_ = take_event();
     if (start_ && hipEventRecord(start_, s) != hipSuccess) {
         g_pool.push_back(start_);

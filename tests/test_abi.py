@@ -76,7 +76,9 @@ def test_workspace_size_and_validation(L):
     fwd = n.value
     assert fwd > 0 and fwd % 256 == 0
     assert lib.synthpix_workspace_size(pairs, 2, ctypes.byref(_rp(L)), None, 1, ctypes.byref(n)) == 0
-    assert n.value > fwd
+    # the backward is particle-major: five floats per particle plus 64-bit flow sums, no bins
+    assert n.value >= 5 * 4 * (52429 + 6554) + 8 * 2 * 256 * 256   # both grids at flow_offset 0
+    assert n.value % 256 == 0
     bad = [dict(sheet_sigma=0.0), dict(d_max=0.0), dict(d_max=17.0), dict(blur_radius=4),
            dict(blur_radius=1, blur_sigma=0.0), dict(noise_sigma=-1.0), dict(bits=17)]
     for kw in bad:
@@ -148,3 +150,57 @@ def test_advect_and_render_validation(L):
     assert lib.synthpix_render_pair(two, fake, 2, None, fake, fake, fake, fake, fake, fake, fake,
                                     ctypes.byref(rp), fake, ctypes.c_void_p(0x10000), 1 << 30,
                                     None) == L.SP_ERR_INVALID_ARG
+
+
+def test_plan_validation(L):
+    lib = L.load()
+    pairs = _pairs(L, [(64, 64, 16, 16, 100)])
+    sp = L.SeedParams(0.02, 0.02, 0, 1.0, 5.0, 0.0, 0.0, 0.8, 1.0, -1.0, 1.0)
+    ap = L.AdvectParams(1.0, 1, 0)
+    rp = _rp(L)
+    fake = [0x1000 * (k + 1) for k in range(9)]
+    io = L.BatchIO(*fake)
+    h = ctypes.c_void_p()
+    args = (pairs, 1, ctypes.byref(sp), 0, ctypes.byref(ap), ctypes.byref(rp))
+    assert lib.synthpix_plan_create(*args, ctypes.byref(io), 0, 0, None, None) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_plan_create(*args, None, 0, 0, None, ctypes.byref(h)) == L.SP_ERR_INVALID_ARG
+    bad_io = L.BatchIO(*fake)
+    bad_io.flow = None
+    assert lib.synthpix_plan_create(*args, ctypes.byref(bad_io), 0, 0, None,
+                                    ctypes.byref(h)) == L.SP_ERR_INVALID_ARG
+    bad_rp = _rp(L)
+    bad_rp.bits = 17
+    assert lib.synthpix_plan_create(pairs, 1, ctypes.byref(sp), 0, ctypes.byref(ap), ctypes.byref(bad_rp),
+                                    ctypes.byref(io), 0, 0, None, ctypes.byref(h)) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_plan_create(pairs, 0, ctypes.byref(sp), 0, ctypes.byref(ap), ctypes.byref(rp),
+                                    ctypes.byref(io), 0, 0, None, ctypes.byref(h)) == L.SP_ERR_INVALID_ARG
+    assert not h.value
+    assert lib.synthpix_plan_launch(None, None) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_plan_tiling(None, None) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_plan_destroy(None) == L.SP_OK
+
+
+def test_backward_validation(L):
+    lib = L.load()
+    pairs = _pairs(L, [(64, 64, 16, 16, 100)])
+    fake = ctypes.c_void_p(0x1000)
+    rp = _rp(L)
+    n = ctypes.c_size_t()
+    assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(rp), None, 1, ctypes.byref(n)) == 0
+    # status + kmax + five per-particle float arrays + the fixed-point flow grid
+    assert n.value >= 5 * 4 * 100 + 8 * 2 * 16 * 16
+    args = [pairs, fake, 1, None, fake] + [fake] * 5
+
+    def call(rp_, ws=ctypes.c_void_p(0x100000), nbytes=1 << 30, grad=fake):
+        return lib.synthpix_render_pair_backward(*args, ctypes.byref(rp_), grad, fake, fake, fake, fake, fake,
+                                                 fake, fake, ws, nbytes, None)
+
+    rp.bits = 12
+    assert call(rp) == L.SP_ERR_UNSUPPORTED
+    rp.bits = 0
+    rp.advect.substeps = 0
+    assert call(rp) == L.SP_ERR_INVALID_ARG
+    rp.advect.substeps = 2
+    assert call(rp, grad=None) == L.SP_ERR_INVALID_ARG
+    assert call(rp, nbytes=n.value - 1) == L.SP_ERR_WORKSPACE
+    assert call(rp, ws=ctypes.c_void_p(0x100010)) == L.SP_ERR_WORKSPACE

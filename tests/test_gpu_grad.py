@@ -1,0 +1,198 @@
+"""GPU backward (``synthpix_render_pair_backward``) against the float64 oracle
+gradient and float64 central differences.
+
+Inputs (particles, flows, dL/dJ) are seeded host draws shared by both sides;
+the oracle's frame-2 positions are its own float64 advection.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import epilogue as oep
+from oracle import grad as ogr
+from oracle import ra32
+from workloads import get_workload, make_flows, particles
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2512_09664_amd as sp
+    import gpu_util as gu
+
+TOL = 1e-4   # of each quantity's largest magnitude
+
+
+def _batch(sizes, grids, n_per_pair, seed, zero_frac=0.15):
+    """Host particles and flows of a small uneven batch, plus its device copies."""
+    rng = np.random.default_rng(seed)
+    P = {k: [] for k in ("x", "y", "z", "d", "I0")}
+    flows = []
+    for p, ((H, W), (Gh, Gw)) in enumerate(zip(sizes, grids)):
+        q = particles.random_particles(seed * 100 + p, n_per_pair, H, W, d_range=(1.0, 4.5), pad=3.0,
+                                       zero_frac=zero_frac)
+        for k in P:
+            P[k].append(q[k])
+        flows.append(rng.normal(0.0, 1.2, size=(Gh, Gw, 2)).astype(np.float32))
+    batch = gu.batch_for(sizes, grids, [n_per_pair] * len(sizes))
+    dev = {k: gu.to_dev(np.concatenate(v)) for k, v in P.items()}
+    flow_dev = gu.to_dev(np.concatenate([f.reshape(-1) for f in flows]))
+    return P, flows, batch, dev, flow_dev
+
+
+def _grad_images(batch, seed):
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(batch.n_pixels).astype(np.float32)
+    return g, gu.to_dev(g)
+
+
+def _oracle_pair(P, p, flows, H, W, gJ, off, rp, blur):
+    w = oep.blur_weights(blur, rp.blur_sigma) if blur else None
+    integ = "rk4" if rp.advect.integrator == 1 else "euler"
+    return ogr.backward_pair(P["x"][p], P["y"][p], P["z"][p], P["d"][p], P["I0"][p], float(np.float32(rp.sheet_sigma)),
+                             flows[p], H, W, gJ[off:off + 2 * H * W].reshape(2, H, W), dt=rp.advect.dt,
+                             substeps=rp.advect.substeps, integrator=integ, w_blur=w, cutoff=True)
+
+
+def _close(got, ref, what, tol=TOL):
+    scale = float(np.max(np.abs(ref))) if np.size(ref) else 0.0
+    err = float(np.max(np.abs(np.asarray(got, np.float64) - ref))) if np.size(ref) else 0.0
+    assert err <= tol * scale + 1e-30, f"{what}: max error {err:.3e} vs scale {scale:.3e}"
+
+
+CASES = [("euler", 1, 0, 0.5), ("rk4", 2, 1, 0.5), ("rk4", 4, 2, 0.8), ("euler", 3, 3, 0.45)]
+
+
+@pytest.mark.parametrize("integ,n_sub,blur,sheet", CASES)
+def test_backward_matches_oracle_gradient(integ, n_sub, blur, sheet):
+    sizes = [(16, 16), (24, 20), (40, 48), (33, 17)]
+    grids = [(6, 6), (8, 7), (10, 12), (9, 5)]
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, 14, 3 + n_sub + 10 * blur)
+    rp = sp.render_params(sheet, 5.0, blur, 0.8, 0.0, 0, 0, 1.0, n_sub, integ)
+    gJ, gJ_dev = _grad_images(batch, 99 + blur)
+    ws = sp.alloc_workspace(batch, rp, backward=True)
+    g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                                workspace=ws)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    G = {k: gu.to_np(v) for k, v in g.items()}
+    fo = 0
+    for p, (H, W) in enumerate(sizes):
+        ref = _oracle_pair(P, p, flows, H, W, gJ, batch.host[p].image_offset, rp, blur)
+        sl = slice(batch.host[p].particle_offset, batch.host[p].particle_offset + 14)
+        for key in ("x1", "y1", "z", "d", "I0"):
+            _close(G[key][sl], ref[key], f"pair {p} {key}")
+        n_f = flows[p].size
+        _close(G["flow"][fo:fo + n_f].reshape(flows[p].shape), ref["flow"], f"pair {p} flow")
+        fo += n_f
+        term_scale = np.sum(np.abs(ref["z"] * P["z"][p])) / np.float32(rp.sheet_sigma)
+        assert abs(G["sheet"][p] - ref["s"]) <= TOL * term_scale + 1e-30, (p, G["sheet"][p], ref["s"])
+        # masked particles get exactly zero
+        dead = P["I0"][p] == 0
+        for key in ("x1", "y1", "z", "d", "I0"):
+            assert np.all(G[key][sl][dead] == 0.0)
+
+
+def test_backward_matches_central_differences():
+    """16x16 pair: every per-particle gradient, the sheet width and a set of flow
+    nodes against float64 central differences (h = 1e-4) of the smooth forward."""
+    H = W = 16
+    P, flows, batch, dev, flow_dev = _batch([(H, W)], [(6, 6)], 6, 41, zero_frac=0.0)
+    rp = sp.render_params(0.6, 5.0, 1, 0.7, 0.0, 0, 0, 1.0, 2, "rk4")
+    gJ, gJ_dev = _grad_images(batch, 5)
+    g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev)
+    G = {k: gu.to_np(v) for k, v in g.items()}
+    w = oep.blur_weights(1, rp.blur_sigma)
+    s = float(np.float32(rp.sheet_sigma))
+    base = {k: P[k][0].astype(np.float64) for k in P}
+    flow = flows[0].astype(np.float64)
+    target = gJ.astype(np.float64).reshape(2, H, W)
+
+    def L(x=base["x"], y=base["y"], z=base["z"], d=base["d"], I0=base["I0"], s=s, flow=flow):
+        J = ogr.forward_pair(x, y, z, d, I0, s, flow, H, W, dt=1.0, substeps=2, integrator="rk4", w_blur=w,
+                             cutoff=False)
+        return float(np.sum(J * target))
+
+    h = 1e-4
+
+    def fd(name, arr, idx):
+        a = arr.copy()
+        a[idx] += h
+        lp = L(**{name: a})
+        a[idx] -= 2 * h
+        lm = L(**{name: a})
+        return (lp - lm) / (2 * h)
+
+    for name, key in (("x", "x1"), ("y", "y1"), ("z", "z"), ("d", "d"), ("I0", "I0")):
+        num = np.array([fd(name, base[name], i) for i in range(6)])
+        _close(G[key], num, key, tol=1e-3)
+    num_s = (L(s=s + h) - L(s=s - h)) / (2 * h)
+    assert abs(G["sheet"][0] - num_s) <= 1e-3 * abs(num_s)
+    rng = np.random.default_rng(0)
+    nodes = [tuple(rng.integers(0, n) for n in flow.shape) for _ in range(24)]
+    num_f = np.array([fd("flow", flow, idx) for idx in nodes])
+    got_f = np.array([G["flow"].reshape(flow.shape)[idx] for idx in nodes])
+    full_scale = np.max(np.abs(G["flow"]))
+    assert full_scale > 0
+    assert np.max(np.abs(got_f - num_f)) <= 1e-3 * full_scale
+
+
+def test_backward_is_deterministic_and_autograd_agrees():
+    sizes = [(40, 48), (24, 20)]
+    P, flows, batch, dev, flow_dev = _batch(sizes, [(10, 12), (8, 7)], 30, 7)
+    rp = sp.render_params(0.5, 5.0, 1, 0.7, 0.0, 0, 0, 1.0, 4, "rk4")
+    gJ, gJ_dev = _grad_images(batch, 11)
+    runs = [sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev)
+            for _ in range(2)]
+    torch.cuda.synchronize()
+    for k in runs[0]:
+        assert torch.equal(runs[0][k], runs[1][k]), k
+    inp = {k: v.clone().requires_grad_(True) for k, v in dev.items()}
+    fl = flow_dev.clone().requires_grad_(True)
+    sheet = torch.tensor(0.5, device=gu.DEV, requires_grad=True)
+    img = sp.render_images(batch, fl, inp["x"], inp["y"], inp["z"], inp["d"], inp["I0"], sheet, rp)
+    ref_img = sp.render_pair(batch, dev["x"], dev["y"], *sp.advect(batch, flow_dev, rp.advect, dev["x"], dev["y"]),
+                             dev["z"], dev["d"], dev["I0"], rp)
+    assert torch.equal(img.detach(), ref_img)
+    (img * gJ_dev).sum().backward()
+    g = runs[0]
+    for name, key in (("x", "x1"), ("y", "y1"), ("z", "z"), ("d", "d"), ("I0", "I0")):
+        assert torch.equal(inp[name].grad, g[key]), key
+    assert torch.equal(fl.grad, g["flow"])
+    assert torch.allclose(sheet.grad, g["sheet"].sum())
+
+
+def test_backward_full_size_pairs(ra):
+    """grad_512 at full size (64 pairs of 512x512, RK4 x4, 3x3 blur): every
+    gradient of two sampled pairs against the oracle."""
+    wl = get_workload("grad_512")
+    flows = make_flows(wl.flow, wl.seed, wl.sizes, wl.grid_div, wl.max_disp, wl.dt, wl.uniform_uv)
+    n_max = [sp.particle_count(H, W, wl.ppp[1]) for (H, W) in wl.sizes]
+    batch = gu.batch_for(wl.sizes, [f.shape[:2] for f in flows], n_max)
+    P = {k: [] for k in ("x", "y", "z", "d", "I0")}
+    for p, (H, W) in enumerate(wl.sizes):
+        q = ra.seed_pair(H, W, n_max[p], wl.ppp, p, wl.seed, wl.d_dist, wl.d_params, wl.I0, wl.z)
+        for k in P:
+            P[k].append(q[k])
+    dev = {k: gu.to_dev(np.concatenate(v)) for k, v in P.items()}
+    flow_dev = gu.to_dev(np.concatenate([f.reshape(-1) for f in flows]))
+    rp = sp.render_params(wl.sheet_sigma, wl.d_max, wl.blur_radius, wl.blur_sigma, 0.0, 0, wl.seed, wl.dt,
+                          wl.substeps, wl.integrator)
+    gJ, gJ_dev = _grad_images(batch, 2024)
+    ws = sp.alloc_workspace(batch, rp, backward=True)
+    g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                                workspace=ws)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    G = {k: gu.to_np(v) for k, v in g.items()}
+    for p in (0, 37):
+        H, W = wl.sizes[p]
+        ref = _oracle_pair(P, p, flows, H, W, gJ, batch.host[p].image_offset, rp, wl.blur_radius)
+        po = batch.host[p].particle_offset
+        sl = slice(po, po + n_max[p])
+        for key in ("x1", "y1", "z", "d", "I0"):
+            _close(G[key][sl], ref[key], f"pair {p} {key}")
+        fo = batch.host[p].flow_offset
+        _close(G["flow"][fo:fo + flows[p].size].reshape(flows[p].shape), ref["flow"], f"pair {p} flow")
+        term_scale = np.sum(np.abs(ref["z"] * P["z"][p])) / np.float32(rp.sheet_sigma)
+        assert abs(G["sheet"][p] - ref["s"]) <= TOL * term_scale

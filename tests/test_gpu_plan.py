@@ -1,0 +1,100 @@
+"""Captured batch plans on the GPU: a plan's graph replay gives exactly what the
+eager calls give, the autotuner only changes speed, and pair-id advance draws
+the next batch of pairs."""
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import get_workload
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2512_09664_amd as sp
+    from gpu_util import DEV, batch_for, params_of, to_np, workload_inputs
+
+# uneven pair sizes, a ragged mix with odd edges
+SIZES = ((64, 96), (128, 128), (33, 200), (256, 64), (97, 31), (160, 144), (48, 48), (200, 120))
+
+
+def _workload(bits=12, noise=0.01):
+    return get_workload("uneven_256").with_(sizes=SIZES, bits=bits, noise_sigma=noise, blur_radius=1,
+                                            integrator="rk4", substeps=2, flow="lamb_oseen")
+
+
+def _io(batch, flow_dev, bits):
+    n = batch.n_particles
+    io = {k: torch.empty(n, dtype=torch.float32, device=DEV) for k in ("x1", "y1", "x2", "y2", "z", "d", "I0")}
+    io["flow"] = flow_dev
+    io["images"] = torch.empty(batch.n_pixels, dtype=sp.api.U16 if bits else torch.float32, device=DEV)
+    io["n_active"] = torch.empty(batch.n_pairs, dtype=torch.int32, device=DEV)
+    io["ppp"] = torch.empty(batch.n_pairs, dtype=torch.float64, device=DEV)
+    return io
+
+
+def _eager(batch, flow_dev, sprm, aprm, rprm, seed, tile=None):
+    P = sp.seed(batch, sprm, seed)
+    x2, y2 = sp.advect(batch, flow_dev, aprm, P["x"], P["y"])
+    img = sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, tile)
+    torch.cuda.synchronize()
+    return P, x2, y2, img
+
+
+def _same(a, b):
+    return np.array_equal(to_np(a), to_np(b))
+
+
+@pytest.mark.parametrize("bits,noise", [(12, 0.01), (0, 0.0)])
+def test_plan_replays_match_eager(bits, noise):
+    wl = _workload(bits, noise)
+    flows, batch, flow_dev = workload_inputs(wl)
+    sprm, aprm, rprm = params_of(wl)
+    P, x2, y2, img = _eager(batch, flow_dev, sprm, aprm, rprm, wl.seed)
+    io = _io(batch, flow_dev, bits)
+    plan = sp.Plan(batch, sprm, wl.seed, aprm, rprm, io)
+    for r in range(3):
+        io["images"].zero_()
+        io["x2"].fill_(-7.0)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert _same(io["images"], img), f"replay {r}"
+        assert _same(io["x1"], P["x"]) and _same(io["x2"], x2) and _same(io["y2"], y2)
+        assert _same(io["n_active"], P["n_active"])
+        # unrelated eager work between replays
+        _ = (io["x1"] * 2).sum().item()
+    plan.close()
+
+
+def test_autotuned_plan_is_bitwise_identical():
+    wl = _workload()
+    flows, batch, flow_dev = workload_inputs(wl)
+    sprm, aprm, rprm = params_of(wl)
+    _, _, _, img = _eager(batch, flow_dev, sprm, aprm, rprm, wl.seed)
+    io = _io(batch, flow_dev, wl.bits)
+    plan = sp.Plan(batch, sprm, wl.seed, aprm, rprm, io, autotune=True)
+    t = plan.tiling
+    assert t.tile_w in (32, 64, 128) and t.tile_h in (16, 32, 64) and t.cap in (32, 64, 128)
+    for _ in range(2):
+        io["images"].zero_()
+        plan.launch()
+        torch.cuda.synchronize()
+        assert _same(io["images"], img)
+    plan.close()
+
+
+def test_plan_advances_pair_ids():
+    wl = _workload()
+    flows, batch, flow_dev = workload_inputs(wl)
+    sprm, aprm, rprm = params_of(wl)
+    n = batch.n_pairs
+    io = _io(batch, flow_dev, wl.bits)
+    plan = sp.Plan(batch, sprm, wl.seed, aprm, rprm, io, advance_pair_ids=True)
+    for k in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        ids = [k * n + p for p in range(n)]
+        bk = batch_for(wl.sizes, [f.shape[:2] for f in flows], batch.n_max, ids)
+        _, _, _, img = _eager(bk, flow_dev, sprm, aprm, rprm, wl.seed)
+        assert _same(io["images"], img), f"launch {k}"
+    plan.close()

@@ -47,6 +47,130 @@ def describe(wl):
             "blur_sigma": wl.blur_sigma, "noise_sigma": wl.noise_sigma, "bits": wl.bits}
 
 
+def _inputs(sp, torch, np, dev, wl):
+    from workloads import make_flows
+    flows = make_flows(wl.flow, wl.seed, wl.sizes, wl.grid_div, wl.max_disp, wl.dt, wl.uniform_uv)
+    n_max = [sp.particle_count(H, W, wl.ppp[1]) for (H, W) in wl.sizes]
+    batch = sp.PairBatch.build(wl.sizes, [f.shape[:2] for f in flows], n_max, device=dev)
+    flow = torch.from_numpy(np.concatenate([f.reshape(-1) for f in flows])).to(dev)
+    sprm = sp.seed_params(wl.ppp, wl.d_dist, wl.d_params, wl.I0, wl.z)
+    aprm = sp.advect_params(wl.dt, wl.substeps, wl.integrator)
+    rprm = sp.render_params(wl.sheet_sigma, wl.d_max, wl.blur_radius, wl.blur_sigma, wl.noise_sigma, wl.bits,
+                            wl.seed, wl.dt, wl.substeps, wl.integrator)
+    return flows, n_max, batch, flow, sprm, aprm, rprm
+
+
+def _plan_io(sp, torch, batch, flow, bits, dev):
+    n = max(batch.n_particles, 1)
+    io = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in ("x1", "y1", "x2", "y2", "z", "d", "I0")}
+    io["flow"] = flow
+    io["images"] = torch.empty(batch.n_pixels, dtype=sp.api.U16 if bits else torch.float32, device=dev)
+    return io
+
+
+def _time_plan(torch, plan, steps):
+    plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def plan_throughput(sp, torch, np, dev, wl, flows, flow, batch, sprm, aprm, rprm, steps=20):
+    """The same workload as one autotuned, graph-captured plan (fresh pair ids every launch)."""
+    io = _plan_io(sp, torch, batch, flow, wl.bits, dev)
+    plan = sp.Plan(batch, sprm, wl.seed, aprm, rprm, io, autotune=True, advance_pair_ids=True)
+    t = plan.tiling
+    dt = _time_plan(torch, plan, steps)
+    plan.close()
+    return {"pairs_per_s": round(wl.n_pairs / dt, 1), "ms_per_step": round(1000 * dt, 4),
+            "tiling": [t.tile_w, t.tile_h, t.chunk, t.cap]}
+
+
+def uneven_batched_vs_per_pair(sp, torch, np, dev, steps=5):
+    """256 uneven pairs (256^2 .. 2048^2, ppp U[0.005, 0.1]): one graph-captured
+    batch vs one launch sequence per pair."""
+    from workloads import get_workload
+    wl = get_workload("uneven_256")
+    flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
+    io = _plan_io(sp, torch, batch, flow, wl.bits, dev)
+    plan = sp.Plan(batch, sprm, wl.seed, aprm, rprm, io, autotune=True, advance_pair_ids=True)
+    t_batched = _time_plan(torch, plan, steps)
+    plan.close()
+    singles = []
+    for p in range(wl.n_pairs):
+        H, W = wl.sizes[p]
+        hp = batch.host[p]
+        b1 = sp.PairBatch.build([wl.sizes[p]], [flows[p].shape[:2]], [n_max[p]], [p], device=dev)
+        sl = slice(hp.particle_offset, hp.particle_offset + n_max[p])
+        P1 = {"x": io["x1"][sl], "y": io["y1"][sl], "z": io["z"][sl], "d": io["d"][sl], "I0": io["I0"][sl],
+              "n_active": torch.empty(1, dtype=torch.int32, device=dev),
+              "ppp": torch.empty(1, dtype=torch.float64, device=dev)}
+        singles.append((b1, flow[hp.flow_offset:hp.flow_offset + flows[p].size], P1, io["x2"][sl], io["y2"][sl],
+                        io["images"][hp.image_offset:hp.image_offset + 2 * H * W],
+                        sp.alloc_workspace(b1, rprm)))
+
+    def per_pair_step(k):
+        for b1, fl1, P1, x21, y21, im1, ws1 in singles:
+            sp.seed(b1, sprm, wl.seed + k, out=P1)
+            sp.advect(b1, fl1, aprm, P1["x"], P1["y"], x21, y21)
+            sp.render_pair(b1, P1["x"], P1["y"], x21, y21, P1["z"], P1["d"], P1["I0"], rprm, None, im1, ws1)
+
+    per_pair_step(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        per_pair_step(k + 1)
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / steps
+    out = {"pairs": wl.n_pairs, "gpx_per_step": round(wl.pixels() / 1e9, 4),
+           "batched_pairs_per_s": round(wl.n_pairs / t_batched, 1),
+           "per_pair_pairs_per_s": round(wl.n_pairs / t_single, 1),
+           "batched_vs_per_pair": round(t_single / t_batched, 3)}
+    del singles, io, plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def gradient_cost(sp, torch, np, dev, steps=10):
+    """grad_512 (64 pairs of 512^2, RK4 x4, 3x3 blur, float images): advect +
+    render forward vs the backward from dL/dJ."""
+    from workloads import get_workload
+    wl = get_workload("grad_512")
+    flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
+    P = sp.seed(batch, sprm, wl.seed)
+    x2 = torch.empty_like(P["x"])
+    y2 = torch.empty_like(P["y"])
+    img = torch.empty(batch.n_pixels, dtype=torch.float32, device=dev)
+    gJ = torch.randn(batch.n_pixels, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+    wsf = sp.alloc_workspace(batch, rprm)
+    wsb = sp.alloc_workspace(batch, rprm, backward=True)
+
+    def fwd():
+        sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2)
+        sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, img, wsf)
+
+    def bwd():
+        sp.render_pair_backward(batch, flow, P["x"], P["y"], P["z"], P["d"], P["I0"], rprm, gJ, None, wsb)
+
+    fwd()
+    bwd()
+    torch.cuda.synchronize()
+    res = {}
+    for name, fn in (("fwd", fwd), ("bwd", bwd)):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / steps
+    del wsb, wsf, gJ, img
+    torch.cuda.empty_cache()
+    return {"fwd_ms": round(1000 * res["fwd"], 4), "bwd_ms": round(1000 * res["bwd"], 4),
+            "fwd_bwd_over_fwd": round((res["fwd"] + res["bwd"]) / res["fwd"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +180,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3, help="steps of the per-pair-launch comparison")
     ap.add_argument("--cpu-sample-pairs", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the uneven-batch (graph plan vs per-pair launches) and gradient measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="also run a plain device copy of MB megabytes (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -180,6 +306,17 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 copies of {nbytes} bytes")
 
+    extras = {}
+    if not args.no_extras:
+        extras["graph_plan"] = plan_throughput(sp, torch, np, dev, wl, flows, flow, batch, sprm, aprm, rprm)
+        log(f"[bench] graph plan on {wl.name}: {extras['graph_plan']}")
+        del images, ws, P, x2, y2
+        torch.cuda.empty_cache()
+        extras["uneven_256"] = uneven_batched_vs_per_pair(sp, torch, np, dev)
+        log(f"[bench] uneven_256: {extras['uneven_256']}")
+        extras["grad_512"] = gradient_cost(sp, torch, np, dev)
+        log(f"[bench] grad_512: {extras['grad_512']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import pipeline as opipe
@@ -200,7 +337,7 @@ def main():
             "data": "synthetic", "config": describe(wl), "gpx_per_s": round(gpx_per_s, 2),
             "step_hbm_frac": round(step_hbm_frac, 4), "kernels_us": {k: round(v["avg_us"], 2) for k, v in
                                                                       kernels.items()},
-            "plain": plain, "roofline": roofline, "cpu_baseline": cpu}
+            "plain": plain, **extras, "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
 

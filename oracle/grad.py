@@ -174,14 +174,23 @@ def advect_adjoint(flow, H, W, x1, y1, gx2, gy2, dt=1.0, substeps=1, integrator=
 # ----------------------------------------------------------------------------- full backward
 
 def backward_pair(x1, y1, z, d, I0, s, flow, H, W, gJ, dt=1.0, substeps=1,
-                  integrator="euler", w_blur=None, cutoff=False):
-    """dL/d{x1, y1, z, d, I0, s, flow} given dL/dJ [2, H, W] for one pair."""
+                  integrator="euler", w_blur=None, cutoff=False, frame2=None):
+    """dL/d{x1, y1, z, d, I0, s, flow} given dL/dJ [2, H, W] for one pair.
+
+    ``frame2`` optionally gives the frame-2 positions (x2, y2) the render adjoint
+    is evaluated at (default: this module's float64 advection of (x1, y1)); the
+    flow adjoint always follows the float64 trajectory.  It lets a comparison
+    with a binary32 implementation separate position rounding from the
+    gradient arithmetic."""
     x1 = np.asarray(x1, dtype=np.float64)
     y1 = np.asarray(y1, dtype=np.float64)
     z = np.asarray(z, dtype=np.float64)
     d = np.asarray(d, dtype=np.float64)
     I0 = np.asarray(I0, dtype=np.float64)
     x2, y2 = adv.advect(flow, H, W, x1, y1, dt, substeps, integrator)
+    if frame2 is not None:
+        x2 = np.asarray(frame2[0], dtype=np.float64)
+        y2 = np.asarray(frame2[1], dtype=np.float64)
     Sz = rd.sheet_factor(z, s)
     A = I0 * Sz
     g = {k: np.zeros_like(x1) for k in ("x1", "y1", "z", "d", "I0")}

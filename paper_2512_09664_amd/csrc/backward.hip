@@ -344,12 +344,12 @@ __device__ __forceinline__ void substep_adjoint(const FlowView& fv, NodeRun<SCAT
     gpy += ((b1y + b2y) + b3y) + b4y;
 }
 
-constexpr int CKPT = 32;
-
 // SCATTER = false: the sweep's largest upstream value (into kmax_bits) and the
 // final position gradient (added to g_x1, g_y1).  SCATTER = true: the same
 // sweep again, node sums into the fixed-point grid.
-template <bool SCATTER>
+// CK checkpoints of the trajectory are kept, one every L = ceil(substeps / CK)
+// substeps; each segment is recomputed into SK >= L slots during the sweep.
+template <bool SCATTER, int CK, int SK>
 __global__ void __launch_bounds__(256)
 bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap, int en)
 {
@@ -388,9 +388,9 @@ bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap, int en)
         const int S = ap.substeps;
         const float h = ap.dt / (float)S;
         const float hh = h * 0.5f;
-        const int L = (S + CKPT - 1) / CKPT;
+        const int L = (S + CK - 1) / CK;
         const int nseg = (S + L - 1) / L;
-        float cpx[CKPT], cpy[CKPT];
+        float cpx[CK], cpy[CK];
         float qx = px, qy = py;
         for (int s = 0; s < S; ++s) {
             if (s % L == 0) {
@@ -399,7 +399,7 @@ bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap, int en)
             }
             if (s + 1 < S) substep(fv, qx, qy, h, hh, ap.integrator);
         }
-        float spx[CKPT], spy[CKPT];
+        float spx[SK], spy[SK];
         for (int seg = nseg - 1; seg >= 0; --seg) {
             const int s0 = seg * L;
             const int len = (S - s0) < L ? (S - s0) : L;
@@ -484,6 +484,22 @@ bwd_sheet(const synthpix_pair* __restrict__ pairs, const float* __restrict__ she
     if (threadIdx.x == 0) g_sheet[blockIdx.x] = (float)red[0];
 }
 
+template <bool SCATTER>
+void launch_advect_adjoint(const BwdArgs& a, int64_t n_span, const synthpix_advect_params& ap, int en, unsigned blocks,
+                           hipStream_t s)
+{
+    const int S = ap.substeps;
+#define SP_ADJ(CK, SK) hipLaunchKernelGGL((bwd_advect<SCATTER, CK, SK>), dim3(blocks), dim3(256), 0, s, a, n_span, ap, en)
+    if (S <= 1) SP_ADJ(1, 1);
+    else if (S <= 2) SP_ADJ(2, 1);
+    else if (S <= 4) SP_ADJ(4, 1);
+    else if (S <= 8) SP_ADJ(8, 1);
+    else if (S <= 16) SP_ADJ(16, 1);
+    else if (S <= 32) SP_ADJ(32, 1);
+    else SP_ADJ(32, 32);       // substeps <= 1024 = 32 * 32
+#undef SP_ADJ
+}
+
 hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, const synthpix_advect_params& ap,
                            int blur, int en, hipStream_t s)
 {
@@ -509,11 +525,11 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         const unsigned ab = (unsigned)((n_span + 255) / 256);
         {
             TimedScope ts("bwd_advect_max", s);
-            hipLaunchKernelGGL(bwd_advect<false>, dim3(ab), dim3(256), 0, s, a, n_span, ap, en);
+            launch_advect_adjoint<false>(a, n_span, ap, en, ab, s);
         }
         {
             TimedScope ts("bwd_advect_scatter", s);
-            hipLaunchKernelGGL(bwd_advect<true>, dim3(ab), dim3(256), 0, s, a, n_span, ap, en);
+            launch_advect_adjoint<true>(a, n_span, ap, en, ab, s);
         }
     }
     {

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import advect as oadv
 from oracle import epilogue as oep
 from oracle import grad as ogr
 from workloads import get_workload, make_flows, particles
@@ -52,6 +53,52 @@ def _oracle_pair(P, p, flows, H, W, gJ, off, rp, blur, frame2=None):
     return ogr.backward_pair(P["x"][p], P["y"][p], P["z"][p], P["d"][p], P["I0"][p], float(np.float32(rp.sheet_sigma)),
                              flows[p], H, W, gJ[off:off + 2 * H * W].reshape(2, H, W), dt=rp.advect.dt,
                              substeps=rp.advect.substeps, integrator=integ, w_blur=w, cutoff=True, frame2=frame2)
+
+
+def _kinks(flow, H, W, x1, y1, dt, substeps, integrator, eps=2e-4):
+    """Particles whose float64 trajectory has a bilinear sample within ``eps``
+    grid units (several times the binary32 trajectory's rounding) of a cell
+    edge or of the clamp boundary.  The velocity's
+    derivative jumps there, so either one-sided derivative is a correct
+    gradient and binary32 and float64 trajectories may take different sides.
+    Returns the per-particle flag and a mask of the grid nodes those
+    particles' samples touch."""
+    Gh, Gw = flow.shape[:2]
+    px = np.asarray(x1, np.float64)
+    py = np.asarray(y1, np.float64)
+    h = dt / substeps
+    stages = []
+    for _ in range(substeps):
+        if integrator == "euler":
+            stages.append((px, py))
+            u, v = oadv.sample(flow, H, W, px, py)
+            px, py = px + h * u, py + h * v
+            continue
+        k1 = oadv.sample(flow, H, W, px, py)
+        p2 = (px + 0.5 * h * k1[0], py + 0.5 * h * k1[1])
+        k2 = oadv.sample(flow, H, W, *p2)
+        p3 = (px + 0.5 * h * k2[0], py + 0.5 * h * k2[1])
+        k3 = oadv.sample(flow, H, W, *p3)
+        p4 = (px + h * k3[0], py + h * k3[1])
+        k4 = oadv.sample(flow, H, W, *p4)
+        stages += [(px, py), p2, p3, p4]
+        px = px + h * (k1[0] + 2 * k2[0] + 2 * k3[0] + k4[0]) / 6.0
+        py = py + h * (k1[1] + 2 * k2[1] + 2 * k3[1] + k4[1]) / 6.0
+    flag = np.zeros(len(px), dtype=bool)
+    cells = []
+    for sx, sy in stages:
+        gx = sx * (Gw / W) - 0.5
+        gy = sy * (Gh / H) - 0.5
+        flag |= (np.abs(gx - np.rint(gx)) < eps) | (np.abs(gy - np.rint(gy)) < eps)
+        j0 = np.minimum(np.floor(np.clip(gx, 0, Gw - 1)).astype(int), Gw - 2)
+        i0 = np.minimum(np.floor(np.clip(gy, 0, Gh - 1)).astype(int), Gh - 2)
+        cells.append((i0, j0))
+    nodes = np.zeros((Gh, Gw), dtype=bool)
+    for i0, j0 in cells:
+        for di in (0, 1):
+            for dj in (0, 1):
+                nodes[i0[flag] + di, j0[flag] + dj] = True
+    return flag, nodes
 
 
 def _close(got, ref, what, tol=TOL):
@@ -196,10 +243,21 @@ def test_backward_full_size_pairs(ra):
         ref64 = _oracle_pair(P, p, flows, H, W, gJ, batch.host[p].image_offset, rp, wl.blur_radius)
         po = batch.host[p].particle_offset
         sl = slice(po, po + n_max[p])
-        for key in ("x1", "y1", "z", "d", "I0"):
+        kink, kink_nodes = _kinks(flows[p], H, W, P["x"][p], P["y"][p], wl.dt, wl.substeps, wl.integrator)
+        assert kink.sum() < 0.05 * len(kink)
+        for key in ("z", "d", "I0"):
             _close(G[key][sl], ref[key], f"pair {p} {key}")
             _close(G[key][sl], ref64[key], f"pair {p} {key} (float64 trajectory)", tol=2e-3)
+        for key in ("x1", "y1"):
+            # exact where the trajectory's velocity is differentiable; at a kink
+            # the two one-sided derivatives differ by O(h) of the flow's jump
+            scale = np.max(np.abs(ref[key]))
+            _close(G[key][sl][~kink], ref[key][~kink], f"pair {p} {key}")
+            assert np.max(np.abs(G[key][sl] - ref[key])) <= 5e-3 * scale, key
         fo = batch.host[p].flow_offset
-        _close(G["flow"][fo:fo + flows[p].size].reshape(flows[p].shape), ref["flow"], f"pair {p} flow")
+        gf = G["flow"][fo:fo + flows[p].size].reshape(flows[p].shape)
+        scale = np.max(np.abs(ref["flow"]))
+        assert np.max(np.abs(gf - ref["flow"])[~kink_nodes]) <= TOL * scale, f"pair {p} flow"
+        assert np.max(np.abs(gf - ref["flow"])) <= 5e-3 * scale, f"pair {p} flow near kinks"
         term_scale = np.sum(np.abs(ref["z"] * P["z"][p])) / np.float32(rp.sheet_sigma)
         assert abs(G["sheet"][p] - ref["s"]) <= TOL * term_scale

@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 METRIC = "image pairs/s & Gpx/s at 1024²,0.05 ppp; % HBM roofline; batched vs plain"
 HBM_PEAK_GBS = 8000.0
 RENDER_SRC = os.path.join(ROOT, "paper_2512_09664_amd", "csrc", "bin_render.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_tile_scale_1024_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_tile_scale_1024_traffic.txt")
 
 
 def log(*a):
@@ -258,9 +258,9 @@ def main():
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
+            tr = dict(ln.strip().split("=", 1) for ln in f if "=" in ln and not ln.startswith("#"))
         if tr.get("source_sha") == source_sha(RENDER_SRC) and tr.get("workload") == wl.name:
-            traffic = tr.get("bytes_per_launch")
+            traffic = int(tr["bytes_per_launch"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
 

@@ -189,7 +189,7 @@ int64_t flow_span(const synthpix_pair* ph, int32_t n_pairs)
 
 // Backward workspace: particle-major, no bins.
 struct BwdLayout {
-    size_t status, kmax, x2, y2, gx2, gy2, sheet, fixed, total;
+    size_t status, scale, x2, y2, gx2, gy2, sheet, fixed, total;
 };
 
 BwdLayout bwd_layout(int64_t n_span, int64_t n_flow)
@@ -198,7 +198,7 @@ BwdLayout bwd_layout(int64_t n_span, int64_t n_flow)
     size_t o = 0;
     const size_t nf = sizeof(float) * (size_t)n_span;
     w.status = o; o = align256(o + 16);
-    w.kmax = o; o = align256(o + 4);
+    w.scale = o; o = align256(o + 16);
     w.x2 = o; o = align256(o + nf);
     w.y2 = o; o = align256(o + nf);
     w.gx2 = o; o = align256(o + nf);
@@ -491,7 +491,7 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.gy2 = reinterpret_cast<float*>(ws + wl.gy2);
     a.sheet = reinterpret_cast<float*>(ws + wl.sheet);
     a.fixed = reinterpret_cast<unsigned long long*>(ws + wl.fixed);
-    a.kmax_bits = reinterpret_cast<uint32_t*>(ws + wl.kmax);
+    a.scale = reinterpret_cast<uint32_t*>(ws + wl.scale);
     a.status = reinterpret_cast<uint32_t*>(ws + wl.status);
     a.sheet_sigma = rp->sheet_sigma;
     a.d_max = rp->d_max;

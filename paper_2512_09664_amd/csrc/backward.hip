@@ -14,12 +14,13 @@
 // tiles.
 //
 // Flow adjoint: a reverse sweep through the recomputed Euler / RK4 substeps
-// (checkpointed every ceil(substeps / 32) substeps).  Each bilinear sample
-// passes its upstream gradient to its four grid nodes; consecutive samples in
-// one cell are merged per particle, and node sums are accumulated in 64-bit
-// fixed point, so the result does not depend on the order of the additions.
-// The fixed-point scale is a power of two set from the largest upstream value
-// (found by a first sweep) and the sample count, so no sum can overflow.
+// (checkpointed).  Each bilinear sample passes its upstream gradient to its
+// four grid nodes; consecutive samples in one cell are merged per particle,
+// and node sums are accumulated in 64-bit fixed point, so the result does not
+// depend on the order of the additions.  The fixed-point scale is a power of
+// two from an a-priori bound on every upstream value (largest dL/dx2 and the
+// flow's Lipschitz constant through the stage recurrences) and the sample
+// count, so no sum can leave the int64 range.
 #include "device_math.hpp"
 #include "flow.hpp"
 #include "launch.hpp"
@@ -28,8 +29,10 @@ namespace sp {
 
 constexpr int BG = 16;             // lanes per particle in the gather
 constexpr int BPW = 256 / BG;      // particles per workgroup
-constexpr int BT = 64;             // table slots: support (<= 3 d_max + 2) + 4 b zero padding
+constexpr int GROWS = 8;           // patch rows loaded per batch (independent loads in flight)
 
+// BT table slots cover the support (<= 3 d_max + 2 pixels) plus 4 b of zero padding.
+template <int BT>
 struct GatherLds {
     float rx[BPW][3][BT];          // raw column factors gx dx^k, k = 0, 1, 2 (slot = c - c0 + 2b)
     float ry[BPW][3][BT];
@@ -44,11 +47,11 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-template <int B>
+template <int B, int BT>
 __global__ void __launch_bounds__(256)
 bwd_gather(BwdArgs a, int64_t n_span)
 {
-    __shared__ GatherLds S;
+    __shared__ GatherLds<BT> S;
     const int grp = threadIdx.x / BG, lane = threadIdx.x % BG;
     const int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * BPW + grp;
 
@@ -161,15 +164,27 @@ bwd_gather(BwdArgs a, int64_t n_span)
             for (int t = tlo + lane; t < thi; t += BG) {
                 const float X0 = T[0][t], X1 = T[1][t], X2 = T[2][t];
                 const float* __restrict__ col = gimg + (int64_t)(r0 - B) * W + (c0 - B + t);
-                for (int u = ulo; u < uhi; ++u) {
-                    const float e = col[(int64_t)u * W];
-                    const float4 ty = S.ty[grp][u];
-                    const float a0 = ty.x * e, a1 = ty.y * e, a2 = ty.z * e;
-                    s0 = __builtin_fmaf(a0, X0, s0);
-                    s_x = __builtin_fmaf(a0, X1, s_x);
-                    s_y = __builtin_fmaf(a1, X0, s_y);
-                    s_r = __builtin_fmaf(a0, X2, s_r);
-                    s_r = __builtin_fmaf(a2, X0, s_r);
+                for (int u = ulo; u < uhi; u += GROWS) {
+                    // GROWS loads issued together; rows past the patch re-read its last
+                    // row and are weighted by zero
+                    float e[GROWS];
+#pragma unroll
+                    for (int k = 0; k < GROWS; ++k) {
+                        const int uu = u + k < uhi ? u + k : uhi - 1;
+                        e[k] = col[(int64_t)uu * W];
+                    }
+#pragma unroll
+                    for (int k = 0; k < GROWS; ++k) {
+                        const int uu = u + k < uhi ? u + k : uhi - 1;
+                        const float4 ty = S.ty[grp][uu];
+                        const float ek = u + k < uhi ? e[k] : 0.0f;
+                        const float a0 = ty.x * ek, a1 = ty.y * ek, a2 = ty.z * ek;
+                        s0 = __builtin_fmaf(a0, X0, s0);
+                        s_x = __builtin_fmaf(a0, X1, s_x);
+                        s_y = __builtin_fmaf(a1, X0, s_y);
+                        s_r = __builtin_fmaf(a0, X2, s_r);
+                        s_r = __builtin_fmaf(a2, X0, s_r);
+                    }
                 }
             }
         }
@@ -256,20 +271,19 @@ __device__ __forceinline__ Sample sample_jac(const FlowView& fv, float px, float
 }
 
 // Per-particle accumulation of node contributions, merged while consecutive
-// samples stay in one grid cell.
-template <bool SCATTER>
+// samples stay in one grid cell, flushed as 64-bit fixed-point atomic adds
+// (integer sums: the result does not depend on their order).
 struct NodeRun {
     int cell = -1, i0 = 0, j0 = 0;
     float acc[8];
-    float kmax = 0.0f;
     unsigned long long* fixed;
     int64_t base;         // element offset of the pair's grid
     int Gw;
-    double scale;
+    double scale;         // 2^e; 0 when the flow gradient is not accumulated
 
     __device__ void flush()
     {
-        if (!SCATTER || cell < 0) return;
+        if (cell < 0) return;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             const int64_t e = base + 2 * ((int64_t)(i0 + (n >> 1)) * Gw + (j0 + (n & 1)));
@@ -286,8 +300,7 @@ struct NodeRun {
 
     __device__ void add(const Sample& s, float ku, float kv)
     {
-        kmax = __builtin_fmaxf(kmax, __builtin_fmaxf(__builtin_fabsf(ku), __builtin_fabsf(kv)));
-        if (!SCATTER) return;
+        if (scale == 0.0) return;
         const int key = s.i0 * Gw + s.j0;
         if (key != cell) {
             flush();
@@ -307,9 +320,8 @@ struct NodeRun {
 };
 
 // Back-propagate one sample with upstream (ku, kv); returns J^T k in (bx, by).
-template <bool SCATTER>
-__device__ __forceinline__ void stage_back(const FlowView& fv, NodeRun<SCATTER>& run, float px, float py, float ku,
-                                           float kv, float& bx, float& by)
+__device__ __forceinline__ void stage_back(const FlowView& fv, NodeRun& run, float px, float py, float ku, float kv,
+                                           float& bx, float& by)
 {
     const Sample s = sample_jac(fv, px, py);
     run.add(s, ku, kv);
@@ -317,9 +329,8 @@ __device__ __forceinline__ void stage_back(const FlowView& fv, NodeRun<SCATTER>&
     by = s.jy.x * ku + s.jy.y * kv;
 }
 
-template <bool SCATTER>
-__device__ __forceinline__ void substep_adjoint(const FlowView& fv, NodeRun<SCATTER>& run, float px, float py,
-                                                float h, float hh, int integrator, float& gpx, float& gpy)
+__device__ __forceinline__ void substep_adjoint(const FlowView& fv, NodeRun& run, float px, float py, float h,
+                                                float hh, int integrator, float& gpx, float& gpy)
 {
     float bx, by;
     if (integrator == SP_EULER) {
@@ -344,127 +355,175 @@ __device__ __forceinline__ void substep_adjoint(const FlowView& fv, NodeRun<SCAT
     gpy += ((b1y + b2y) + b3y) + b4y;
 }
 
-// SCATTER = false: the sweep's largest upstream value (into kmax_bits) and the
-// final position gradient (added to g_x1, g_y1).  SCATTER = true: the same
-// sweep again, node sums into the fixed-point grid.
-// CK checkpoints of the trajectory are kept, one every L = ceil(substeps / CK)
-// substeps; each segment is recomputed into SK >= L slots during the sweep.
-template <bool SCATTER, int CK, int SK>
+// Words of the fixed-point scale block in the workspace.
+enum { SC_G2MAX = 0, SC_LIP = 1, SC_EXP = 2, SC_STATE = 3 };
+enum { SC_NONE = 0, SC_VALID = 1, SC_NONFINITE = 2 };
+
+// Reverse sweep of every particle: final position gradient (added to g_x1,
+// g_y1) and node sums into the fixed-point grid.  CK checkpoints of the
+// trajectory are kept, one every L = ceil(substeps / CK) substeps; each segment
+// is recomputed into SK >= L slots during the sweep.
+template <int CK, int SK>
 __global__ void __launch_bounds__(256)
-bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap, int en)
+bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
 {
     const int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    NodeRun<SCATTER> run;
+    if (g >= n_span) return;
+    const int p = find_pair_by_particle(a.pairs, a.n_pairs, g);
+    const synthpix_pair P = a.pairs[p];
+    const int64_t i = g - P.particle_offset;
+    if (i < 0 || i >= P.n_max) return;
+    float gpx = a.gx2[g], gpy = a.gy2[g];
+    const float px = a.x1[g], py = a.y1[g];
+    if ((gpx == 0.0f && gpy == 0.0f) || !__builtin_isfinite(px) || !__builtin_isfinite(py)) return;
+    NodeRun run;
     run.fixed = a.fixed;
-    run.base = 0;
-    run.Gw = 2;
-    run.scale = 0.0;
-    bool live = false;
-    FlowView fv{reinterpret_cast<const float2*>(a.flow), 2, 2, 1.0f, 1.0f};
-    float gpx = 0.0f, gpy = 0.0f, px = 0.0f, py = 0.0f;
-    if (g < n_span) {
-        const int p = find_pair_by_particle(a.pairs, a.n_pairs, g);
-        const synthpix_pair P = a.pairs[p];
-        const int64_t i = g - P.particle_offset;
-        if (i >= 0 && i < P.n_max) {
-            gpx = a.gx2[g];
-            gpy = a.gy2[g];
-            px = a.x1[g];
-            py = a.y1[g];
-            live = (gpx != 0.0f || gpy != 0.0f) && __builtin_isfinite(px) && __builtin_isfinite(py);
-            fv = flow_view(P, a.flow);
-            run.base = P.flow_offset;
-            run.Gw = P.Gw;
+    run.base = P.flow_offset;
+    run.Gw = P.Gw;
+    run.scale = a.scale[SC_STATE] == SC_VALID ? __builtin_ldexp(1.0, (int)a.scale[SC_EXP]) : 0.0;
+    const FlowView fv = flow_view(P, a.flow);
+
+    const int S = ap.substeps;
+    const float h = ap.dt / (float)S;
+    const float hh = h * 0.5f;
+    const int L = (S + CK - 1) / CK;
+    const int nseg = (S + L - 1) / L;
+    float cpx[CK], cpy[CK];
+    float qx = px, qy = py;
+    for (int s = 0; s < S; ++s) {
+        if (s % L == 0) {
+            cpx[s / L] = qx;
+            cpy[s / L] = qy;
         }
+        if (s + 1 < S) substep(fv, qx, qy, h, hh, ap.integrator);
     }
-    if (SCATTER) {
-        const float M = __uint_as_float(*a.kmax_bits);
-        if (!(M > 0.0f) || !__builtin_isfinite(M)) return;
-        int em;
-        (void)__builtin_frexpf(M, &em);
-        run.scale = __builtin_ldexp(1.0, 61 - em - en);
+    float spx[SK], spy[SK];
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int s0 = seg * L;
+        const int len = (S - s0) < L ? (S - s0) : L;
+        spx[0] = cpx[seg];
+        spy[0] = cpy[seg];
+        for (int k = 1; k < len; ++k) {
+            float tx = spx[k - 1], ty = spy[k - 1];
+            substep(fv, tx, ty, h, hh, ap.integrator);
+            spx[k] = tx;
+            spy[k] = ty;
+        }
+        for (int k = len - 1; k >= 0; --k) substep_adjoint(fv, run, spx[k], spy[k], h, hh, ap.integrator, gpx, gpy);
     }
-    if (live) {
-        const int S = ap.substeps;
-        const float h = ap.dt / (float)S;
-        const float hh = h * 0.5f;
-        const int L = (S + CK - 1) / CK;
-        const int nseg = (S + L - 1) / L;
-        float cpx[CK], cpy[CK];
-        float qx = px, qy = py;
-        for (int s = 0; s < S; ++s) {
-            if (s % L == 0) {
-                cpx[s / L] = qx;
-                cpy[s / L] = qy;
-            }
-            if (s + 1 < S) substep(fv, qx, qy, h, hh, ap.integrator);
-        }
-        float spx[SK], spy[SK];
-        for (int seg = nseg - 1; seg >= 0; --seg) {
-            const int s0 = seg * L;
-            const int len = (S - s0) < L ? (S - s0) : L;
-            spx[0] = cpx[seg];
-            spy[0] = cpy[seg];
-            for (int k = 1; k < len; ++k) {
-                float tx = spx[k - 1], ty = spy[k - 1];
-                substep(fv, tx, ty, h, hh, ap.integrator);
-                spx[k] = tx;
-                spy[k] = ty;
-            }
-            for (int k = len - 1; k >= 0; --k)
-                substep_adjoint<SCATTER>(fv, run, spx[k], spy[k], h, hh, ap.integrator, gpx, gpy);
-        }
-        run.flush();
-        if (!SCATTER) {
-            a.g_x1[g] += gpx;
-            a.g_y1[g] += gpy;
-        }
+    run.flush();
+    a.g_x1[g] += gpx;
+    a.g_y1[g] += gpy;
+}
+
+// Inputs of the fixed-point scale: the largest |dL/dx2|, |dL/dy2| and a bound L
+// on the transposed velocity Jacobian's max-row-sum over every cell (the
+// bilinear x-derivative is a blend of the cell's two edge differences, so its
+// magnitude is at most the larger one).  Blocks (pair, slice); float bits of
+// non-negative values order like unsigned integers.
+__global__ void __launch_bounds__(256)
+bwd_bounds(BwdArgs a)
+{
+    const synthpix_pair P = a.pairs[blockIdx.x];
+    const int nsl = gridDim.y, sl = blockIdx.y;
+    float gm = 0.0f;
+    for (int64_t i = (int64_t)sl * 256 + threadIdx.x; i < P.n_max; i += (int64_t)nsl * 256) {
+        const int64_t g = P.particle_offset + i;
+        gm = __builtin_fmaxf(gm, __builtin_fmaxf(__builtin_fabsf(a.gx2[g]), __builtin_fabsf(a.gy2[g])));
+        if (!__builtin_isfinite(a.gx2[g]) || !__builtin_isfinite(a.gy2[g])) gm = __builtin_inff();
     }
-    if (!SCATTER) {
-        // block maximum of the upstream magnitudes, one atomic per block (float bits of
-        // non-negative values order like unsigned integers)
-        float m = run.kmax;
+    const float2* F = reinterpret_cast<const float2*>(a.flow + P.flow_offset);
+    const float sx = (float)P.Gw / (float)P.W, sy = (float)P.Gh / (float)P.H;
+    const int64_t cells = (int64_t)(P.Gh - 1) * (P.Gw - 1);
+    float lm = 0.0f;
+    for (int64_t k = (int64_t)sl * 256 + threadIdx.x; k < cells; k += (int64_t)nsl * 256) {
+        const int i = (int)(k / (P.Gw - 1)), j = (int)(k % (P.Gw - 1));
+        const float2 A = F[(int64_t)i * P.Gw + j], B = F[(int64_t)i * P.Gw + j + 1];
+        const float2 C = F[(int64_t)(i + 1) * P.Gw + j], E = F[(int64_t)(i + 1) * P.Gw + j + 1];
+        const float lx = sx * (__builtin_fmaxf(__builtin_fabsf(B.x - A.x), __builtin_fabsf(E.x - C.x)) +
+                               __builtin_fmaxf(__builtin_fabsf(B.y - A.y), __builtin_fabsf(E.y - C.y)));
+        const float ly = sy * (__builtin_fmaxf(__builtin_fabsf(C.x - A.x), __builtin_fabsf(E.x - B.x)) +
+                               __builtin_fmaxf(__builtin_fabsf(C.y - A.y), __builtin_fabsf(E.y - B.y)));
+        lm = __builtin_fmaxf(lm, __builtin_fmaxf(lx, ly));
+        if (!__builtin_isfinite(lx) || !__builtin_isfinite(ly)) lm = __builtin_inff();
+    }
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) m = __builtin_fmaxf(m, __shfl_xor(m, o, 64));
-        __shared__ float wmax[4];
-        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const float b = __builtin_fmaxf(__builtin_fmaxf(wmax[0], wmax[1]), __builtin_fmaxf(wmax[2], wmax[3]));
-            if (b != 0.0f) atomicMax(a.kmax_bits, __float_as_uint(b));
-        }
+    for (int o = 32; o >= 1; o >>= 1) {
+        gm = __builtin_fmaxf(gm, __shfl_xor(gm, o, 64));
+        lm = __builtin_fmaxf(lm, __shfl_xor(lm, o, 64));
+    }
+    __shared__ float red[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = gm;
+        red[1][threadIdx.x >> 6] = lm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float G = __builtin_fmaxf(__builtin_fmaxf(red[0][0], red[0][1]), __builtin_fmaxf(red[0][2], red[0][3]));
+        const float Lb = __builtin_fmaxf(__builtin_fmaxf(red[1][0], red[1][1]), __builtin_fmaxf(red[1][2], red[1][3]));
+        if (G != 0.0f) atomicMax(a.scale + SC_G2MAX, __float_as_uint(G));
+        if (Lb != 0.0f) atomicMax(a.scale + SC_LIP, __float_as_uint(Lb));
     }
 }
 
+// The fixed-point exponent e.  Every upstream value k of the reverse sweep obeys
+// |k| <= K = G0 kfac growth^(S-1), from the stage recurrences with |J^T k| <= L |k|
+// (Euler: kfac = |h|, growth = 1 + |h| L; RK4: k4 = c, k3 = 2c + |h| L k4,
+// k2 = 2c + |h|/2 L k3, k1 = c + |h|/2 L k2 with c = |h|/6, growth = 1 + L sum k).
+// A node sum has at most 2^en such terms of weight <= 1, so with
+// e = 61 - ceil(log2 K) - en no partial sum leaves the int64 range.
+__global__ void bwd_scale(uint32_t* __restrict__ sc, synthpix_advect_params ap, int en)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double G0 = (double)__uint_as_float(sc[SC_G2MAX]);
+    const double L = (double)__uint_as_float(sc[SC_LIP]);
+    const int S = ap.substeps;
+    const double h = __builtin_fabs((double)ap.dt / (double)S);
+    double kfac, growth;
+    if (ap.integrator == SP_EULER) {
+        kfac = h;
+        growth = 1.0 + h * L;
+    } else {
+        const double c = h / 6.0;
+        const double k4 = c, k3 = 2.0 * c + h * L * k4, k2 = 2.0 * c + 0.5 * h * L * k3, k1 = c + 0.5 * h * L * k2;
+        kfac = __builtin_fmax(__builtin_fmax(k1, k2), __builtin_fmax(k3, k4));
+        growth = 1.0 + L * (k1 + k2 + k3 + k4);
+    }
+    const double K = G0 * kfac * pow(growth, (double)(S - 1)) * 1.0009765625;
+    uint32_t state = SC_VALID;
+    int e = 0;
+    if (!(G0 > 0.0) || !(h > 0.0)) {
+        state = SC_NONE;
+    } else if (!__builtin_isfinite(K) || !(K > 0.0)) {
+        state = SC_NONFINITE;
+    } else {
+        int k;
+        (void)__builtin_frexp(K, &k);   // K < 2^k
+        e = 61 - k - en;
+    }
+    sc[SC_EXP] = (uint32_t)e;
+    sc[SC_STATE] = state;
+}
+
 __global__ void bwd_init(unsigned long long* __restrict__ fixed, int64_t n, uint32_t* __restrict__ status,
-                         uint32_t* __restrict__ kmax_bits)
+                         uint32_t* __restrict__ sc)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) {
-        status[0] = 0u;
-        status[1] = 0u;
-        status[2] = 0u;
-        status[3] = 0u;
-        *kmax_bits = 0u;
+    if (t < 4) {
+        status[t] = 0u;
+        sc[t] = 0u;
     }
     for (int64_t k = t; k < n; k += (int64_t)gridDim.x * blockDim.x) fixed[k] = 0ull;
 }
 
 __global__ void bwd_flow_finish(const unsigned long long* __restrict__ fixed, int64_t n,
-                                const uint32_t* __restrict__ kmax_bits, int en, float* __restrict__ g_flow)
+                                const uint32_t* __restrict__ sc, float* __restrict__ g_flow)
 {
-    const float M = __uint_as_float(*kmax_bits);
-    double inv = 0.0;
-    float fill = 0.0f;
-    if (M > 0.0f && __builtin_isfinite(M)) {
-        int em;
-        (void)__builtin_frexpf(M, &em);
-        inv = __builtin_ldexp(1.0, -(61 - em - en));
-    } else if (!(M == 0.0f)) {
-        fill = __builtin_nanf("");
-    }
+    const uint32_t state = sc[SC_STATE];
+    const double inv = state == SC_VALID ? __builtin_ldexp(1.0, -(int)sc[SC_EXP]) : 0.0;
+    const float fill = state == SC_NONFINITE ? __builtin_nanf("") : 0.0f;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-        g_flow[k] = inv != 0.0 ? (float)((double)(long long)fixed[k] * inv) : fill;
+        g_flow[k] = state == SC_VALID ? (float)((double)(long long)fixed[k] * inv) : fill;
 }
 
 // Per-pair sum of the sheet-width terms, in float64, in a fixed order.
@@ -484,12 +543,11 @@ bwd_sheet(const synthpix_pair* __restrict__ pairs, const float* __restrict__ she
     if (threadIdx.x == 0) g_sheet[blockIdx.x] = (float)red[0];
 }
 
-template <bool SCATTER>
-void launch_advect_adjoint(const BwdArgs& a, int64_t n_span, const synthpix_advect_params& ap, int en, unsigned blocks,
+void launch_advect_adjoint(const BwdArgs& a, int64_t n_span, const synthpix_advect_params& ap, unsigned blocks,
                            hipStream_t s)
 {
     const int S = ap.substeps;
-#define SP_ADJ(CK, SK) hipLaunchKernelGGL((bwd_advect<SCATTER, CK, SK>), dim3(blocks), dim3(256), 0, s, a, n_span, ap, en)
+#define SP_ADJ(CK, SK) hipLaunchKernelGGL((bwd_advect<CK, SK>), dim3(blocks), dim3(256), 0, s, a, n_span, ap)
     if (S <= 1) SP_ADJ(1, 1);
     else if (S <= 2) SP_ADJ(2, 1);
     else if (S <= 4) SP_ADJ(4, 1);
@@ -506,8 +564,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
     {
         TimedScope ts("bwd_init", s);
         const int64_t blocks = std::min<int64_t>((n_flow + 255) / 256 + 1, 4096);
-        hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.status,
-                           a.kmax_bits);
+        hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.status, a.scale);
     }
     if (n_span > 0) {
         hipError_t e = launch_advect(a.pairs, a.n_pairs, n_span, a.flow, ap, a.x1, a.y1, a.x2, a.y2, s);
@@ -515,28 +572,36 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         const unsigned gb = (unsigned)((n_span + BPW - 1) / BPW);
         {
             TimedScope ts("bwd_gather", s);
+            // slots needed: floor(3 d_max) + 2 support pixels + 4 b padding
+            const bool small = (int)(3.0f * a.d_max) + 2 + 4 * blur <= 32;
+#define SP_GATHER(BB)                                                                  \
+    do {                                                                               \
+        if (small) hipLaunchKernelGGL((bwd_gather<BB, 32>), dim3(gb), dim3(256), 0, s, a, n_span); \
+        else hipLaunchKernelGGL((bwd_gather<BB, 64>), dim3(gb), dim3(256), 0, s, a, n_span);       \
+    } while (0)
             switch (blur) {
-            case 0: hipLaunchKernelGGL(bwd_gather<0>, dim3(gb), dim3(256), 0, s, a, n_span); break;
-            case 1: hipLaunchKernelGGL(bwd_gather<1>, dim3(gb), dim3(256), 0, s, a, n_span); break;
-            case 2: hipLaunchKernelGGL(bwd_gather<2>, dim3(gb), dim3(256), 0, s, a, n_span); break;
-            default: hipLaunchKernelGGL(bwd_gather<3>, dim3(gb), dim3(256), 0, s, a, n_span); break;
+            case 0: SP_GATHER(0); break;
+            case 1: SP_GATHER(1); break;
+            case 2: SP_GATHER(2); break;
+            default: SP_GATHER(3); break;
             }
-        }
-        const unsigned ab = (unsigned)((n_span + 255) / 256);
-        {
-            TimedScope ts("bwd_advect_max", s);
-            launch_advect_adjoint<false>(a, n_span, ap, en, ab, s);
+#undef SP_GATHER
         }
         {
-            TimedScope ts("bwd_advect_scatter", s);
-            launch_advect_adjoint<true>(a, n_span, ap, en, ab, s);
+            TimedScope ts("bwd_bounds", s);
+            hipLaunchKernelGGL(bwd_bounds, dim3((unsigned)a.n_pairs, 16), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(bwd_scale, dim3(1), dim3(64), 0, s, a.scale, ap, en);
+        }
+        {
+            TimedScope ts("bwd_advect", s);
+            launch_advect_adjoint(a, n_span, ap, (unsigned)((n_span + 255) / 256), s);
         }
     }
     {
         TimedScope ts("bwd_flow", s);
         const int64_t blocks = std::min<int64_t>((n_flow + 255) / 256 + 1, 8192);
-        hipLaunchKernelGGL(bwd_flow_finish, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.kmax_bits,
-                           en, a.g_flow);
+        hipLaunchKernelGGL(bwd_flow_finish, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.scale,
+                           a.g_flow);
     }
     {
         TimedScope ts("bwd_sheet", s);

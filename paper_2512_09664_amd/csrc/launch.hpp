@@ -135,7 +135,7 @@ struct BwdArgs {
     float* gy2;
     float* sheet;                // per-particle sheet-width terms (workspace)
     unsigned long long* fixed;   // fixed-point flow-gradient sums (workspace, flow layout)
-    uint32_t* kmax_bits;
+    uint32_t* scale;             // fixed-point scale block: max |dL/dx2|, Lipschitz bound, exponent, state
     uint32_t* status;
     float sheet_sigma;
     float d_max;

@@ -31,7 +31,7 @@ constexpr int BG = 16;             // lanes per particle in the gather
 constexpr int BPW = 256 / BG;      // particles per workgroup
 constexpr int GROWS = 8;           // patch rows loaded per batch (independent loads in flight)
 
-// BT table slots cover the support (<= 3 d_max + 2 pixels) plus 4 b of zero padding.
+// BT table slots cover the pixel range (<= 3 d_max + 3 pixels) plus 4 b of zero padding.
 template <int BT>
 struct GatherLds {
     float rx[BPW][3][BT];          // raw column factors gx dx^k, k = 0, 1, 2 (slot = c - c0 + 2b)
@@ -40,11 +40,37 @@ struct GatherLds {
     float4 ty[BPW][BT];            // blurred row tables (Ty0, Ty1, Ty2, 0)
 };
 
+// Sum over the 16 lanes of a DPP row (a particle's lane group), result in every
+// lane: quad butterflies (quad_perm [1,0,3,2] and [2,3,0,1]) then rotations of
+// the row by 4 and 8 lanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float group_sum(float v)
 {
-#pragma unroll
-    for (int m = BG / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, BG);
+    static_assert(BG == 16, "a lane group is one DPP row");
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x124>(v);
+    v += dpp<0x128>(v);
     return v;
+}
+
+// Pixel indices that may hold the support |(k + 1/2) - p| <= R, clipped to
+// [0, n): a superset by at most one index per side (the exact binary32 test
+// is applied per pixel where the factor tables are filled).
+__device__ __forceinline__ bool cover_range(float p, float R, int n, int& lo, int& hi)
+{
+    if (!__builtin_isfinite(p)) return false;
+    const float a = p - R - 0.5f, b = p + R - 0.5f;
+    if (b < -1.0f || a > (float)n) return false;
+    const int l = (int)__builtin_floorf(a), h = (int)__builtin_ceilf(b);
+    lo = l < 0 ? 0 : l;
+    hi = h > n - 1 ? n - 1 : h;
+    return lo <= hi;
 }
 
 template <int B, int BT>
@@ -90,9 +116,8 @@ bwd_gather(BwdArgs a, int64_t n_span)
             y = f ? a.y2[g] : a.y1[g];
         }
         int c0 = 0, c1 = -1, r0 = 0, r1 = -1;
-        bool on = valid && __builtin_isfinite(x) && __builtin_isfinite(y);
-        on = on && support_range(x, R, W, c0, c1);
-        on = on && support_range(y, R, H, r0, r1);
+        bool on = valid && cover_range(x, R, W, c0, c1);
+        on = on && cover_range(y, R, H, r0, r1);
 
         // raw factor tables; every slot is written (zeros outside the support)
 #pragma unroll
@@ -100,8 +125,8 @@ bwd_gather(BwdArgs a, int64_t n_span)
             const int slot = lane + BG * m;
             const int c = c0 - 2 * B + slot;
             float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
-            if (on && c >= c0 && c <= c1) {
-                const float dx = ((float)c + 0.5f) - x;
+            const float dx = ((float)c + 0.5f) - x;
+            if (on && c >= c0 && c <= c1 && __builtin_fabsf(dx) <= R) {
                 v0 = expneg(kap * (dx * dx));
                 v1 = v0 * dx;
                 v2 = v1 * dx;
@@ -111,8 +136,8 @@ bwd_gather(BwdArgs a, int64_t n_span)
             S.rx[grp][2][slot] = v2;
             const int r = r0 - 2 * B + slot;
             float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
-            if (on && r >= r0 && r <= r1) {
-                const float dy = ((float)r + 0.5f) - y;
+            const float dy = ((float)r + 0.5f) - y;
+            if (on && r >= r0 && r <= r1 && __builtin_fabsf(dy) <= R) {
                 u0 = expneg(kap * (dy * dy));
                 u1 = u0 * dy;
                 u2 = u1 * dy;
@@ -245,8 +270,10 @@ __device__ __forceinline__ Sample sample_jac(const FlowView& fv, float px, float
     const float fx = gx - (float)j0;
     const float fy = gy - (float)i0;
     const float2* row0 = fv.F + (size_t)i0 * fv.Gw + j0;
-    const float2* row1 = row0 + fv.Gw;
-    const float2 A = row0[0], Bn = row0[1], C = row1[0], E = row1[1];
+    const float4 r0 = load_pair(row0);
+    const float4 r1 = load_pair(row0 + fv.Gw);
+    const float2 A = make_float2(r0.x, r0.y), Bn = make_float2(r0.z, r0.w);
+    const float2 C = make_float2(r1.x, r1.y), E = make_float2(r1.z, r1.w);
     {
         const float top = __builtin_fmaf(fx, Bn.x - A.x, A.x);
         const float bot = __builtin_fmaf(fx, E.x - C.x, C.x);
@@ -272,24 +299,30 @@ __device__ __forceinline__ Sample sample_jac(const FlowView& fv, float px, float
 
 // Per-particle accumulation of node contributions, merged while consecutive
 // samples stay in one grid cell, flushed as 64-bit fixed-point atomic adds
-// (integer sums: the result does not depend on their order).
-struct NodeRun {
-    int cell = -1, i0 = 0, j0 = 0;
+// (integer sums: the result does not depend on their order).  The two runs
+// before the current one are held back, so that most lanes flush together at
+// the end of the sweep instead of wherever their own run boundaries fall.
+struct CellRun {
+    int i0 = -1, j0 = 0;
     float acc[8];
+};
+
+struct NodeRun {
+    CellRun cur, prev1, prev2;
     unsigned long long* fixed;
     int64_t base;         // element offset of the pair's grid
     int Gw;
     double scale;         // 2^e; 0 when the flow gradient is not accumulated
 
-    __device__ void flush()
+    __device__ void flush(const CellRun& r)
     {
-        if (cell < 0) return;
+        if (r.i0 < 0) return;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            const int64_t e = base + 2 * ((int64_t)(i0 + (n >> 1)) * Gw + (j0 + (n & 1)));
+            const int64_t e = base + 2 * ((int64_t)(r.i0 + (n >> 1)) * Gw + (r.j0 + (n & 1)));
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const float v = acc[2 * n + c];
+                const float v = r.acc[2 * n + c];
                 if (v != 0.0f) {
                     const long long q = (long long)__builtin_rint((double)v * scale);
                     atomicAdd(fixed + e + c, (unsigned long long)q);
@@ -298,23 +331,30 @@ struct NodeRun {
         }
     }
 
+    __device__ void finish()
+    {
+        flush(cur);
+        flush(prev1);
+        flush(prev2);
+    }
+
     __device__ void add(const Sample& s, float ku, float kv)
     {
         if (scale == 0.0) return;
-        const int key = s.i0 * Gw + s.j0;
-        if (key != cell) {
-            flush();
-            cell = key;
-            i0 = s.i0;
-            j0 = s.j0;
+        if (s.i0 != cur.i0 || s.j0 != cur.j0) {
+            if (prev2.i0 >= 0) flush(prev2);
+            prev2 = prev1;
+            prev1 = cur;
+            cur.i0 = s.i0;
+            cur.j0 = s.j0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
+            for (int k = 0; k < 8; ++k) cur.acc[k] = 0.0f;
         }
         const float w[4] = {(1.0f - s.fx) * (1.0f - s.fy), s.fx * (1.0f - s.fy), (1.0f - s.fx) * s.fy, s.fx * s.fy};
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            acc[2 * n] = __builtin_fmaf(w[n], ku, acc[2 * n]);
-            acc[2 * n + 1] = __builtin_fmaf(w[n], kv, acc[2 * n + 1]);
+            cur.acc[2 * n] = __builtin_fmaf(w[n], ku, cur.acc[2 * n]);
+            cur.acc[2 * n + 1] = __builtin_fmaf(w[n], kv, cur.acc[2 * n + 1]);
         }
     }
 };
@@ -411,7 +451,7 @@ bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
         }
         for (int k = len - 1; k >= 0; --k) substep_adjoint(fv, run, spx[k], spy[k], h, hh, ap.integrator, gpx, gpy);
     }
-    run.flush();
+    run.finish();
     a.g_x1[g] += gpx;
     a.g_y1[g] += gpy;
 }
@@ -572,8 +612,8 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         const unsigned gb = (unsigned)((n_span + BPW - 1) / BPW);
         {
             TimedScope ts("bwd_gather", s);
-            // slots needed: floor(3 d_max) + 2 support pixels + 4 b padding
-            const bool small = (int)(3.0f * a.d_max) + 2 + 4 * blur <= 32;
+            // slots needed: floor(3 d_max) + 4 covered pixels + 4 b padding
+            const bool small = (int)(3.0f * a.d_max) + 4 + 4 * blur <= 32;
 #define SP_GATHER(BB)                                                                  \
     do {                                                                               \
         if (small) hipLaunchKernelGGL((bwd_gather<BB, 32>), dim3(gb), dim3(256), 0, s, a, n_span); \

@@ -325,7 +325,8 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     uint16_t* items = reinterpret_cast<uint16_t*>(rs + lay.tables);     // 2 * tables entries
     int* s_wave = reinterpret_cast<int*>(items + 2 * lay.tables);
     float* tmp = reinterpret_cast<float*>(stg);   // blur scratch, reuses the particle tables
-    __shared__ unsigned long long s_asum;
+    __shared__ float s_asum[4];
+    float asum = 0.0f;
 
     // one (frame, tile) item per workgroup; XCD-contiguous numbering keeps
     // neighbouring tiles (which share particles) on one L2
@@ -349,7 +350,6 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
 
     for (int k = threadIdx.x; k < (lay.acc_words >> 2); k += 256)
         reinterpret_cast<uint4*>(acc)[k] = make_uint4(0u, 0u, 0u, 0u);
-    if (threadIdx.x == 0) s_asum = 0ull;
 
     for (int base = 0; base < cnt; base += cap) {
         const int n = min(cap, cnt - base);
@@ -380,7 +380,7 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             }
             stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (r.z * r.z), r.w);
             box[threadIdx.x] = pack_box(c0, w, r0, h);
-            if (w > 0) atomicAdd(&s_asum, (unsigned long long)(uint32_t)r.w);
+            if (w > 0) asum += r.w;
         }
         // work items: one per patch line j < max(w, h); item j carries the j-th
         // column factor (if j < w) and the j-th row factor (if j < h)
@@ -435,8 +435,14 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             }
         }
     }
+    // the sum of all staged peaks bounds every pixel's sum: flag a tile where it
+    // could reach 2^32 (float sum, compared with a margin for its rounding)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) asum += __shfl_xor(asum, o, 64);
+    if ((threadIdx.x & 63) == 0) s_asum[threadIdx.x >> 6] = asum;
     __syncthreads();
-    if (threadIdx.x == 0 && s_asum >= 4294967296ull) atomicOr(status, SP_STATUS_FIXED_RANGE);
+    if (threadIdx.x == 0 && (s_asum[0] + s_asum[1]) + (s_asum[2] + s_asum[3]) >= 4294000000.0f)
+        atomicOr(status, SP_STATUS_FIXED_RANGE);
 
     // fixed point -> float happens as the blur / store passes read the accumulator
     constexpr float FIX = 0x1p-24f;

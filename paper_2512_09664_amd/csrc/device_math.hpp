@@ -140,7 +140,10 @@ __device__ __forceinline__ float cos2pi_ra(float u)
 // ---------------------------------------------------------------- support ranges
 // Pixel indices k in [0, n) with |(k + 1/2) - p| <= R, the difference and the
 // comparison in binary32.  The float offset is monotone in k, so the set is an
-// interval; it is found from a float estimate and corrected by re-testing.
+// interval [K0, K1].  Its ends are estimated as ceil(p - R - 1/2) and
+// floor(p + R - 1/2); for |p| < 2^15 the estimates' rounding errors are far
+// below one pixel, so each is within one of the exact end and a single
+// re-test on either side fixes it.
 
 __device__ __forceinline__ bool in_support(int k, float p, float R)
 {
@@ -156,16 +159,12 @@ __device__ __forceinline__ bool support_range(float p, float R, int n, int& lo, 
         // far outside the image: nothing in [0, n); still exact since |dx| > R for every k
         return false;
     }
-    // estimates of the first and last pixel with |(k + 1/2) - p| <= R, then exact
-    // correction by re-testing the binary32 predicate (monotone in k)
     int k0 = (int)__builtin_ceilf(a - 0.5f);
     int k1 = (int)__builtin_floorf(b - 0.5f);
+    k0 = in_support(k0 - 1, p, R) ? k0 - 1 : (in_support(k0, p, R) ? k0 : k0 + 1);
+    k1 = in_support(k1 + 1, p, R) ? k1 + 1 : (in_support(k1, p, R) ? k1 : k1 - 1);
     k0 = k0 < 0 ? 0 : k0;
     k1 = k1 > n - 1 ? n - 1 : k1;
-    while (k0 > 0 && in_support(k0 - 1, p, R)) --k0;
-    while (k0 <= k1 && !in_support(k0, p, R)) ++k0;
-    while (k1 < n - 1 && in_support(k1 + 1, p, R)) ++k1;
-    while (k1 >= k0 && !in_support(k1, p, R)) --k1;
     if (k0 > k1) return false;
     lo = k0;
     hi = k1;

@@ -9,6 +9,15 @@
 
 namespace sp {
 
+// Two consecutive (u, v) nodes as one 16-byte load (8-byte aligned address; the
+// hardware handles the unaligned vector access).
+__device__ __forceinline__ float4 load_pair(const float2* p)
+{
+    float4 v;
+    __builtin_memcpy(&v, p, sizeof(v));
+    return v;
+}
+
 struct FlowView {
     const float2* __restrict__ F;
     int Gh, Gw;
@@ -27,9 +36,12 @@ __device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, floa
     i0 = i0 > fv.Gh - 2 ? fv.Gh - 2 : i0;
     const float fx = gx - (float)j0;
     const float fy = gy - (float)i0;
+    // the cell's two nodes of one grid row are adjacent: one 16-byte load per row
     const float2* row0 = fv.F + (size_t)i0 * fv.Gw + j0;
-    const float2* row1 = row0 + fv.Gw;
-    const float2 a = row0[0], b = row0[1], c = row1[0], e = row1[1];
+    const float4 r0 = load_pair(row0);
+    const float4 r1 = load_pair(row0 + fv.Gw);
+    const float2 a = make_float2(r0.x, r0.y), b = make_float2(r0.z, r0.w);
+    const float2 c = make_float2(r1.x, r1.y), e = make_float2(r1.z, r1.w);
     float2 out;
     {
         const float top = __builtin_fmaf(fx, b.x - a.x, a.x);

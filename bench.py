@@ -115,7 +115,7 @@ def uneven_batched_vs_per_pair(sp, torch, np, dev, steps=5):
     def per_pair_step(k):
         for b1, fl1, P1, x21, y21, im1, ws1 in singles:
             sp.seed(b1, sprm, wl.seed + k, out=P1)
-            sp.advect(b1, fl1, aprm, P1["x"], P1["y"], x21, y21)
+            sp.advect(b1, fl1, aprm, P1["x"], P1["y"], x21, y21, ws1)
             sp.render_pair(b1, P1["x"], P1["y"], x21, y21, P1["z"], P1["d"], P1["I0"], rprm, None, im1, ws1)
 
     per_pair_step(0)
@@ -149,7 +149,7 @@ def gradient_cost(sp, torch, np, dev, steps=10):
     wsb = sp.alloc_workspace(batch, rprm, backward=True)
 
     def fwd():
-        sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2)
+        sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2, wsf)
         sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, img, wsf)
 
     def bwd():
@@ -219,7 +219,7 @@ def main():
     def step(k):
         rprm.seed = wl.seed + k                       # a fresh batch of particles and noise per step
         sp.seed(batch, sprm, wl.seed + k, out=P)
-        sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2)
+        sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2, ws)
         sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, images, ws)
 
     for k in range(args.warmup):
@@ -239,7 +239,8 @@ def main():
     t1 = time.perf_counter()
     sp.timing_enable(False)
     kernels = {}
-    for name in ("seed", "advect", "bin_layout", "prep", "bin_count", "bin_scan", "bin_scatter", "render_tile"):
+    for name in ("seed", "order", "advect", "bin_layout", "prep", "bin_count", "bin_scan", "bin_scatter",
+                 "render_tile"):
         ms, n = sp.timing_read(name)
         if n:
             kernels[name] = {"avg_us": 1000.0 * ms / n, "launches": n}
@@ -285,7 +286,7 @@ def main():
             rprm.seed = wl.seed + k
             for b1, fl1, P1, x21, y21, im1 in singles:
                 sp.seed(b1, sprm, wl.seed + k, out=P1)
-                sp.advect(b1, fl1, aprm, P1["x"], P1["y"], x21, y21)
+                sp.advect(b1, fl1, aprm, P1["x"], P1["y"], x21, y21, ws)
                 sp.render_pair(b1, P1["x"], P1["y"], x21, y21, P1["z"], P1["d"], P1["I0"], rprm, None, im1, ws)
 
         plain_step(0)

@@ -144,7 +144,8 @@ synthpix_status synthpix_default_tiling(const synthpix_pair* pairs_host, int32_t
                                         const synthpix_render_params* rp, synthpix_tiling* out);
 
 /* Bytes of workspace needed by synthpix_render_pair (backward = 0) or
- * synthpix_render_pair_backward (backward = 1) for this batch and tiling. */
+ * synthpix_render_pair_backward (backward = 1) for this batch and tiling.  The
+ * forward size also covers synthpix_advect's optional workspace. */
 synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t n_pairs,
                                         const synthpix_render_params* rp,
                                         const synthpix_tiling* tiling, int32_t backward,
@@ -200,10 +201,20 @@ synthpix_status synthpix_seed(const synthpix_pair* pairs_host, const synthpix_pa
  * (Section 2, "Sampling the particles"): bilinear, clamped-to-edge sampling,
  * `substeps` steps of explicit Euler or classical RK4.
  * flow: device floats holding every pair's grid at pair.flow_offset.
- * x1, y1 -> x2, y2: device float arrays (x2/y2 may not alias x1/y1). */
+ * x1, y1 -> x2, y2: device float arrays (x2/y2 may not alias x1/y1).
+ * workspace: optional device scratch, 256-byte aligned, of at least
+ * synthpix_advect_workspace_size bytes (any workspace sized by
+ * synthpix_workspace_size also fits).  With it, particles are first ordered by
+ * home block so that neighbouring threads sample neighbouring grid cells; the
+ * results are identical with or without it (NULL: particle index order). */
 synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
                                 int32_t n_pairs, const float* flow, const synthpix_advect_params* ap,
-                                const float* x1, const float* y1, float* x2, float* y2, void* stream);
+                                const float* x1, const float* y1, float* x2, float* y2,
+                                void* workspace, size_t ws_bytes, void* stream);
+
+/* Bytes of the optional synthpix_advect workspace for this batch. */
+synthpix_status synthpix_advect_workspace_size(const synthpix_pair* pairs_host, int32_t n_pairs,
+                                               size_t* bytes_out);
 
 /* Render both exposures of every pair and apply blur, noise and storage
  * (Eq. 1; Section 2, "Considerations on the aggregation", "Efficient

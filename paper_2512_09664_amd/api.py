@@ -153,12 +153,25 @@ def seed(batch: PairBatch, sp, seed_value: int, out=None):
     return o
 
 
-def advect(batch: PairBatch, flow: torch.Tensor, ap, x1: torch.Tensor, y1: torch.Tensor, x2=None, y2=None):
+def advect_workspace_size(batch: PairBatch) -> int:
+    n = ctypes.c_size_t(0)
+    L.check(L.load().synthpix_advect_workspace_size(batch.host_ptr, batch.n_pairs, ctypes.byref(n)))
+    return n.value
+
+
+def advect(batch: PairBatch, flow: torch.Tensor, ap, x1: torch.Tensor, y1: torch.Tensor, x2=None, y2=None,
+           workspace: Optional[torch.Tensor] = None, ordered: bool = True):
+    """Run ``synthpix_advect``.  ``ordered`` processes particles in home-block
+    order (same results, faster); its scratch is ``workspace`` if given (e.g. a
+    render workspace), else a temporary."""
     _need_cuda(flow, x1, y1)
     x2 = torch.empty_like(x1) if x2 is None else x2
     y2 = torch.empty_like(y1) if y2 is None else y2
+    if ordered and workspace is None:
+        workspace = torch.empty(max(advect_workspace_size(batch), 256), dtype=torch.uint8, device=x1.device)
+    ws, nb = (_ptr(workspace), workspace.numel()) if ordered else (None, 0)
     L.check(L.load().synthpix_advect(batch.host_ptr, batch.dev_ptr, batch.n_pairs, _ptr(flow), ctypes.byref(ap),
-                                     _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _stream()))
+                                     _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), ws, nb, _stream()))
     return x2, y2
 
 

@@ -259,6 +259,61 @@ synthpix_tiling default_tiling()
 
 }  // namespace
 
+// Home blocks of the advection order: 32 x 32 pixels, or larger where a pair
+// would have more than 16384 blocks (the count pass holds one pair's block
+// histogram in LDS).
+sp::RenderConfig order_config(const synthpix_pair* ph, int32_t n_pairs)
+{
+    int lb = 5;
+    for (int32_t p = 0; p < n_pairs; ++p)
+        while ((int64_t)((ph[p].W + (1 << lb) - 1) >> lb) * ((ph[p].H + (1 << lb) - 1) >> lb) > 16384) ++lb;
+    sp::RenderConfig c{};
+    c.tile_w = c.tile_h = 1 << lb;
+    c.log_tw = c.log_th = lb;
+    c.chunk = 4096;
+    c.cap = 32;
+    c.apron = 0;
+    c.kx = c.ky = 1;     // one entry per particle
+    c.d_max = 1.0f;
+    return c;
+}
+
+sp::OrderLayout order_layout(int32_t n_pairs, const sp::BatchTotals& T, size_t base)
+{
+    sp::OrderLayout w{};
+    size_t o = base;
+    w.status = o; o = align256(o + 16);
+    w.layout = o; o = align256(o + sizeof(sp::PairLayout) * (size_t)n_pairs);
+    w.tile_count = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)T.tiles);
+    w.tile_offset = o; o = align256(o + sizeof(int64_t) * 2 * (size_t)T.tiles);
+    w.hist = o; o = align256(o + sizeof(uint32_t) * (size_t)T.hist);
+    w.entries = o; o = align256(o + sizeof(int32_t) * (size_t)T.entries);
+    w.total = o;
+    return w;
+}
+
+// Order workspace bytes for a batch (0 when the batch is invalid).
+size_t order_bytes(const synthpix_pair* ph, int32_t n_pairs)
+{
+    sp::BatchTotals T;
+    if (batch_totals(ph, n_pairs, order_config(ph, n_pairs), &T) != SP_OK) return 0;
+    return order_layout(n_pairs, T, 0).total;
+}
+
+// Builds the home-block order of (x, y) in `ws` at byte offset `base` and
+// returns it for the advection launch.
+hipError_t enqueue_order(const synthpix_pair* ph, const synthpix_pair* pd, int32_t n_pairs, const float* x,
+                         const float* y, char* ws, size_t base, hipStream_t s, sp::AdvectOrder* out)
+{
+    const sp::RenderConfig cfg = order_config(ph, n_pairs);
+    sp::BatchTotals T;
+    if (batch_totals(ph, n_pairs, cfg, &T) != SP_OK) return hipErrorInvalidValue;
+    const sp::OrderLayout ol = order_layout(n_pairs, T, base);
+    out->L = reinterpret_cast<const sp::PairLayout*>(ws + ol.layout);
+    out->entries = reinterpret_cast<const int32_t*>(ws + ol.entries);
+    return sp::launch_order(pd, n_pairs, x, y, cfg, T, ws, ol, s);
+}
+
 extern "C" {
 
 int32_t synthpix_version(void) { return SYNTHPIX_VERSION; }
@@ -296,14 +351,16 @@ synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t
     if ((st = check_render_params(rp))) return st;
     const synthpix_tiling t = tiling ? *tiling : default_tiling();
     if ((st = check_tiling(t))) return st;
+    const size_t ob = order_bytes(pairs_host, n_pairs);
+    if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (backward) {
-        *bytes_out = bwd_layout(span, flow_span(pairs_host, n_pairs)).total;
+        *bytes_out = bwd_layout(span, flow_span(pairs_host, n_pairs)).total + ob;
         return SP_OK;
     }
     const sp::RenderConfig cfg = make_config(*rp, t);
     sp::BatchTotals T;
     if ((st = batch_totals(pairs_host, n_pairs, cfg, &T))) return st;
-    *bytes_out = workspace_layout(n_pairs, T, 0, pairs_host).total;
+    *bytes_out = std::max(workspace_layout(n_pairs, T, 0, pairs_host).total, ob);
     return SP_OK;
 }
 
@@ -390,9 +447,22 @@ synthpix_status synthpix_seed(const synthpix_pair* pairs_host, const synthpix_pa
     return SP_OK;
 }
 
+synthpix_status synthpix_advect_workspace_size(const synthpix_pair* pairs_host, int32_t n_pairs, size_t* bytes_out)
+{
+    if (!bytes_out) return fail(SP_ERR_INVALID_ARG, "bytes_out must be non-NULL");
+    int64_t span;
+    synthpix_status st = check_pairs(pairs_host, pairs_host, n_pairs, &span);
+    if (st) return st;
+    const size_t b = order_bytes(pairs_host, n_pairs);
+    if (!b) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
+    *bytes_out = b;
+    return SP_OK;
+}
+
 synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev, int32_t n_pairs,
                                 const float* flow, const synthpix_advect_params* ap, const float* x1,
-                                const float* y1, float* x2, float* y2, void* stream)
+                                const float* y1, float* x2, float* y2, void* workspace, size_t ws_bytes,
+                                void* stream)
 {
     int64_t span;
     synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
@@ -402,7 +472,18 @@ synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_
     if (!dev_ptr_ok(x1) || !dev_ptr_ok(y1) || !dev_ptr_ok(x2) || !dev_ptr_ok(y2))
         return fail(SP_ERR_INVALID_ARG, "x1, y1, x2, y2 must be non-NULL, 4-byte aligned device pointers");
     if (x1 == x2 || y1 == y2) return fail(SP_ERR_INVALID_ARG, "x2/y2 must not alias x1/y1");
-    const hipError_t e = sp::launch_advect(pairs_dev, n_pairs, span, flow, *ap, x1, y1, x2, y2, as_stream(stream));
+    sp::AdvectOrder order{nullptr, nullptr};
+    if (workspace) {
+        if (!aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+        const size_t need = order_bytes(pairs_host, n_pairs);
+        if (!need) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
+        if (ws_bytes < need) return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+        const hipError_t e = enqueue_order(pairs_host, pairs_dev, n_pairs, x1, y1, static_cast<char*>(workspace), 0,
+                                           as_stream(stream), &order);
+        if (e != hipSuccess) return hip_fail(e, "advect order launch");
+    }
+    const hipError_t e = sp::launch_advect(pairs_dev, n_pairs, span, flow, *ap, x1, y1, x2, y2, as_stream(stream),
+                                           order);
     if (e != hipSuccess) return hip_fail(e, "advect launch");
     return SP_OK;
 }
@@ -464,11 +545,20 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
         return fail(SP_ERR_INVALID_ARG, "gradient outputs must be non-NULL, 4-byte aligned device pointers");
     const int64_t n_flow = flow_span(pairs_host, n_pairs);
     const BwdLayout wl = bwd_layout(span, n_flow);
+    const size_t ob = order_bytes(pairs_host, n_pairs);
+    if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    if (ws_bytes < wl.total)
-        return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, wl.total);
+    if (ws_bytes < wl.total + ob)
+        return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, wl.total + ob);
     char* ws = static_cast<char*>(workspace);
+    sp::AdvectOrder a_order_tmp{nullptr, nullptr};
+    {
+        const hipError_t e = enqueue_order(pairs_host, pairs_dev, n_pairs, x1, y1, ws, wl.total, as_stream(stream),
+                                           &a_order_tmp);
+        if (e != hipSuccess) return hip_fail(e, "backward order launch");
+    }
     sp::BwdArgs a{};
+    a.order = a_order_tmp;
     a.pairs = pairs_dev;
     a.n_pairs = n_pairs;
     a.flow = flow;
@@ -535,8 +625,12 @@ hipError_t enqueue_batch(synthpix_plan* P, const synthpix_tiling& t, hipStream_t
     hipError_t e = sp::launch_seed(P->pairs_dev, P->n_pairs, P->span, P->sp, P->seed, P->io.x1, P->io.y1, P->io.z,
                                    P->io.d, P->io.I0, P->io.n_active, P->io.ppp, s);
     if (e != hipSuccess) return e;
+    sp::AdvectOrder order{nullptr, nullptr};
+    e = enqueue_order(P->pairs_host.data(), P->pairs_dev, P->n_pairs, P->io.x1, P->io.y1,
+                      static_cast<char*>(P->workspace), 0, s, &order);
+    if (e != hipSuccess) return e;
     e = sp::launch_advect(P->pairs_dev, P->n_pairs, P->span, P->io.flow, P->ap, P->io.x1, P->io.y1, P->io.x2,
-                          P->io.y2, s);
+                          P->io.y2, s, order);
     if (e != hipSuccess) return e;
     const sp::RenderConfig cfg = make_config(P->rp, t);
     sp::BatchTotals T;
@@ -623,7 +717,7 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
     }
     // workspace for the largest candidate
     std::vector<synthpix_tiling> cands = autotune ? tiling_candidates(*rp) : std::vector<synthpix_tiling>{t0};
-    size_t ws = 0;
+    size_t ws = order_bytes(pairs_host, n_pairs);   // the advection order shares the render workspace
     std::vector<synthpix_tiling> ok;
     for (const auto& t : cands) {
         sp::BatchTotals T;

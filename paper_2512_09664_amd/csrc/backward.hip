@@ -407,12 +407,18 @@ template <int CK, int SK>
 __global__ void __launch_bounds__(256)
 bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
 {
-    const int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (g >= n_span) return;
     const int p = find_pair_by_particle(a.pairs, a.n_pairs, g);
     const synthpix_pair P = a.pairs[p];
-    const int64_t i = g - P.particle_offset;
+    int64_t i = g - P.particle_offset;
     if (i < 0 || i >= P.n_max) return;
+    // slots follow the home-block order when one is given: neighbouring lanes then
+    // sample, and add into, neighbouring grid cells
+    if (a.order.entries) {
+        i = a.order.entries[a.order.L[p].entry_base + i];
+        g = P.particle_offset + i;
+    }
     float gpx = a.gx2[g], gpy = a.gy2[g];
     const float px = a.x1[g], py = a.y1[g];
     if ((gpx == 0.0f && gpy == 0.0f) || !__builtin_isfinite(px) || !__builtin_isfinite(py)) return;
@@ -607,7 +613,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.status, a.scale);
     }
     if (n_span > 0) {
-        hipError_t e = launch_advect(a.pairs, a.n_pairs, n_span, a.flow, ap, a.x1, a.y1, a.x2, a.y2, s);
+        hipError_t e = launch_advect(a.pairs, a.n_pairs, n_span, a.flow, ap, a.x1, a.y1, a.x2, a.y2, s, a.order);
         if (e != hipSuccess) return e;
         const unsigned gb = (unsigned)((n_span + BPW - 1) / BPW);
         {

@@ -188,6 +188,50 @@ bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__
     }
 }
 
+// ------------------------------------------------------------------ home order
+
+// A spatial processing order for per-particle work that samples the flow grid:
+// particle i of a pair goes to the block (a "tile" of the order's config) that
+// holds its clamped position; blocks are listed row-major, so consecutive
+// entries are particles close together.  Count and scatter passes as for the
+// tile lists, one entry per particle, in the frame-1 half of the lists.
+__device__ __forceinline__ int home_block(float x, float y, int W, int H, const PairLayout& PL,
+                                          const RenderConfig& cfg)
+{
+    const int cx = !(x >= 0.0f) ? 0 : (x >= (float)W ? W - 1 : (int)x);
+    const int cy = !(y >= 0.0f) ? 0 : (y >= (float)H ? H - 1 : (int)y);
+    return (cy >> cfg.log_th) * PL.ntx + (cx >> cfg.log_tw);
+}
+
+template <bool SCATTER>
+__global__ void __launch_bounds__(256)
+order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
+           const float* __restrict__ x, const float* __restrict__ y, RenderConfig cfg, uint32_t* __restrict__ hist,
+           int32_t* __restrict__ entries, unsigned n_chunks_total)
+{
+    extern __shared__ uint32_t lh[];
+    const unsigned cb = xcd_contiguous(blockIdx.x, n_chunks_total);
+    const int p = find_pair_by_chunk(L, n_pairs, cb);
+    const synthpix_pair P = pairs[p];
+    const PairLayout PL = L[p];
+    const int chunk = (int)cb - PL.chunk_base;
+    const int nt = PL.ntx * PL.nty;
+    uint32_t* gh = hist + PL.hist_base + (int64_t)chunk * nt;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = SCATTER ? gh[t] : 0u;
+    __syncthreads();
+    const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
+    int32_t* seg = entries + PL.entry_base;
+    for (int i = chunk * cfg.chunk + threadIdx.x; i < i_end; i += blockDim.x) {
+        const int64_t g = P.particle_offset + i;
+        const uint32_t slot = atomicAdd(&lh[home_block(x[g], y[g], P.W, P.H, PL, cfg)], 1u);
+        if (SCATTER) seg[slot] = i;
+    }
+    if (!SCATTER) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < nt; t += blockDim.x) gh[t] = lh[t];
+    }
+}
+
 // Per (pair, frame): tile totals, exclusive tile offsets (within the pair-frame
 // segment) and, in place, each chunk's starting slot inside every tile list.
 __global__ void __launch_bounds__(256)
@@ -627,6 +671,29 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
         return hipErrorInvalidValue;
 #undef SP_SHAPE
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float* x, const float* y,
+                        const RenderConfig& cfg, const BatchTotals& tot, char* ws, const OrderLayout& ol,
+                        hipStream_t s)
+{
+    uint32_t* status = reinterpret_cast<uint32_t*>(ws + ol.status);
+    PairLayout* L = reinterpret_cast<PairLayout*>(ws + ol.layout);
+    uint32_t* tile_count = reinterpret_cast<uint32_t*>(ws + ol.tile_count);
+    int64_t* tile_offset = reinterpret_cast<int64_t*>(ws + ol.tile_offset);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(ws + ol.hist);
+    int32_t* entries = reinterpret_cast<int32_t*>(ws + ol.entries);
+    TimedScope ts("order", s);
+    hipLaunchKernelGGL(bin_layout, dim3(1), dim3(256), 0, s, pairs_dev, n_pairs, cfg, L, status);
+    if (tot.chunks == 0) return hipGetLastError();
+    const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
+    hipLaunchKernelGGL(order_pass<false>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
+                       y, cfg, hist, entries, (unsigned)tot.chunks);
+    hipLaunchKernelGGL(bin_scan, dim3((unsigned)n_pairs, 1), dim3(256), 0, s, L, hist, tile_count, tile_offset,
+                       tot.tiles);
+    hipLaunchKernelGGL(order_pass<true>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
+                       y, cfg, hist, entries, (unsigned)tot.chunks);
     return hipGetLastError();
 }
 

@@ -70,6 +70,22 @@ struct WorkspaceLayout {
     size_t total;
 };
 
+// Workspace of the spatial order used by the advection kernels: a pair layout,
+// per-block counts and offsets, per-chunk histograms and one entry per particle.
+struct OrderLayout {
+    size_t status, layout, tile_count, tile_offset, hist, entries, total;
+};
+
+hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float* x, const float* y,
+                        const RenderConfig& cfg, const BatchTotals& tot, char* ws, const OrderLayout& ol,
+                        hipStream_t s);
+
+// The order a launch of the advection kernel follows (null: particle index order).
+struct AdvectOrder {
+    const PairLayout* L;
+    const int32_t* entries;
+};
+
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
                        const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
                        float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s);
@@ -78,7 +94,7 @@ hipError_t launch_advance(synthpix_pair* pairs_dev, int n_pairs, uint64_t step, 
 
 hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
                          const synthpix_advect_params& ap, const float* x1, const float* y1, float* x2,
-                         float* y2, hipStream_t s);
+                         float* y2, hipStream_t s, AdvectOrder order = AdvectOrder{nullptr, nullptr});
 
 struct RenderArgs {
     const synthpix_pair* pairs;
@@ -113,6 +129,7 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
 
 // Everything the backward kernels read and write.
 struct BwdArgs {
+    AdvectOrder order;           // home-block order of the frame-1 positions
     const synthpix_pair* pairs;
     int n_pairs;
     const float* flow;

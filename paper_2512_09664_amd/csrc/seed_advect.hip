@@ -148,21 +148,25 @@ __device__ __forceinline__ void integrate_n(const FlowView* fv, float* px, float
 
 constexpr int ADVECT_ILP = 2;
 
+// SORTED: thread slots follow the home-block order (neighbouring lanes sample
+// neighbouring grid cells, so the bilinear gathers share cache lines); each
+// slot reads its particle index from the order's entry list.
+template <bool SORTED>
 __global__ void __launch_bounds__(256)
 advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span,
               const float* __restrict__ flow, synthpix_advect_params ap,
               const float* __restrict__ x1, const float* __restrict__ y1,
-              float* __restrict__ x2, float* __restrict__ y2)
+              float* __restrict__ x2, float* __restrict__ y2, AdvectOrder order)
 {
     // consecutive particle blocks (same pair, same flow grid) stay on one XCD
     const int64_t base = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * (256 * ADVECT_ILP) + threadIdx.x;
     FlowView fv[ADVECT_ILP];
     float px[ADVECT_ILP], py[ADVECT_ILP];
-    bool live[ADVECT_ILP];
+    int64_t gi[ADVECT_ILP];
 #pragma unroll
     for (int q = 0; q < ADVECT_ILP; ++q) {
         const int64_t g = base + 256 * q;
-        live[q] = false;
+        gi[q] = -1;
         px[q] = py[q] = 0.0f;
         fv[q] = FlowView{reinterpret_cast<const float2*>(flow), 2, 2, 1.0f, 1.0f};
         if (g < n_span) {
@@ -170,19 +174,19 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
             const synthpix_pair P = pairs[p];
             const int64_t i = g - P.particle_offset;
             if (i >= 0 && i < P.n_max) {
-                live[q] = true;
+                gi[q] = SORTED ? P.particle_offset + order.entries[order.L[p].entry_base + i] : g;
                 fv[q] = flow_view(P, flow);
-                px[q] = x1[g];
-                py[q] = y1[g];
+                px[q] = x1[gi[q]];
+                py[q] = y1[gi[q]];
             }
         }
     }
     integrate_n<ADVECT_ILP>(fv, px, py, ap.dt, ap.substeps, ap.integrator);
 #pragma unroll
     for (int q = 0; q < ADVECT_ILP; ++q) {
-        if (live[q]) {
-            x2[base + 256 * q] = px[q];
-            y2[base + 256 * q] = py[q];
+        if (gi[q] >= 0) {
+            x2[gi[q]] = px[q];
+            y2[gi[q]] = py[q];
         }
     }
 }
@@ -220,13 +224,17 @@ hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_sp
 
 hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
                          const synthpix_advect_params& ap, const float* x1, const float* y1, float* x2,
-                         float* y2, hipStream_t s)
+                         float* y2, hipStream_t s, AdvectOrder order)
 {
     if (n_span <= 0) return hipSuccess;
     const int64_t blocks = (n_span + 256 * ADVECT_ILP - 1) / (256 * ADVECT_ILP);
     TimedScope ts("advect", s);
-    hipLaunchKernelGGL(advect_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
-                       flow, ap, x1, y1, x2, y2);
+    if (order.entries)
+        hipLaunchKernelGGL(advect_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
+                           flow, ap, x1, y1, x2, y2, order);
+    else
+        hipLaunchKernelGGL(advect_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
+                           flow, ap, x1, y1, x2, y2, order);
     return hipGetLastError();
 }
 

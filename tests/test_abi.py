@@ -129,13 +129,24 @@ def test_advect_and_render_validation(L):
     fake = ctypes.c_void_p(0x1000)
     ap = L.AdvectParams(1.0, 0, 1)
     assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
-                               ctypes.c_void_p(0x3000), None) == L.SP_ERR_INVALID_ARG
+                               ctypes.c_void_p(0x3000), None, 0, None) == L.SP_ERR_INVALID_ARG
     ap = L.AdvectParams(1.0, 4, 7)
     assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
-                               ctypes.c_void_p(0x3000), None) == L.SP_ERR_INVALID_ARG
+                               ctypes.c_void_p(0x3000), None, 0, None) == L.SP_ERR_INVALID_ARG
     ap = L.AdvectParams(1.0, 4, 1)
     assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, fake, ctypes.c_void_p(0x3000),
-                               None) == L.SP_ERR_INVALID_ARG   # aliasing
+                               None, 0, None) == L.SP_ERR_INVALID_ARG   # aliasing
+    n = ctypes.c_size_t()
+    assert lib.synthpix_advect_workspace_size(pairs, 1, ctypes.byref(n)) == 0 and n.value >= 4 * 100
+    assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
+                               ctypes.c_void_p(0x3000), ctypes.c_void_p(0x10000), n.value - 1,
+                               None) == L.SP_ERR_WORKSPACE
+    assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
+                               ctypes.c_void_p(0x3000), ctypes.c_void_p(0x10010), n.value,
+                               None) == L.SP_ERR_WORKSPACE
+    wsz = ctypes.c_size_t()
+    assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(_rp(L)), None, 0, ctypes.byref(wsz)) == 0
+    assert wsz.value >= n.value
     # workspace too small / misaligned
     rp = _rp(L)
     st = lib.synthpix_render_pair(pairs, fake, 1, None, fake, fake, fake, fake, fake, fake, fake, ctypes.byref(rp),

@@ -85,7 +85,10 @@ def test_advect_matches_oracle(ra, integ, n, dt):
     x1 = gu.to_dev(np.concatenate([q["x"] for q in parts]))
     y1 = gu.to_dev(np.concatenate([q["y"] for q in parts]))
     x2, y2 = sp.advect(b, flow, sp.advect_params(dt, n, integ), x1, y1)
+    ux2, uy2 = sp.advect(b, flow, sp.advect_params(dt, n, integ), x1, y1, ordered=False)
     torch.cuda.synchronize()
+    # the home-block order changes which thread moves which particle, nothing else
+    assert torch.equal(x2, ux2) and torch.equal(y2, uy2)
     gx, gy = gu.to_np(x2), gu.to_np(y2)
     for p, sl in enumerate(gu.pair_slices(b)):
         H, W = sizes[p]
@@ -96,6 +99,32 @@ def test_advect_matches_oracle(ra, integ, n, dt):
         # start value's own spacing
         tol = (4 + 2 * n) * float(np.spacing(np.float32(max(np.abs(ox).max(), np.abs(oy).max()))))
         assert np.max(np.abs(gx[sl] - ox)) <= tol and np.max(np.abs(gy[sl] - oy)) <= tol
+
+
+def test_advect_order_with_large_pairs(ra):
+    """Pairs large enough that the home blocks grow past 32 px (8192^2 and
+    16384 x 1024), between small ones;
+    ordered and index-order launches agree with the mirror bit for bit."""
+    sizes = [(33, 17), (8192, 8192), (16384, 1024), (64, 64)]
+    rng = np.random.default_rng(9)
+    fl = [wflows.fourier_grid(rng, H, W, 9, 7, max_disp=5.0) for (H, W) in sizes]
+    n = [200, 6000, 3000, 500]
+    parts = [particles.random_particles(40 + p, n[p], H, W, pad=6) for p, (H, W) in enumerate(sizes)]
+    _say("advect order, large pairs")
+    b = gu.batch_for(sizes, [f.shape[:2] for f in fl], n)
+    flow = gu.to_dev(np.concatenate([f.reshape(-1) for f in fl]))
+    x1 = gu.to_dev(np.concatenate([q["x"] for q in parts]))
+    y1 = gu.to_dev(np.concatenate([q["y"] for q in parts]))
+    ap = sp.advect_params(1.0, 2, "rk4")
+    x2, y2 = sp.advect(b, flow, ap, x1, y1)
+    ux2, uy2 = sp.advect(b, flow, ap, x1, y1, ordered=False)
+    torch.cuda.synchronize()
+    assert torch.equal(x2, ux2) and torch.equal(y2, uy2)
+    gx, gy = gu.to_np(x2), gu.to_np(y2)
+    for p, sl in enumerate(gu.pair_slices(b)):
+        H, W = sizes[p]
+        rx, ry = ra.advect(fl[p], H, W, parts[p]["x"], parts[p]["y"], 1.0, 2, "rk4")
+        assert np.array_equal(gx[sl], rx) and np.array_equal(gy[sl], ry), p
 
 
 # ----------------------------------------------------------------------------- render

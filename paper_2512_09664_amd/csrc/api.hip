@@ -189,10 +189,10 @@ int64_t flow_span(const synthpix_pair* ph, int32_t n_pairs)
 
 // Backward workspace: particle-major, no bins.
 struct BwdLayout {
-    size_t status, scale, x2, y2, gx2, gy2, sheet, fixed, total;
+    size_t status, scale, x2, y2, gx2, gy2, sheet, sheet_part, bound_part, fixed, total;
 };
 
-BwdLayout bwd_layout(int64_t n_span, int64_t n_flow)
+BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs)
 {
     BwdLayout w{};
     size_t o = 0;
@@ -204,6 +204,8 @@ BwdLayout bwd_layout(int64_t n_span, int64_t n_flow)
     w.gx2 = o; o = align256(o + nf);
     w.gy2 = o; o = align256(o + nf);
     w.sheet = o; o = align256(o + nf);
+    w.sheet_part = o; o = align256(o + sizeof(double) * sp::BWD_SLICES * (size_t)n_pairs);
+    w.bound_part = o; o = align256(o + sizeof(float) * 2 * sp::BWD_SLICES * (size_t)n_pairs);
     w.fixed = o; o = align256(o + sizeof(uint64_t) * (size_t)n_flow);
     w.total = o;
     return w;
@@ -354,7 +356,7 @@ synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t
     const size_t ob = order_bytes(pairs_host, n_pairs);
     if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (backward) {
-        *bytes_out = bwd_layout(span, flow_span(pairs_host, n_pairs)).total + ob;
+        *bytes_out = bwd_layout(span, flow_span(pairs_host, n_pairs), n_pairs).total + ob;
         return SP_OK;
     }
     const sp::RenderConfig cfg = make_config(*rp, t);
@@ -544,7 +546,7 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
         !dev_ptr_ok(g_sheet) || !dev_ptr_ok(g_flow))
         return fail(SP_ERR_INVALID_ARG, "gradient outputs must be non-NULL, 4-byte aligned device pointers");
     const int64_t n_flow = flow_span(pairs_host, n_pairs);
-    const BwdLayout wl = bwd_layout(span, n_flow);
+    const BwdLayout wl = bwd_layout(span, n_flow, n_pairs);
     const size_t ob = order_bytes(pairs_host, n_pairs);
     if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -580,6 +582,8 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.gx2 = reinterpret_cast<float*>(ws + wl.gx2);
     a.gy2 = reinterpret_cast<float*>(ws + wl.gy2);
     a.sheet = reinterpret_cast<float*>(ws + wl.sheet);
+    a.sheet_part = reinterpret_cast<double*>(ws + wl.sheet_part);
+    a.bound_part = reinterpret_cast<float*>(ws + wl.bound_part);
     a.fixed = reinterpret_cast<unsigned long long*>(ws + wl.fixed);
     a.scale = reinterpret_cast<uint32_t*>(ws + wl.scale);
     a.status = reinterpret_cast<uint32_t*>(ws + wl.status);

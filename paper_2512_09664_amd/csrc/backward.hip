@@ -79,17 +79,22 @@ bwd_gather(BwdArgs a, int64_t n_span)
 {
     __shared__ GatherLds<BT> S;
     const int grp = threadIdx.x / BG, lane = threadIdx.x % BG;
-    const int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * BPW + grp;
+    const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * BPW;
+    int64_t g = g0 + grp;
 
     bool in_pair = false, valid = false;
     int H = 1, W = 1;
     int64_t img = 0;
     float z = 0.0f, d = 1.0f, I0 = 0.0f;
     if (g < n_span) {
-        const int p = find_pair_by_particle(a.pairs, a.n_pairs, g);
+        const int p = find_pair_from(a.pairs, a.n_pairs, g0, g);
         const synthpix_pair P = a.pairs[p];
-        const int64_t i = g - P.particle_offset;
+        int64_t i = g - P.particle_offset;
         if (i >= 0 && i < P.n_max) {
+            // slots follow the home-block order: neighbouring groups read
+            // overlapping rows of dL/dJ
+            if (a.order.entries) i = a.order.entries[a.order.L[p].entry_base + i];
+            g = P.particle_offset + i;
             in_pair = true;
             H = P.H;
             W = P.W;
@@ -176,7 +181,10 @@ bwd_gather(BwdArgs a, int64_t n_span)
             __syncthreads();
         }
 
-        // gather: sum_q (dL/dJ)_q Ty(r) Tx(c) over the blurred support, inside the image
+        // gather: sum_q (dL/dJ)_q Ty(r) Tx(c) over the blurred support, inside the
+        // image.  The column factors are constant along a lane's column, so each
+        // lane first forms P_j = sum_r (dL/dJ) Ty_j(r) down its column(s) (three
+        // FMAs per pixel) and applies Tx afterwards.
         float s0 = 0.0f, s_x = 0.0f, s_y = 0.0f, s_r = 0.0f;
         if (on) {
             const int nt = (c1 - c0 + 1) + 2 * B, nu = (r1 - r0 + 1) + 2 * B;
@@ -187,8 +195,8 @@ bwd_gather(BwdArgs a, int64_t n_span)
             const float* __restrict__ gimg = a.grad + img + (int64_t)f * H * W;
             const float(*T)[BT] = B > 0 ? S.tx[grp] : S.rx[grp];
             for (int t = tlo + lane; t < thi; t += BG) {
-                const float X0 = T[0][t], X1 = T[1][t], X2 = T[2][t];
                 const float* __restrict__ col = gimg + (int64_t)(r0 - B) * W + (c0 - B + t);
+                float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
                 for (int u = ulo; u < uhi; u += GROWS) {
                     // GROWS loads issued together; rows past the patch re-read its last
                     // row and are weighted by zero
@@ -203,14 +211,16 @@ bwd_gather(BwdArgs a, int64_t n_span)
                         const int uu = u + k < uhi ? u + k : uhi - 1;
                         const float4 ty = S.ty[grp][uu];
                         const float ek = u + k < uhi ? e[k] : 0.0f;
-                        const float a0 = ty.x * ek, a1 = ty.y * ek, a2 = ty.z * ek;
-                        s0 = __builtin_fmaf(a0, X0, s0);
-                        s_x = __builtin_fmaf(a0, X1, s_x);
-                        s_y = __builtin_fmaf(a1, X0, s_y);
-                        s_r = __builtin_fmaf(a0, X2, s_r);
-                        s_r = __builtin_fmaf(a2, X0, s_r);
+                        P0 = __builtin_fmaf(ty.x, ek, P0);
+                        P1 = __builtin_fmaf(ty.y, ek, P1);
+                        P2 = __builtin_fmaf(ty.z, ek, P2);
                     }
                 }
+                const float X0 = T[0][t], X1 = T[1][t], X2 = T[2][t];
+                s0 = __builtin_fmaf(P0, X0, s0);
+                s_x = __builtin_fmaf(P0, X1, s_x);
+                s_y = __builtin_fmaf(P1, X0, s_y);
+                s_r = __builtin_fmaf(P0, X2, __builtin_fmaf(P2, X0, s_r));
             }
         }
         sum0 += group_sum(s0);
@@ -313,20 +323,31 @@ struct NodeRun {
     int64_t base;         // element offset of the pair's grid
     int Gw;
     double scale;         // 2^e; 0 when the flow gradient is not accumulated
+    // the workgroup's LDS window of node sums (rows wi0 .., cols wj0 .., wh x ww
+    // nodes, (u, v) interleaved); nodes outside it go to global memory
+    unsigned long long* win;
+    int wi0, wj0, wh, ww;
+
+    __device__ void add_node(int ni, int nj, int c, unsigned long long q)
+    {
+        const int li = ni - wi0, lj = nj - wj0;
+        if ((unsigned)li < (unsigned)wh && (unsigned)lj < (unsigned)ww)
+            atomicAdd(win + 2 * (li * ww + lj) + c, q);
+        else
+            atomicAdd(fixed + base + 2 * ((int64_t)ni * Gw + nj) + c, q);
+    }
 
     __device__ void flush(const CellRun& r)
     {
         if (r.i0 < 0) return;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            const int64_t e = base + 2 * ((int64_t)(r.i0 + (n >> 1)) * Gw + (r.j0 + (n & 1)));
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const float v = r.acc[2 * n + c];
-                if (v != 0.0f) {
-                    const long long q = (long long)__builtin_rint((double)v * scale);
-                    atomicAdd(fixed + e + c, (unsigned long long)q);
-                }
+                if (v != 0.0f)
+                    add_node(r.i0 + (n >> 1), r.j0 + (n & 1), c,
+                             (unsigned long long)(long long)__builtin_rint((double)v * scale));
             }
         }
     }
@@ -403,95 +424,225 @@ enum { SC_NONE = 0, SC_VALID = 1, SC_NONFINITE = 2 };
 // g_y1) and node sums into the fixed-point grid.  CK checkpoints of the
 // trajectory are kept, one every L = ceil(substeps / CK) substeps; each segment
 // is recomputed into SK >= L slots during the sweep.
+constexpr int WIN_NODES = 2048;   // LDS window capacity (nodes; 32 KB of (u, v) sums)
+constexpr int WIN_MARGIN = 3;     // cells added around the particles' starting cells
+
 template <int CK, int SK>
 __global__ void __launch_bounds__(256)
 bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
 {
-    int64_t g = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    if (g >= n_span) return;
-    const int p = find_pair_by_particle(a.pairs, a.n_pairs, g);
-    const synthpix_pair P = a.pairs[p];
-    int64_t i = g - P.particle_offset;
-    if (i < 0 || i >= P.n_max) return;
-    // slots follow the home-block order when one is given: neighbouring lanes then
-    // sample, and add into, neighbouring grid cells
-    if (a.order.entries) {
-        i = a.order.entries[a.order.L[p].entry_base + i];
-        g = P.particle_offset + i;
+    __shared__ unsigned long long win[2 * WIN_NODES];
+    __shared__ int s_box[4][4];
+    __shared__ int s_pair;
+    const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256;
+    int64_t g = g0 + threadIdx.x;
+    int p = -1;
+    synthpix_pair P{};
+    bool live = false;
+    float gpx = 0.0f, gpy = 0.0f, px = 0.0f, py = 0.0f;
+    if (g < n_span) {
+        p = find_pair_from(a.pairs, a.n_pairs, g0, g);
+        P = a.pairs[p];
+        int64_t i = g - P.particle_offset;
+        if (i >= 0 && i < P.n_max) {
+            // slots follow the home-block order when one is given: neighbouring lanes
+            // then sample, and add into, neighbouring grid cells
+            if (a.order.entries) {
+                i = a.order.entries[a.order.L[p].entry_base + i];
+                g = P.particle_offset + i;
+            }
+            gpx = a.gx2[g];
+            gpy = a.gy2[g];
+            px = a.x1[g];
+            py = a.y1[g];
+            live = (gpx != 0.0f || gpy != 0.0f) && __builtin_isfinite(px) && __builtin_isfinite(py);
+        } else {
+            p = -1;
+        }
     }
-    float gpx = a.gx2[g], gpy = a.gy2[g];
-    const float px = a.x1[g], py = a.y1[g];
-    if ((gpx == 0.0f && gpy == 0.0f) || !__builtin_isfinite(px) || !__builtin_isfinite(py)) return;
     NodeRun run;
     run.fixed = a.fixed;
-    run.base = P.flow_offset;
-    run.Gw = P.Gw;
+    run.base = live ? P.flow_offset : 0;
+    run.Gw = live ? P.Gw : 2;
     run.scale = a.scale[SC_STATE] == SC_VALID ? __builtin_ldexp(1.0, (int)a.scale[SC_EXP]) : 0.0;
-    const FlowView fv = flow_view(P, a.flow);
+    const FlowView fv = live ? flow_view(P, a.flow) : FlowView{reinterpret_cast<const float2*>(a.flow), 2, 2, 1.0f, 1.0f};
 
-    const int S = ap.substeps;
-    const float h = ap.dt / (float)S;
-    const float hh = h * 0.5f;
-    const int L = (S + CK - 1) / CK;
-    const int nseg = (S + L - 1) / L;
-    float cpx[CK], cpy[CK];
-    float qx = px, qy = py;
-    for (int s = 0; s < S; ++s) {
-        if (s % L == 0) {
-            cpx[s / L] = qx;
-            cpy[s / L] = qy;
-        }
-        if (s + 1 < S) substep(fv, qx, qy, h, hh, ap.integrator);
+    // window: the box of the starting cells of this workgroup's live particles of
+    // the first thread's pair, grown by a margin, if it fits
+    if (threadIdx.x == 0) s_pair = p;
+    __syncthreads();
+    const bool mine = live && p == s_pair;
+    int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -1, bj1 = -1;
+    if (mine) {
+        const float gx = __builtin_fminf(__builtin_fmaxf(px * fv.sx - 0.5f, 0.0f), (float)(fv.Gw - 1));
+        const float gy = __builtin_fminf(__builtin_fmaxf(py * fv.sy - 0.5f, 0.0f), (float)(fv.Gh - 1));
+        bj0 = bj1 = (int)gx;
+        bi0 = bi1 = (int)gy;
     }
-    float spx[SK], spy[SK];
-    for (int seg = nseg - 1; seg >= 0; --seg) {
-        const int s0 = seg * L;
-        const int len = (S - s0) < L ? (S - s0) : L;
-        spx[0] = cpx[seg];
-        spy[0] = cpy[seg];
-        for (int k = 1; k < len; ++k) {
-            float tx = spx[k - 1], ty = spy[k - 1];
-            substep(fv, tx, ty, h, hh, ap.integrator);
-            spx[k] = tx;
-            spy[k] = ty;
-        }
-        for (int k = len - 1; k >= 0; --k) substep_adjoint(fv, run, spx[k], spy[k], h, hh, ap.integrator, gpx, gpy);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        bi0 = min(bi0, __shfl_xor(bi0, o, 64));
+        bj0 = min(bj0, __shfl_xor(bj0, o, 64));
+        bi1 = max(bi1, __shfl_xor(bi1, o, 64));
+        bj1 = max(bj1, __shfl_xor(bj1, o, 64));
     }
-    run.finish();
-    a.g_x1[g] += gpx;
-    a.g_y1[g] += gpy;
+    if ((threadIdx.x & 63) == 0) {
+        s_box[threadIdx.x >> 6][0] = bi0;
+        s_box[threadIdx.x >> 6][1] = bj0;
+        s_box[threadIdx.x >> 6][2] = bi1;
+        s_box[threadIdx.x >> 6][3] = bj1;
+    }
+    __syncthreads();
+    bi0 = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0])) - WIN_MARGIN;
+    bj0 = min(min(s_box[0][1], s_box[1][1]), min(s_box[2][1], s_box[3][1])) - WIN_MARGIN;
+    bi1 = max(max(s_box[0][2], s_box[1][2]), max(s_box[2][2], s_box[3][2])) + WIN_MARGIN + 1;
+    bj1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3])) + WIN_MARGIN + 1;
+    const int wh = bi1 - bi0 + 1, ww = bj1 - bj0 + 1;
+    const bool use_win = run.scale != 0.0 && s_pair >= 0 && bi1 >= bi0 && (int64_t)wh * ww <= WIN_NODES;
+    run.win = win;
+    run.wi0 = bi0;
+    run.wj0 = bj0;
+    run.wh = (use_win && mine) ? wh : 0;   // lanes of another pair always go to global memory
+    run.ww = ww;
+    if (use_win) {
+        for (int k = threadIdx.x; k < 2 * wh * ww; k += 256) win[k] = 0ull;
+        __syncthreads();
+    }
+
+    if (live) {
+        const int S = ap.substeps;
+        const float h = ap.dt / (float)S;
+        const float hh = h * 0.5f;
+        const int L = (S + CK - 1) / CK;
+        const int nseg = (S + L - 1) / L;
+        float cpx[CK], cpy[CK];
+        float qx = px, qy = py;
+        for (int s = 0; s < S; ++s) {
+            if (s % L == 0) {
+                cpx[s / L] = qx;
+                cpy[s / L] = qy;
+            }
+            if (s + 1 < S) substep(fv, qx, qy, h, hh, ap.integrator);
+        }
+        float spx[SK], spy[SK];
+        for (int seg = nseg - 1; seg >= 0; --seg) {
+            const int s0 = seg * L;
+            const int len = (S - s0) < L ? (S - s0) : L;
+            spx[0] = cpx[seg];
+            spy[0] = cpy[seg];
+            for (int k = 1; k < len; ++k) {
+                float tx = spx[k - 1], ty = spy[k - 1];
+                substep(fv, tx, ty, h, hh, ap.integrator);
+                spx[k] = tx;
+                spy[k] = ty;
+            }
+            for (int k = len - 1; k >= 0; --k)
+                substep_adjoint(fv, run, spx[k], spy[k], h, hh, ap.integrator, gpx, gpy);
+        }
+        run.finish();
+        a.g_x1[g] += gpx;
+        a.g_y1[g] += gpy;
+    }
+    if (use_win) {
+        // window sums into the pair's grid (window nodes outside the grid hold no sums)
+        __syncthreads();
+        const synthpix_pair Q = a.pairs[s_pair];
+        for (int k = threadIdx.x; k < 2 * wh * ww; k += 256) {
+            const unsigned long long v = win[k];
+            if (v == 0ull) continue;
+            const int n = k >> 1, c = k & 1;
+            const int ni = bi0 + n / ww, nj = bj0 + n % ww;
+            if (ni < 0 || ni >= Q.Gh || nj < 0 || nj >= Q.Gw) continue;
+            atomicAdd(a.fixed + Q.flow_offset + 2 * ((int64_t)ni * Q.Gw + nj) + c, v);
+        }
+    }
 }
 
 // Inputs of the fixed-point scale: the largest |dL/dx2|, |dL/dy2| and a bound L
 // on the transposed velocity Jacobian's max-row-sum over every cell (the
 // bilinear x-derivative is a blend of the cell's two edge differences, so its
-// magnitude is at most the larger one).  Blocks (pair, slice); float bits of
+// magnitude is at most the larger one).  Also each slice's float64 sum of the
+// sheet-width terms, in a fixed order.  Blocks (pair, slice); float bits of
 // non-negative values order like unsigned integers.
+constexpr int BOUND_SLICES = BWD_SLICES;
+
 __global__ void __launch_bounds__(256)
 bwd_bounds(BwdArgs a)
 {
     const synthpix_pair P = a.pairs[blockIdx.x];
-    const int nsl = gridDim.y, sl = blockIdx.y;
+    const int sl = blockIdx.y;
     float gm = 0.0f;
-    for (int64_t i = (int64_t)sl * 256 + threadIdx.x; i < P.n_max; i += (int64_t)nsl * 256) {
+    double sh = 0.0;
+    for (int64_t i = (int64_t)sl * 256 + threadIdx.x; i < P.n_max; i += (int64_t)BOUND_SLICES * 256) {
         const int64_t g = P.particle_offset + i;
-        gm = __builtin_fmaxf(gm, __builtin_fmaxf(__builtin_fabsf(a.gx2[g]), __builtin_fabsf(a.gy2[g])));
-        if (!__builtin_isfinite(a.gx2[g]) || !__builtin_isfinite(a.gy2[g])) gm = __builtin_inff();
+        const float u = a.gx2[g], v = a.gy2[g];
+        gm = __builtin_fmaxf(gm, __builtin_fmaxf(__builtin_fabsf(u), __builtin_fabsf(v)));
+        if (!__builtin_isfinite(u) || !__builtin_isfinite(v)) gm = __builtin_inff();
+        sh += (double)a.sheet[g];
     }
     const float2* F = reinterpret_cast<const float2*>(a.flow + P.flow_offset);
     const float sx = (float)P.Gw / (float)P.W, sy = (float)P.Gh / (float)P.H;
-    const int64_t cells = (int64_t)(P.Gh - 1) * (P.Gw - 1);
     float lm = 0.0f;
-    for (int64_t k = (int64_t)sl * 256 + threadIdx.x; k < cells; k += (int64_t)nsl * 256) {
-        const int i = (int)(k / (P.Gw - 1)), j = (int)(k % (P.Gw - 1));
-        const float2 A = F[(int64_t)i * P.Gw + j], B = F[(int64_t)i * P.Gw + j + 1];
-        const float2 C = F[(int64_t)(i + 1) * P.Gw + j], E = F[(int64_t)(i + 1) * P.Gw + j + 1];
-        const float lx = sx * (__builtin_fmaxf(__builtin_fabsf(B.x - A.x), __builtin_fabsf(E.x - C.x)) +
-                               __builtin_fmaxf(__builtin_fabsf(B.y - A.y), __builtin_fabsf(E.y - C.y)));
-        const float ly = sy * (__builtin_fmaxf(__builtin_fabsf(C.x - A.x), __builtin_fabsf(E.x - B.x)) +
-                               __builtin_fmaxf(__builtin_fabsf(C.y - A.y), __builtin_fabsf(E.y - B.y)));
-        lm = __builtin_fmaxf(lm, __builtin_fmaxf(lx, ly));
-        if (!__builtin_isfinite(lx) || !__builtin_isfinite(ly)) lm = __builtin_inff();
+    for (int i = sl; i < P.Gh - 1; i += BOUND_SLICES)
+        for (int j = threadIdx.x; j < P.Gw - 1; j += 256) {
+            const float2 A = F[(int64_t)i * P.Gw + j], B = F[(int64_t)i * P.Gw + j + 1];
+            const float2 C = F[(int64_t)(i + 1) * P.Gw + j], E = F[(int64_t)(i + 1) * P.Gw + j + 1];
+            const float lx = sx * (__builtin_fmaxf(__builtin_fabsf(B.x - A.x), __builtin_fabsf(E.x - C.x)) +
+                                   __builtin_fmaxf(__builtin_fabsf(B.y - A.y), __builtin_fabsf(E.y - C.y)));
+            const float ly = sy * (__builtin_fmaxf(__builtin_fabsf(C.x - A.x), __builtin_fabsf(E.x - B.x)) +
+                                   __builtin_fmaxf(__builtin_fabsf(C.y - A.y), __builtin_fabsf(E.y - B.y)));
+            lm = __builtin_fmaxf(lm, __builtin_fmaxf(lx, ly));
+            if (!__builtin_isfinite(lx) || !__builtin_isfinite(ly)) lm = __builtin_inff();
+        }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        gm = __builtin_fmaxf(gm, __shfl_xor(gm, o, 64));
+        lm = __builtin_fmaxf(lm, __shfl_xor(lm, o, 64));
+    }
+    __shared__ float red[2][4];
+    __shared__ double sred[256];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = gm;
+        red[1][threadIdx.x >> 6] = lm;
+    }
+    sred[threadIdx.x] = sh;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // per-block results (no same-address atomics); bwd_scale reduces them
+        const int64_t k = (int64_t)blockIdx.x * BOUND_SLICES + sl;
+        a.bound_part[2 * k] = __builtin_fmaxf(__builtin_fmaxf(red[0][0], red[0][1]),
+                                              __builtin_fmaxf(red[0][2], red[0][3]));
+        a.bound_part[2 * k + 1] = __builtin_fmaxf(__builtin_fmaxf(red[1][0], red[1][1]),
+                                                  __builtin_fmaxf(red[1][2], red[1][3]));
+        a.sheet_part[k] = sred[0];
+    }
+}
+
+// The fixed-point exponent e.  Every upstream value k of the reverse sweep obeys
+// |k| <= K = G0 kfac growth^(S-1), from the stage recurrences with |J^T k| <= L |k|
+// (Euler: kfac = |h|, growth = 1 + |h| L; RK4: k4 = c, k3 = 2c + |h| L k4,
+// k2 = 2c + |h|/2 L k3, k1 = c + |h|/2 L k2 with c = |h|/6, growth = 1 + L sum k).
+// A node sum has at most 2^en such terms of weight <= 1, so with
+// e = 61 - ceil(log2 K) - en no partial sum leaves the int64 range.
+__global__ void __launch_bounds__(256)
+bwd_scale(uint32_t* __restrict__ sc, synthpix_advect_params ap, int en, const double* __restrict__ sheet_part,
+          const float* __restrict__ bound_part, int n_pairs, float* __restrict__ g_sheet)
+{
+    // per-pair sheet-width gradient: the slices' float64 sums in slice order
+    for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
+        double t = 0.0;
+        for (int k = 0; k < BOUND_SLICES; ++k) t += sheet_part[(int64_t)p * BOUND_SLICES + k];
+        g_sheet[p] = (float)t;
+    }
+    // maxima over all (pair, slice) blocks
+    float gm = 0.0f, lm = 0.0f;
+    for (int64_t k = threadIdx.x; k < (int64_t)n_pairs * BOUND_SLICES; k += blockDim.x) {
+        gm = __builtin_fmaxf(gm, bound_part[2 * k]);
+        lm = __builtin_fmaxf(lm, bound_part[2 * k + 1]);
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -504,25 +655,13 @@ bwd_bounds(BwdArgs a)
         red[1][threadIdx.x >> 6] = lm;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const float G = __builtin_fmaxf(__builtin_fmaxf(red[0][0], red[0][1]), __builtin_fmaxf(red[0][2], red[0][3]));
-        const float Lb = __builtin_fmaxf(__builtin_fmaxf(red[1][0], red[1][1]), __builtin_fmaxf(red[1][2], red[1][3]));
-        if (G != 0.0f) atomicMax(a.scale + SC_G2MAX, __float_as_uint(G));
-        if (Lb != 0.0f) atomicMax(a.scale + SC_LIP, __float_as_uint(Lb));
-    }
-}
-
-// The fixed-point exponent e.  Every upstream value k of the reverse sweep obeys
-// |k| <= K = G0 kfac growth^(S-1), from the stage recurrences with |J^T k| <= L |k|
-// (Euler: kfac = |h|, growth = 1 + |h| L; RK4: k4 = c, k3 = 2c + |h| L k4,
-// k2 = 2c + |h|/2 L k3, k1 = c + |h|/2 L k2 with c = |h|/6, growth = 1 + L sum k).
-// A node sum has at most 2^en such terms of weight <= 1, so with
-// e = 61 - ceil(log2 K) - en no partial sum leaves the int64 range.
-__global__ void bwd_scale(uint32_t* __restrict__ sc, synthpix_advect_params ap, int en)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double G0 = (double)__uint_as_float(sc[SC_G2MAX]);
-    const double L = (double)__uint_as_float(sc[SC_LIP]);
+    if (threadIdx.x != 0) return;
+    const double G0 = (double)__builtin_fmaxf(__builtin_fmaxf(red[0][0], red[0][1]),
+                                              __builtin_fmaxf(red[0][2], red[0][3]));
+    const double L = (double)__builtin_fmaxf(__builtin_fmaxf(red[1][0], red[1][1]),
+                                             __builtin_fmaxf(red[1][2], red[1][3]));
+    sc[SC_G2MAX] = __float_as_uint((float)G0);
+    sc[SC_LIP] = __float_as_uint((float)L);
     const int S = ap.substeps;
     const double h = __builtin_fabs((double)ap.dt / (double)S);
     double kfac, growth;
@@ -572,22 +711,6 @@ __global__ void bwd_flow_finish(const unsigned long long* __restrict__ fixed, in
         g_flow[k] = state == SC_VALID ? (float)((double)(long long)fixed[k] * inv) : fill;
 }
 
-// Per-pair sum of the sheet-width terms, in float64, in a fixed order.
-__global__ void __launch_bounds__(256)
-bwd_sheet(const synthpix_pair* __restrict__ pairs, const float* __restrict__ sheet, float* __restrict__ g_sheet)
-{
-    const synthpix_pair P = pairs[blockIdx.x];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < P.n_max; i += 256) s += (double)sheet[P.particle_offset + i];
-    __shared__ double red[256];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) g_sheet[blockIdx.x] = (float)red[0];
-}
 
 void launch_advect_adjoint(const BwdArgs& a, int64_t n_span, const synthpix_advect_params& ap, unsigned blocks,
                            hipStream_t s)
@@ -635,8 +758,9 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         }
         {
             TimedScope ts("bwd_bounds", s);
-            hipLaunchKernelGGL(bwd_bounds, dim3((unsigned)a.n_pairs, 16), dim3(256), 0, s, a);
-            hipLaunchKernelGGL(bwd_scale, dim3(1), dim3(64), 0, s, a.scale, ap, en);
+            hipLaunchKernelGGL(bwd_bounds, dim3((unsigned)a.n_pairs, BOUND_SLICES), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(bwd_scale, dim3(1), dim3(256), 0, s, a.scale, ap, en, a.sheet_part, a.bound_part,
+                               a.n_pairs, a.g_sheet);
         }
         {
             TimedScope ts("bwd_advect", s);
@@ -648,10 +772,6 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         const int64_t blocks = std::min<int64_t>((n_flow + 255) / 256 + 1, 8192);
         hipLaunchKernelGGL(bwd_flow_finish, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.scale,
                            a.g_flow);
-    }
-    {
-        TimedScope ts("bwd_sheet", s);
-        hipLaunchKernelGGL(bwd_sheet, dim3((unsigned)a.n_pairs), dim3(256), 0, s, a.pairs, a.sheet, a.g_sheet);
     }
     return hipGetLastError();
 }

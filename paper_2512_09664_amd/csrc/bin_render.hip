@@ -108,9 +108,10 @@ __global__ void __launch_bounds__(256)
 prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span, RenderArgs a,
              float d_max, float4* __restrict__ rec0, float4* __restrict__ rec1, uint32_t* __restrict__ status)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t g = g0 + threadIdx.x;
     if (g >= n_span) return;
-    const int p = find_pair_by_particle(pairs, n_pairs, g);
+    const int p = find_pair_from(pairs, n_pairs, g0, g);
     const int64_t i = g - pairs[p].particle_offset;
     if (i < 0 || i >= pairs[p].n_max) return;
     const float cs = 0.5f / (a.sheet_sigma * a.sheet_sigma);

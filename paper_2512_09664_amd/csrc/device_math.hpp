@@ -202,4 +202,15 @@ __device__ __forceinline__ int find_pair_by_particle(const synthpix_pair* pairs,
     return lo;
 }
 
+// Pair of particle g when g0 <= g is a particle index common to the whole
+// workgroup: the search for g0 is uniform (scalar loads), then each lane steps
+// forward over the few pair starts between g0 and g.
+__device__ __forceinline__ int find_pair_from(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t g0,
+                                              int64_t g)
+{
+    int p = find_pair_by_particle(pairs, n_pairs, g0);
+    while (p + 1 < n_pairs && pairs[p + 1].particle_offset <= g) ++p;
+    return p;
+}
+
 }  // namespace sp

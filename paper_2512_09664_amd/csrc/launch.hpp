@@ -127,6 +127,9 @@ bool render_shape_supported(int tile_w, int tile_h);
 hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot,
                          char* ws, const WorkspaceLayout& wl, hipStream_t s);
 
+// Particle slices per pair of the backward's bound and sheet-sum pass.
+constexpr int BWD_SLICES = 32;
+
 // Everything the backward kernels read and write.
 struct BwdArgs {
     AdvectOrder order;           // home-block order of the frame-1 positions
@@ -151,6 +154,8 @@ struct BwdArgs {
     float* gx2;                  // dL/dx2, dL/dy2 (workspace)
     float* gy2;
     float* sheet;                // per-particle sheet-width terms (workspace)
+    double* sheet_part;          // per (pair, slice) float64 sums of those terms (workspace)
+    float* bound_part;           // per (pair, slice) max |dL/dx2| and Lipschitz bound (workspace)
     unsigned long long* fixed;   // fixed-point flow-gradient sums (workspace, flow layout)
     uint32_t* scale;             // fixed-point scale block: max |dL/dx2|, Lipschitz bound, exponent, state
     uint32_t* status;

@@ -44,9 +44,10 @@ seed_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span
             float* __restrict__ x, float* __restrict__ y, float* __restrict__ z,
             float* __restrict__ d, float* __restrict__ I0)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t g = g0 + threadIdx.x;
     if (g >= n_span) return;
-    const int p = find_pair_by_particle(pairs, n_pairs, g);
+    const int p = find_pair_from(pairs, n_pairs, g0, g);
     const synthpix_pair P = pairs[p];
     const int64_t i64 = g - P.particle_offset;
     if (i64 < 0 || i64 >= P.n_max) return;
@@ -159,7 +160,8 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
               float* __restrict__ x2, float* __restrict__ y2, AdvectOrder order)
 {
     // consecutive particle blocks (same pair, same flow grid) stay on one XCD
-    const int64_t base = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * (256 * ADVECT_ILP) + threadIdx.x;
+    const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * (256 * ADVECT_ILP);
+    const int64_t base = g0 + threadIdx.x;
     FlowView fv[ADVECT_ILP];
     float px[ADVECT_ILP], py[ADVECT_ILP];
     int64_t gi[ADVECT_ILP];
@@ -170,7 +172,7 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
         px[q] = py[q] = 0.0f;
         fv[q] = FlowView{reinterpret_cast<const float2*>(flow), 2, 2, 1.0f, 1.0f};
         if (g < n_span) {
-            const int p = find_pair_by_particle(pairs, n_pairs, g);
+            const int p = find_pair_from(pairs, n_pairs, g0, g);
             const synthpix_pair P = pairs[p];
             const int64_t i = g - P.particle_offset;
             if (i >= 0 && i < P.n_max) {

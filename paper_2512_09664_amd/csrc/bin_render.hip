@@ -396,14 +396,19 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     for (int k = threadIdx.x; k < (lay.acc_words >> 2); k += 256)
         reinterpret_cast<uint4*>(acc)[k] = make_uint4(0u, 0u, 0u, 0u);
 
+    // the record of a thread's particle in the next pass is loaded one pass ahead,
+    // so its two dependent loads overlap the current pass's factor and splat work
+    float4 next = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
+    if ((int)threadIdx.x < min(cap, cnt)) next = rec[p_off + entries[off + threadIdx.x]];
     for (int base = 0; base < cnt; base += cap) {
         const int n = min(cap, cnt - base);
+        const float4 r = next;
+        if ((int)threadIdx.x < cap && base + cap + (int)threadIdx.x < cnt)
+            next = rec[p_off + entries[off + base + cap + threadIdx.x]];
         __syncthreads();
         // stage: one particle per thread
         int w = 0, h = 0, c0 = 0, r0 = 0;
         if ((int)threadIdx.x < n) {
-            const int idx = entries[off + base + threadIdx.x];
-            const float4 r = rec[p_off + idx];
             const float R = 1.5f * r.z;
             int a0, a1, b0, b1;
             if (support_range(r.x, R, pW, a0, a1) && support_range(r.y, R, pH, b0, b1)) {

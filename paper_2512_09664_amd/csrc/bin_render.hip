@@ -174,14 +174,27 @@ bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__
     const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
     const float4* __restrict__ rec = f ? rec1 : rec0;
     int32_t* seg = entries + PL.entry_base + (int64_t)f * PL.entry_cap;
-    for (int i = chunk * cfg.chunk + threadIdx.x; i < i_end; i += blockDim.x) {
-        int tx0, tx1, ty0, ty1;
-        if (!tile_rect(rec[P.particle_offset + i], P.H, P.W, cfg, PL.ntx, PL.nty, tx0, tx1, ty0, ty1)) continue;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
-                const uint32_t slot = atomicAdd(&lh[ty * PL.ntx + tx], 1u);
-                if (SCATTER) seg[slot] = i;
-            }
+    // BIN_ILP particles per thread and step: their record loads and LDS atomic
+    // round trips overlap
+    constexpr int BIN_ILP = 4;
+    for (int i0 = chunk * cfg.chunk + threadIdx.x; i0 < i_end; i0 += BIN_ILP * blockDim.x) {
+        float4 r[BIN_ILP];
+#pragma unroll
+        for (int q = 0; q < BIN_ILP; ++q) {
+            const int i = i0 + q * blockDim.x;
+            r[q] = i < i_end ? rec[P.particle_offset + i] : make_float4(0.0f, 0.0f, -1.0f, 0.0f);
+        }
+#pragma unroll
+        for (int q = 0; q < BIN_ILP; ++q) {
+            const int i = i0 + q * blockDim.x;
+            int tx0, tx1, ty0, ty1;
+            if (!tile_rect(r[q], P.H, P.W, cfg, PL.ntx, PL.nty, tx0, tx1, ty0, ty1)) continue;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    const uint32_t slot = atomicAdd(&lh[ty * PL.ntx + tx], 1u);
+                    if (SCATTER) seg[slot] = i;
+                }
+        }
     }
     if (!SCATTER) {
         __syncthreads();

@@ -89,6 +89,23 @@ def plan_throughput(sp, torch, np, dev, wl, flows, flow, batch, sprm, aprm, rprm
             "tiling": [t.tile_w, t.tile_h, t.chunk, t.cap]}
 
 
+def dense_throughput(sp, torch, np, dev, steps=10):
+    """dense_2048 (32 pairs of 2048^2, 0.1 ppp, d ~ U[2, 6], RK4 x 8, 5x5 blur,
+    noise 0.02, 12-bit) as one autotuned graph-captured plan."""
+    from workloads import get_workload
+    wl = get_workload("dense_2048")
+    flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
+    io = _plan_io(sp, torch, batch, flow, wl.bits, dev)
+    plan = sp.Plan(batch, sprm, wl.seed, aprm, rprm, io, autotune=True, advance_pair_ids=True)
+    t = plan.tiling
+    dt = _time_plan(torch, plan, steps)
+    plan.close()
+    del io
+    torch.cuda.empty_cache()
+    return {"pairs_per_s": round(wl.n_pairs / dt, 1), "gpx_per_s": round(wl.pixels() / dt / 1e9, 2),
+            "ms_per_step": round(1000 * dt, 4), "tiling": [t.tile_w, t.tile_h, t.chunk, t.cap]}
+
+
 def uneven_batched_vs_per_pair(sp, torch, np, dev, steps=5):
     """256 uneven pairs (256^2 .. 2048^2, ppp U[0.005, 0.1]): one graph-captured
     batch vs one launch sequence per pair."""
@@ -317,6 +334,8 @@ def main():
         log(f"[bench] uneven_256: {extras['uneven_256']}")
         extras["grad_512"] = gradient_cost(sp, torch, np, dev)
         log(f"[bench] grad_512: {extras['grad_512']}")
+        extras["dense_2048"] = dense_throughput(sp, torch, np, dev)
+        log(f"[bench] dense_2048: {extras['dense_2048']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -373,33 +373,35 @@ def test_diameter_above_max_is_flagged():
 
 # ----------------------------------------------------------------------------- full size, sampled
 
-def test_full_size_scale_1024_sampled(ra):
-    """The 64-pair 1024x1024 batch exactly as the benchmark launches it (noise on,
-    12-bit codes): sampled pixels against the float64 oracle computed one by one,
-    and two whole pairs bit-exact against the binary32 mirror with noise off."""
-    wl = get_workload("scale_1024")
+def _full_size_sampled(ra, wl, pairs, exact_pairs, per_frame=24, seed=0):
+    """A whole workload launched as the benchmark launches it (noise on, integer
+    codes): sampled pixels against the float64 oracle computed one by one, and
+    whole pairs bit-exact against the binary32 mirror with noise off."""
     batch, flows, P, x2, y2, img = gu.run_pipeline(wl)
     im = gu.to_np(img)
-    rng = np.random.default_rng(0)
-    w = oep.blur_weights(wl.blur_radius, wl.blur_sigma).astype(np.float64)
+    rng = np.random.default_rng(seed)
+    b = wl.blur_radius
+    w = oep.blur_weights(b, wl.blur_sigma).astype(np.float64)
     H, W = wl.sizes[0]
     plane = H * W
+    L = (1 << wl.bits) - 1
+    reach = 1.5 * wl.d_max + b + 2
     checked = 0
-    for p in (0, 17, 63):
+    for p in pairs:
         _say("full-size sampled pair", p)
         O = oseed.seed_pair(H, W, p, wl.seed, wl.ppp, wl.d_dist, wl.d_params, wl.I0, wl.z)
         ox2, oy2 = oadv.advect(flows[p], H, W, O["x"], O["y"], wl.dt, wl.substeps, wl.integrator)
         for f, (xx, yy) in enumerate(((O["x"], O["y"]), (ox2, oy2))):
             noise = oep.noise_normals(H, W, f, p, wl.seed)
-            for _ in range(24):
+            for _ in range(per_frame):
                 r, c = int(rng.integers(0, H)), int(rng.integers(0, W))
-                sel = (np.abs(xx - c) < 12) & (np.abs(yy - r) < 12)
+                sel = (np.abs(xx - c) < reach) & (np.abs(yy - r) < reach)
                 J = 0.0
-                for i in (-1, 0, 1):
-                    for j in (-1, 0, 1):
+                for i in range(-b, b + 1):
+                    for j in range(-b, b + 1):
                         rr, cc = r + i, c + j
                         if 0 <= rr < H and 0 <= cc < W:
-                            J += w[i + 1] * w[j + 1] * orend.render_pixel_direct(
+                            J += w[i + b] * w[j + b] * orend.render_pixel_direct(
                                 xx[sel], yy[sel], O["z"][sel], O["d"][sel], O["I0"][sel], rr, cc, wl.sheet_sigma)
                 K = J + wl.noise_sigma * noise[r, c]
                 q = int(oep.quantise(np.array([K]), wl.bits)[0])
@@ -408,13 +410,25 @@ def test_full_size_scale_1024_sampled(ra):
                 if abs(g - q) == 1:
                     # only next to a rounding boundary: float error budget 1e-5 of the
                     # noise term plus the render's 1e-6 of full scale
-                    bound = 4095 * (1e-5 * wl.noise_sigma * abs(noise[r, c]) + 1e-6)
-                    assert abs((K * 4095) % 1.0 - 0.5) <= bound, (p, f, r, c)
+                    bound = L * (1e-5 * wl.noise_sigma * abs(noise[r, c]) + 1e-6)
+                    assert abs((K * L) % 1.0 - 0.5) <= bound, (p, f, r, c)
                 checked += 1
-    assert checked == 3 * 2 * 24
+    assert checked == len(pairs) * 2 * per_frame
     # noise off: whole pairs bit-exact against the mirror
     batch, flows, P, x2, y2, img = gu.run_pipeline(wl, noise=0.0)
     im = gu.to_np(img)
-    for p in (0, 63):
+    for p in exact_pairs:
+        _say("full-size bit-exact pair", p)
         mir = ra.generate_pair_noiseless(wl, p, flows[p], H, W)
         assert np.array_equal(im[p * 2 * plane:(p + 1) * 2 * plane].reshape(2, H, W), mir["codes"]), p
+
+
+def test_full_size_scale_1024_sampled(ra):
+    """64 pairs of 1024x1024, 0.05 ppp, 3x3 blur, noise 0.01, 12-bit codes."""
+    _full_size_sampled(ra, get_workload("scale_1024"), (0, 17, 63), (0, 63))
+
+
+def test_full_size_dense_2048_sampled(ra):
+    """32 pairs of 2048x2048, 0.1 ppp, d ~ U[2, 6], RK4 x 8, 5x5 blur, noise 0.02,
+    12-bit codes: the dense stress configuration."""
+    _full_size_sampled(ra, get_workload("dense_2048"), (0, 31), (5,), per_frame=16, seed=1)

@@ -56,13 +56,19 @@ class PairBatch:
 
     @staticmethod
     def build(sizes: Sequence[Tuple[int, int]], grids: Sequence[Tuple[int, int]], n_max: Sequence[int],
-              pair_ids: Optional[Sequence[int]] = None, device="cuda") -> "PairBatch":
+              pair_ids: Optional[Sequence[int]] = None, device="cuda",
+              gaps: Tuple[int, int, int] = (0, 0, 0)) -> "PairBatch":
+        """Pairs packed in table order; ``gaps`` leaves that many unused particles,
+        image elements and flow floats (even) before every pair's range."""
+        if gaps[2] % 2:
+            raise ValueError("flow gaps must be even (one (u, v) node is two floats)")
         n = len(sizes)
         arr = (L.Pair * n)()
         po = io = fo = 0
         for p in range(n):
             H, W = sizes[p]
             Gh, Gw = grids[p]
+            po, io, fo = po + gaps[0], io + gaps[1], fo + gaps[2]
             arr[p].H, arr[p].W, arr[p].Gh, arr[p].Gw = int(H), int(W), int(Gh), int(Gw)
             arr[p].n_max = int(n_max[p])
             arr[p].reserved = 0

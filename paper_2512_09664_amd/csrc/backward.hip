@@ -36,7 +36,6 @@ template <int BT>
 struct GatherLds {
     float rx[BPW][3][BT];          // raw column factors gx dx^k, k = 0, 1, 2 (slot = c - c0 + 2b)
     float ry[BPW][3][BT];
-    float tx[BPW][3][BT];          // blurred column tables (slot = q - c0 + b)
     float4 ty[BPW][BT];            // blurred row tables (Ty0, Ty1, Ty2, 0)
 };
 
@@ -47,6 +46,16 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// A particle's lane group lies inside one wavefront and its LDS tables are
+// private to it, so the group synchronises with a wave-level fence instead of
+// a workgroup barrier (LDS operations of one wave complete in issue order).
+__device__ __forceinline__ void group_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ float group_sum(float v)
@@ -155,30 +164,25 @@ bwd_gather(BwdArgs a, int64_t n_span)
                 S.ry[grp][2][slot] = u2;
             }
         }
-        __syncthreads();
+        group_sync();
         if (B > 0) {
-            // table slot t is pixel c0 - b + t; raw slot t + 2b - k' holds pixel q - (k' - b)
+            // blurred row tables (the column ones are formed per column in the gather);
+            // table slot t is pixel r0 - b + t; raw slot t + 2b - k' holds pixel q - (k' - b)
 #pragma unroll
             for (int m = 0; m < BT / BG; ++m) {
                 const int t = lane + BG * m;
                 if (t < BT - 2 * B) {
-                    float X[3] = {0.0f, 0.0f, 0.0f}, Y[3] = {0.0f, 0.0f, 0.0f};
+                    float Y[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
                     for (int k = 0; k <= 2 * B; ++k) {
                         const float w = a.blur_w[k];
 #pragma unroll
-                        for (int j = 0; j < 3; ++j) {
-                            X[j] = __builtin_fmaf(w, S.rx[grp][j][t + 2 * B - k], X[j]);
-                            Y[j] = __builtin_fmaf(w, S.ry[grp][j][t + 2 * B - k], Y[j]);
-                        }
+                        for (int j = 0; j < 3; ++j) Y[j] = __builtin_fmaf(w, S.ry[grp][j][t + 2 * B - k], Y[j]);
                     }
-                    S.tx[grp][0][t] = X[0];
-                    S.tx[grp][1][t] = X[1];
-                    S.tx[grp][2][t] = X[2];
                     S.ty[grp][t] = make_float4(Y[0], Y[1], Y[2], 0.0f);
                 }
             }
-            __syncthreads();
+            group_sync();
         }
 
         // gather: sum_q (dL/dJ)_q Ty(r) Tx(c) over the blurred support, inside the
@@ -193,7 +197,7 @@ bwd_gather(BwdArgs a, int64_t n_span)
             const int ulo = B - r0 > 0 ? B - r0 : 0;
             const int uhi = nu < H - r0 + B ? nu : H - r0 + B;
             const float* __restrict__ gimg = a.grad + img + (int64_t)f * H * W;
-            const float(*T)[BT] = B > 0 ? S.tx[grp] : S.rx[grp];
+            const float(*T)[BT] = S.rx[grp];
             for (int t = tlo + lane; t < thi; t += BG) {
                 const float* __restrict__ col = gimg + (int64_t)(r0 - B) * W + (c0 - B + t);
                 float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
@@ -216,7 +220,15 @@ bwd_gather(BwdArgs a, int64_t n_span)
                         P2 = __builtin_fmaf(ty.z, ek, P2);
                     }
                 }
-                const float X0 = T[0][t], X1 = T[1][t], X2 = T[2][t];
+                // blurred column factors of this column, from the raw ones
+                float X0 = 0.0f, X1 = 0.0f, X2 = 0.0f;
+#pragma unroll
+                for (int k = 0; k <= 2 * B; ++k) {
+                    const float w = B > 0 ? a.blur_w[k] : 1.0f;
+                    X0 = __builtin_fmaf(w, T[0][t + 2 * B - k], X0);
+                    X1 = __builtin_fmaf(w, T[1][t + 2 * B - k], X1);
+                    X2 = __builtin_fmaf(w, T[2][t + 2 * B - k], X2);
+                }
                 s0 = __builtin_fmaf(P0, X0, s0);
                 s_x = __builtin_fmaf(P0, X1, s_x);
                 s_y = __builtin_fmaf(P1, X0, s_y);
@@ -227,7 +239,7 @@ bwd_gather(BwdArgs a, int64_t n_span)
         sx[f] = group_sum(s_x);
         sy[f] = group_sum(s_y);
         sumr += group_sum(s_r);
-        __syncthreads();
+        group_sync();
     }
 
     if (!in_pair || lane != 0) return;

@@ -169,8 +169,8 @@ def gradient_cost(sp, torch, np, dev, steps=10):
         sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2, wsf)
         sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, img, wsf)
 
-    def bwd():
-        sp.render_pair_backward(batch, flow, P["x"], P["y"], P["z"], P["d"], P["I0"], rprm, gJ, None, wsb)
+    def bwd():   # as the autograd wrapper calls it: the forward's frame-2 positions are reused
+        sp.render_pair_backward(batch, flow, P["x"], P["y"], P["z"], P["d"], P["I0"], rprm, gJ, None, wsb, x2=x2, y2=y2)
 
     fwd()
     bwd()

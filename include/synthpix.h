@@ -233,16 +233,21 @@ synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synt
 
 /* Gradient of a loss L of the float images J (bits must be 0) with respect to
  * the frame-1 positions, z, d, I0, each pair's sheet width and each pair's flow
- * grid.  Frame-2 positions are recomputed from (x1, y1) and the flow with
- * rp->advect; footprints are recomputed, nothing from the forward is stored.
+ * grid (differentiating Eq. 1 with the Gaussian sheet peak, the patch cutoff
+ * held fixed, and the blur; noise is additive and has no gradient).
+ * Frame-2 positions: x2, y2 as produced by synthpix_advect from (x1, y1) with
+ * rp->advect, or both NULL to have them recomputed; footprints and the
+ * trajectory are recomputed, nothing else from the forward is needed.
  * grad_images: device floats dL/dJ, same layout as the forward's images.
  * Outputs (device floats, overwritten): g_x1, g_y1, g_z, g_d, g_I0 per particle,
- * g_sheet [n_pairs], g_flow with the flow's layout.
- * workspace: >= synthpix_workspace_size(..., 1). */
+ * g_sheet [n_pairs], g_flow with the flow's layout (zero outside the pairs'
+ * grids).  Deterministic: flow-grid sums are 64-bit fixed point.
+ * tiling is unused (may be NULL); workspace: >= synthpix_workspace_size(..., 1). */
 synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host,
                                               const synthpix_pair* pairs_dev, int32_t n_pairs,
                                               const synthpix_tiling* tiling, const float* flow,
-                                              const float* x1, const float* y1, const float* z,
+                                              const float* x1, const float* y1,
+                                              const float* x2, const float* y2, const float* z,
                                               const float* d, const float* I0,
                                               const synthpix_render_params* rp,
                                               const float* grad_images,

@@ -244,9 +244,11 @@ def render_pair(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, tile=None, image
     return images
 
 
-def render_pair_backward(batch: PairBatch, flow, x1, y1, z, d, I0, rp, grad_images, tile=None, workspace=None):
-    """Run ``synthpix_render_pair_backward``; returns dict of gradients."""
-    _need_cuda(flow, x1, y1, z, d, I0, grad_images)
+def render_pair_backward(batch: PairBatch, flow, x1, y1, z, d, I0, rp, grad_images, tile=None, workspace=None,
+                         x2=None, y2=None):
+    """Run ``synthpix_render_pair_backward``; returns dict of gradients.  Pass the
+    forward's frame-2 positions as x2, y2 to skip their recomputation."""
+    _need_cuda(flow, x1, y1, z, d, I0, grad_images, x2, y2)
     dev = x1.device
     g = {k: torch.empty_like(x1) for k in ("x1", "y1", "z", "d", "I0")}
     g["sheet"] = torch.empty(batch.n_pairs, dtype=torch.float32, device=dev)
@@ -255,9 +257,9 @@ def render_pair_backward(batch: PairBatch, flow, x1, y1, z, d, I0, rp, grad_imag
         workspace = alloc_workspace(batch, rp, tile, backward=True)
     L.check(L.load().synthpix_render_pair_backward(
         batch.host_ptr, batch.dev_ptr, batch.n_pairs, ctypes.byref(tile) if tile is not None else None,
-        _ptr(flow), _ptr(x1), _ptr(y1), _ptr(z), _ptr(d), _ptr(I0), ctypes.byref(rp), _ptr(grad_images),
-        _ptr(g["x1"]), _ptr(g["y1"]), _ptr(g["z"]), _ptr(g["d"]), _ptr(g["I0"]), _ptr(g["sheet"]),
-        _ptr(g["flow"]), _ptr(workspace), workspace.numel(), _stream()))
+        _ptr(flow), _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(z), _ptr(d), _ptr(I0), ctypes.byref(rp),
+        _ptr(grad_images), _ptr(g["x1"]), _ptr(g["y1"]), _ptr(g["z"]), _ptr(g["d"]), _ptr(g["I0"]),
+        _ptr(g["sheet"]), _ptr(g["flow"]), _ptr(workspace), workspace.numel(), _stream()))
     return g
 
 
@@ -319,8 +321,8 @@ class Plan:
 
 class _RenderImages(torch.autograd.Function):
     """advect + render as one differentiable op: inputs flow, x1, y1, z, d, I0
-    and the sheet width; output the float images.  The backward recomputes
-    everything from the saved inputs (``synthpix_render_pair_backward``)."""
+    and the sheet width; output the float images.  The backward reuses the
+    frame-2 positions and recomputes the rest (``synthpix_render_pair_backward``)."""
 
     @staticmethod
     def forward(ctx, flow, x1, y1, z, d, I0, sheet, batch, rp, tile):
@@ -330,14 +332,15 @@ class _RenderImages(torch.autograd.Function):
         rp2.sheet_sigma = float(sheet)
         x2, y2 = advect(batch, flow, rp2.advect, x1, y1)
         img = render_pair(batch, x1, y1, x2, y2, z, d, I0, rp2, tile)
-        ctx.save_for_backward(flow, x1, y1, z, d, I0, sheet)
+        ctx.save_for_backward(flow, x1, y1, x2, y2, z, d, I0, sheet)
         ctx.batch, ctx.rp, ctx.tile = batch, rp2, tile
         return img
 
     @staticmethod
     def backward(ctx, grad):
-        flow, x1, y1, z, d, I0, sheet = ctx.saved_tensors
-        g = render_pair_backward(ctx.batch, flow, x1, y1, z, d, I0, ctx.rp, grad.contiguous(), ctx.tile)
+        flow, x1, y1, x2, y2, z, d, I0, sheet = ctx.saved_tensors
+        g = render_pair_backward(ctx.batch, flow, x1, y1, z, d, I0, ctx.rp, grad.contiguous(), ctx.tile,
+                                 x2=x2, y2=y2)
         g_sheet = g["sheet"].sum().to(sheet.dtype).reshape(sheet.shape)
         return g["flow"], g["x1"], g["y1"], g["z"], g["d"], g["I0"], g_sheet, None, None, None
 

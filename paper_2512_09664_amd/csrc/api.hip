@@ -525,7 +525,8 @@ synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synt
 
 synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
                                               int32_t n_pairs, const synthpix_tiling* tiling, const float* flow,
-                                              const float* x1, const float* y1, const float* z, const float* d,
+                                              const float* x1, const float* y1, const float* x2,
+                                              const float* y2, const float* z, const float* d,
                                               const float* I0, const synthpix_render_params* rp,
                                               const float* grad_images, float* g_x1, float* g_y1, float* g_z,
                                               float* g_d, float* g_I0, float* g_sheet, float* g_flow,
@@ -542,6 +543,8 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     if (!dev_ptr_ok(x1) || !dev_ptr_ok(y1) || !dev_ptr_ok(z) || !dev_ptr_ok(d) || !dev_ptr_ok(I0) ||
         !dev_ptr_ok(grad_images))
         return fail(SP_ERR_INVALID_ARG, "inputs must be non-NULL, 4-byte aligned device pointers");
+    if ((x2 == nullptr) != (y2 == nullptr) || (x2 && (!dev_ptr_ok(x2) || !dev_ptr_ok(y2))))
+        return fail(SP_ERR_INVALID_ARG, "x2 and y2 must both be NULL or both aligned device pointers");
     if (!dev_ptr_ok(g_x1) || !dev_ptr_ok(g_y1) || !dev_ptr_ok(g_z) || !dev_ptr_ok(g_d) || !dev_ptr_ok(g_I0) ||
         !dev_ptr_ok(g_sheet) || !dev_ptr_ok(g_flow))
         return fail(SP_ERR_INVALID_ARG, "gradient outputs must be non-NULL, 4-byte aligned device pointers");
@@ -566,8 +569,11 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.flow = flow;
     a.x1 = x1;
     a.y1 = y1;
-    a.x2 = reinterpret_cast<float*>(ws + wl.x2);
-    a.y2 = reinterpret_cast<float*>(ws + wl.y2);
+    a.x2w = reinterpret_cast<float*>(ws + wl.x2);
+    a.y2w = reinterpret_cast<float*>(ws + wl.y2);
+    a.x2 = x2 ? x2 : a.x2w;
+    a.y2 = y2 ? y2 : a.y2w;
+    a.recompute_x2 = x2 == nullptr;
     a.z = z;
     a.d = d;
     a.I0 = I0;

@@ -748,8 +748,11 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.status, a.scale);
     }
     if (n_span > 0) {
-        hipError_t e = launch_advect(a.pairs, a.n_pairs, n_span, a.flow, ap, a.x1, a.y1, a.x2, a.y2, s, a.order);
-        if (e != hipSuccess) return e;
+        if (a.recompute_x2) {
+            const hipError_t e = launch_advect(a.pairs, a.n_pairs, n_span, a.flow, ap, a.x1, a.y1, a.x2w, a.y2w, s,
+                                               a.order);
+            if (e != hipSuccess) return e;
+        }
         const unsigned gb = (unsigned)((n_span + BPW - 1) / BPW);
         {
             TimedScope ts("bwd_gather", s);

@@ -138,8 +138,11 @@ struct BwdArgs {
     const float* flow;
     const float* x1;
     const float* y1;
-    float* x2;                   // recomputed frame-2 positions (workspace)
-    float* y2;
+    const float* x2;             // frame-2 positions: the caller's, or the recomputed ones
+    const float* y2;
+    float* x2w;                  // recomputed frame-2 positions (workspace)
+    float* y2w;
+    bool recompute_x2;
     const float* z;
     const float* d;
     const float* I0;

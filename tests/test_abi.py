@@ -200,7 +200,7 @@ def test_backward_validation(L):
     assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(rp), None, 1, ctypes.byref(n)) == 0
     # status + kmax + five per-particle float arrays + the fixed-point flow grid
     assert n.value >= 5 * 4 * 100 + 8 * 2 * 16 * 16
-    args = [pairs, fake, 1, None, fake] + [fake] * 5
+    args = [pairs, fake, 1, None, fake, fake, fake, None, None] + [fake] * 3
 
     def call(rp_, ws=ctypes.c_void_p(0x100000), nbytes=1 << 30, grad=fake):
         return lib.synthpix_render_pair_backward(*args, ctypes.byref(rp_), grad, fake, fake, fake, fake, fake,
@@ -215,3 +215,6 @@ def test_backward_validation(L):
     assert call(rp, grad=None) == L.SP_ERR_INVALID_ARG
     assert call(rp, nbytes=n.value - 1) == L.SP_ERR_WORKSPACE
     assert call(rp, ws=ctypes.c_void_p(0x100010)) == L.SP_ERR_WORKSPACE
+    half = [pairs, fake, 1, None, fake, fake, fake, fake, None] + [fake] * 3   # x2 without y2
+    assert lib.synthpix_render_pair_backward(*half, ctypes.byref(rp), fake, fake, fake, fake, fake, fake, fake,
+                                             fake, ctypes.c_void_p(0x100000), 1 << 30, None) == L.SP_ERR_INVALID_ARG

@@ -191,9 +191,13 @@ def test_backward_is_deterministic_and_autograd_agrees():
     gJ, gJ_dev = _grad_images(batch, 11)
     runs = [sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev)
             for _ in range(2)]
+    x2, y2 = sp.advect(batch, flow_dev, rp.advect, dev["x"], dev["y"])
+    given = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                                    x2=x2, y2=y2)
     torch.cuda.synchronize()
     for k in runs[0]:
         assert torch.equal(runs[0][k], runs[1][k]), k
+        assert torch.equal(runs[0][k], given[k]), k   # the forward's x2, y2 instead of recomputing them
     inp = {k: v.clone().requires_grad_(True) for k, v in dev.items()}
     fl = flow_dev.clone().requires_grad_(True)
     sheet = torch.tensor(0.5, device=gu.DEV, requires_grad=True)

@@ -371,6 +371,23 @@ def test_diameter_above_max_is_flagged():
     assert img[0, 10, 10] == 1.0 and img[0, 20, 20] == 0.0
 
 
+def test_fixed_point_range_is_flagged():
+    """The integer pixel sums hold up to 256 full-scale units; a tile whose staged
+    peaks could reach that raises SP_STATUS_FIXED_RANGE, ordinary tiles do not."""
+    n = 300
+    arrs = dict(x1=np.full(n, 10.5, np.float32), y1=np.full(n, 10.5, np.float32),
+                x2=np.full(n, 40.5, np.float32), y2=np.full(n, 40.5, np.float32),
+                z=np.zeros(n, np.float32), d=np.full(n, 2.0, np.float32), I0=np.ones(n, np.float32))
+    b = gu.batch_for([(64, 64)], [(4, 4)], [n])
+    rp = sp.render_params(0.5, 4.0, 0, 0.7, 0.0, 0)
+    ws = sp.alloc_workspace(b, rp)
+    _render_gpu(b, arrs, rp, workspace=ws)
+    assert sp.read_status(ws) & sp._lib.SP_STATUS_FIXED_RANGE
+    arrs["I0"][:] = 0.5                      # 150 full-scale units: in range
+    _render_gpu(b, arrs, rp, workspace=ws)
+    assert sp.read_status(ws) == 0
+
+
 # ----------------------------------------------------------------------------- full size, sampled
 
 def _full_size_sampled(ra, wl, pairs, exact_pairs, per_frame=24, seed=0):

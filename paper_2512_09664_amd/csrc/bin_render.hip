@@ -444,6 +444,9 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (r.z * r.z), r.w);
             box[threadIdx.x] = pack_box(c0, w, r0, h);
             if (w > 0) asum += r.w;
+            // zero column factors up to the next multiple of four: the splat adds
+            // whole quads, the columns past the patch adding zero
+            for (int j = w; j < ((w + 3) & ~3); ++j) gx[threadIdx.x * WM + j] = 0.0f;
         }
         // work items: one per patch line j < max(w, h); item j carries the j-th
         // column factor (if j < w) and the j-th row factor (if j < h)
@@ -470,8 +473,8 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             }
         }
         __syncthreads();
-        // splat: one patch row per work item, eight columns per step; lanes past
-        // the patch edge add zero (the accumulator has slack for the overrun)
+        // splat: one patch row per work item, eight columns per step; columns past
+        // the patch edge carry zero factors (the accumulator has slack for the overrun)
         for (int i = threadIdx.x; i < tm_; i += 256) {
             const int it = items[i];
             const int k = it >> 8, j = it & 255;
@@ -482,18 +485,17 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             const float* gk = gx + k * WM;
             uint32_t* dst = acc + (pr0 + j) * RW + pc0;
             for (int cs0 = 0; cs0 < pw; cs0 += 8) {
-                const int cw = pw - cs0;
                 const float4 g0 = *reinterpret_cast<const float4*>(gk + cs0);
                 atomicAdd(dst + cs0 + 0, (uint32_t)(rv * g0.x));
-                atomicAdd(dst + cs0 + 1, cw > 1 ? (uint32_t)(rv * g0.y) : 0u);
-                atomicAdd(dst + cs0 + 2, cw > 2 ? (uint32_t)(rv * g0.z) : 0u);
-                atomicAdd(dst + cs0 + 3, cw > 3 ? (uint32_t)(rv * g0.w) : 0u);
-                if (cw > 4) {
+                atomicAdd(dst + cs0 + 1, (uint32_t)(rv * g0.y));
+                atomicAdd(dst + cs0 + 2, (uint32_t)(rv * g0.z));
+                atomicAdd(dst + cs0 + 3, (uint32_t)(rv * g0.w));
+                if (pw - cs0 > 4) {
                     const float4 g1 = *reinterpret_cast<const float4*>(gk + cs0 + 4);
                     atomicAdd(dst + cs0 + 4, (uint32_t)(rv * g1.x));
-                    atomicAdd(dst + cs0 + 5, cw > 5 ? (uint32_t)(rv * g1.y) : 0u);
-                    atomicAdd(dst + cs0 + 6, cw > 6 ? (uint32_t)(rv * g1.z) : 0u);
-                    atomicAdd(dst + cs0 + 7, cw > 7 ? (uint32_t)(rv * g1.w) : 0u);
+                    atomicAdd(dst + cs0 + 5, (uint32_t)(rv * g1.y));
+                    atomicAdd(dst + cs0 + 6, (uint32_t)(rv * g1.z));
+                    atomicAdd(dst + cs0 + 7, (uint32_t)(rv * g1.w));
                 }
             }
         }

@@ -151,11 +151,13 @@ def uneven_batched_vs_per_pair(sp, torch, np, dev, steps=5):
     return out
 
 
-def gradient_cost(sp, torch, np, dev, steps=10):
-    """grad_512 (64 pairs of 512^2, RK4 x4, 3x3 blur, float images): advect +
-    render forward vs the backward from dL/dJ."""
+def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
+    """Advect + render forward vs the backward from dL/dJ, on float images:
+    grad_512 (64 pairs of 512^2, RK4 x4, 3x3 blur) or dense_2048 (32 pairs of
+    2048^2, 0.1 ppp, d ~ U[2, 6], RK4 x8, 5x5 blur; the differentiable form
+    renders float images, so noise and codes are off)."""
     from workloads import get_workload
-    wl = get_workload("grad_512")
+    wl = get_workload(name).with_(bits=0, noise_sigma=0.0)
     flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
     P = sp.seed(batch, sprm, wl.seed)
     x2 = torch.empty_like(P["x"])
@@ -336,6 +338,8 @@ def main():
         log(f"[bench] grad_512: {extras['grad_512']}")
         extras["dense_2048"] = dense_throughput(sp, torch, np, dev)
         log(f"[bench] dense_2048: {extras['dense_2048']}")
+        extras["dense_2048_grad"] = gradient_cost(sp, torch, np, dev, "dense_2048", steps=5)
+        log(f"[bench] dense_2048_grad: {extras['dense_2048_grad']}")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -24,13 +24,13 @@ if torch.cuda.is_available():
 TOL = 1e-4   # of each quantity's largest magnitude
 
 
-def _batch(sizes, grids, n_per_pair, seed, zero_frac=0.15):
+def _batch(sizes, grids, n_per_pair, seed, zero_frac=0.15, d_range=(1.0, 4.5)):
     """Host particles and flows of a small uneven batch, plus its device copies."""
     rng = np.random.default_rng(seed)
     P = {k: [] for k in ("x", "y", "z", "d", "I0")}
     flows = []
     for p, ((H, W), (Gh, Gw)) in enumerate(zip(sizes, grids)):
-        q = particles.random_particles(seed * 100 + p, n_per_pair, H, W, d_range=(1.0, 4.5), pad=3.0,
+        q = particles.random_particles(seed * 100 + p, n_per_pair, H, W, d_range=d_range, pad=3.0,
                                        zero_frac=zero_frac)
         for k in P:
             P[k].append(q[k])
@@ -107,15 +107,20 @@ def _close(got, ref, what, tol=TOL):
     assert err <= tol * scale + 1e-30, f"{what}: max error {err:.3e} vs scale {scale:.3e}"
 
 
-CASES = [("euler", 1, 0, 0.5), ("rk4", 2, 1, 0.5), ("rk4", 4, 2, 0.8), ("euler", 3, 3, 0.45)]
+# (integrator, substeps, blur radius, sheet width, diameter range, d_max): the last
+# two cases are the dense stress shape (d up to 6, 5x5 blur, RK4 x 8) and
+# diameters wide enough for the 64-slot factor tables
+CASES = [("euler", 1, 0, 0.5, (1.0, 4.5), 5.0), ("rk4", 2, 1, 0.5, (1.0, 4.5), 5.0),
+         ("rk4", 4, 2, 0.8, (1.0, 4.5), 5.0), ("euler", 3, 3, 0.45, (1.0, 4.5), 5.0),
+         ("rk4", 8, 2, 0.5, (2.0, 6.0), 6.0), ("rk4", 2, 1, 0.6, (5.0, 9.5), 10.0)]
 
 
-@pytest.mark.parametrize("integ,n_sub,blur,sheet", CASES)
-def test_backward_matches_oracle_gradient(integ, n_sub, blur, sheet):
+@pytest.mark.parametrize("integ,n_sub,blur,sheet,d_range,d_max", CASES)
+def test_backward_matches_oracle_gradient(integ, n_sub, blur, sheet, d_range, d_max):
     sizes = [(16, 16), (24, 20), (40, 48), (33, 17)]
     grids = [(6, 6), (8, 7), (10, 12), (9, 5)]
-    P, flows, batch, dev, flow_dev = _batch(sizes, grids, 14, 3 + n_sub + 10 * blur)
-    rp = sp.render_params(sheet, 5.0, blur, 0.8, 0.0, 0, 0, 1.0, n_sub, integ)
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, 14, 3 + n_sub + 10 * blur, d_range=d_range)
+    rp = sp.render_params(sheet, d_max, blur, 0.8, 0.0, 0, 0, 1.0, n_sub, integ)
     gJ, gJ_dev = _grad_images(batch, 99 + blur)
     ws = sp.alloc_workspace(batch, rp, backward=True)
     g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
@@ -265,3 +270,71 @@ def test_backward_full_size_pairs(ra):
         assert np.max(np.abs(gf - ref["flow"])) <= 5e-3 * scale, f"pair {p} flow near kinks"
         term_scale = np.sum(np.abs(ref["z"] * P["z"][p])) / np.float32(rp.sheet_sigma)
         assert abs(G["sheet"][p] - ref["s"]) <= TOL * term_scale
+
+
+def test_backward_dense_2048_sampled(ra):
+    """dense_2048 at full size (32 pairs of 2048^2, 0.1 ppp, d ~ U[2, 6], RK4 x 8,
+    5x5 blur).  A particle's own gradients depend only on dL/dJ, its parameters
+    and the flow, so a sample of particles is checked against the oracle run on
+    that sample alone; the flow and sheet gradients, sums over particles, are
+    checked on a second launch in which only the sample is lit."""
+    wl = get_workload("dense_2048")
+    flows = make_flows(wl.flow, wl.seed, wl.sizes, wl.grid_div, wl.max_disp, wl.dt, wl.uniform_uv)
+    n_max = [sp.particle_count(H, W, wl.ppp[1]) for (H, W) in wl.sizes]
+    batch = gu.batch_for(wl.sizes, [f.shape[:2] for f in flows], n_max)
+    P = {k: [] for k in ("x", "y", "z", "d", "I0")}
+    for p, (H, W) in enumerate(wl.sizes):
+        q = ra.seed_pair(H, W, n_max[p], wl.ppp, p, wl.seed, wl.d_dist, wl.d_params, wl.I0, wl.z)
+        for k in P:
+            P[k].append(q[k])
+    dev = {k: gu.to_dev(np.concatenate(v)) for k, v in P.items()}
+    flow_dev = gu.to_dev(np.concatenate([f.reshape(-1) for f in flows]))
+    rp = sp.render_params(wl.sheet_sigma, wl.d_max, wl.blur_radius, wl.blur_sigma, 0.0, 0, wl.seed, wl.dt,
+                          wl.substeps, wl.integrator)
+    gJ, gJ_dev = _grad_images(batch, 2048)
+    ws = sp.alloc_workspace(batch, rp, backward=True)
+    print("[case] dense_2048 backward, all particles", flush=True)
+    g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                                workspace=ws)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    G = {k: gu.to_np(v) for k, v in g.items()}
+    pairs = (0, 31)
+    sel = {p: np.arange(p % 7, n_max[p], 211) for p in pairs}
+    lit = np.concatenate(P["I0"]).copy()
+    keep = np.zeros(lit.size, dtype=bool)
+    for p in pairs:
+        keep[batch.host[p].particle_offset + sel[p]] = True
+    lit[~keep] = 0.0
+    print("[case] dense_2048 backward, sampled particles lit", flush=True)
+    gs = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], gu.to_dev(lit), rp,
+                                 gJ_dev, workspace=ws)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    GS = {k: gu.to_np(v) for k, v in gs.items()}
+    for p in pairs:
+        H, W = wl.sizes[p]
+        s = sel[p]
+        Q = {k: [P[k][p][s]] for k in P}
+        x2, y2 = ra.advect(flows[p], H, W, Q["x"][0], Q["y"][0], wl.dt, wl.substeps, wl.integrator)
+        ref = _oracle_pair(Q, 0, [flows[p]], H, W, gJ, batch.host[p].image_offset, rp, wl.blur_radius, (x2, y2))
+        sl = batch.host[p].particle_offset + s
+        kink, kink_nodes = _kinks(flows[p], H, W, Q["x"][0], Q["y"][0], wl.dt, wl.substeps, wl.integrator)
+        assert kink.sum() < 0.05 * len(kink)
+        for key in ("z", "d", "I0"):
+            _close(G[key][sl], ref[key], f"pair {p} {key}")
+            _close(GS[key][sl], ref[key], f"pair {p} {key} (sample lit)")
+        for key in ("x1", "y1"):
+            scale = np.max(np.abs(ref[key]))
+            _close(G[key][sl][~kink], ref[key][~kink], f"pair {p} {key}")
+            assert np.max(np.abs(G[key][sl] - ref[key])) <= 5e-3 * scale, key
+        fo = batch.host[p].flow_offset
+        gf = GS["flow"][fo:fo + flows[p].size].reshape(flows[p].shape)
+        scale = np.max(np.abs(ref["flow"]))
+        assert np.max(np.abs(gf - ref["flow"])[~kink_nodes]) <= TOL * scale, f"pair {p} flow"
+        assert np.max(np.abs(gf - ref["flow"])) <= 5e-3 * scale, f"pair {p} flow near kinks"
+        term_scale = np.sum(np.abs(ref["z"] * Q["z"][0])) / np.float32(rp.sheet_sigma)
+        assert abs(GS["sheet"][p] - ref["s"]) <= TOL * term_scale, p
+    # pairs with no lit particle get a zero flow gradient in the masked launch
+    fo = batch.host[5].flow_offset
+    assert not np.any(GS["flow"][fo:fo + flows[5].size])

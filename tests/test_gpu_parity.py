@@ -204,6 +204,33 @@ def test_tiling_and_batching_do_not_change_bits():
         o += 2 * H * W
 
 
+@pytest.mark.parametrize("tile", [None, (8, 8, 256, 32), (128, 32, 16384, 128)])
+def test_large_diameters_match_oracle(ra, tile):
+    """Diameters up to 15 px under d_max = 16 (the largest accepted) with the
+    widest blur: patches far wider than small tiles, the widest factor tables."""
+    sizes = [(72, 90), (41, 23)]
+    arrs, n_max = _render_case(61, sizes, 60, d_range=(5.0, 15.0), edge=False)
+    _say("large diameters", tile, sizes)
+    b = gu.batch_for(sizes, [(4, 4)] * 2, n_max)
+    rp = sp.render_params(0.5, 16.0, 3, 1.3, 0.0, 0)
+    tl = sp.tiling(*tile) if tile else None
+    ws = sp.alloc_workspace(b, rp, tl)
+    img = _render_gpu(b, arrs, rp, tl, workspace=ws)
+    assert sp.read_status(ws) == 0
+    w = oep.blur_weights(3, 1.3)
+    o = po = 0
+    for p, (H, W) in enumerate(sizes):
+        sl = slice(po, po + n_max[p])
+        po += n_max[p]
+        for xk, yk in (("x1", "y1"), ("x2", "y2")):
+            got = img[o:o + H * W].reshape(H, W)
+            o += H * W
+            args = (arrs[xk][sl], arrs[yk][sl], arrs["z"][sl], arrs["d"][sl], arrs["I0"][sl])
+            assert np.array_equal(got, ra.blur(ra.render(*args, H, W, 0.5), w)), p
+            ref = oep.blur(orend.render_frame(*args, H, W, 0.5), w)
+            assert np.max(np.abs(got - ref)) <= TOL * ref.max(), p
+
+
 @pytest.mark.parametrize("tile", [None, (16, 16, 256, 32)])
 def test_bins_match_oracle(tile):
     sizes = [(64, 96), (37, 53)]

@@ -10,7 +10,8 @@
 //   prep        : per particle and frame, a 16-byte record (x, y, d, fixed-point
 //                 peak); d < 0 marks a particle that adds nothing
 //   bin_count   : per (pair, frame, particle chunk) LDS histogram of tile hits
-//   bin_scan    : per (pair, frame) exclusive scan -> tile offsets and per-chunk bases
+//   bin_scan    : per tile, chunk bases inside its list and its total; per
+//                 (pair, frame), the exclusive scan of the totals -> list offsets
 //   bin_scatter : per chunk, LDS cursors -> particle indices into tile lists
 //   render_tile : per (pair, frame, tile) stage the list in LDS, splat footprints
 //                 into an LDS fixed-point accumulator (tile + blur apron), then
@@ -158,7 +159,8 @@ template <bool SCATTER>
 __global__ void __launch_bounds__(256)
 bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
          const float4* __restrict__ rec0, const float4* __restrict__ rec1, RenderConfig cfg,
-         uint32_t* __restrict__ hist, int32_t* __restrict__ entries, unsigned n_chunks_total)
+         uint32_t* __restrict__ hist, const int64_t* __restrict__ tile_offset, int64_t tiles_total,
+         int32_t* __restrict__ entries, unsigned n_chunks_total)
 {
     extern __shared__ uint32_t lh[];
     const int f = blockIdx.y;
@@ -169,11 +171,14 @@ bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__
     const int chunk = (int)cb - PL.chunk_base;
     const int nt = PL.ntx * PL.nty;
     uint32_t* gh = hist + PL.hist_base + ((int64_t)f * PL.n_chunks + chunk) * nt;
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = SCATTER ? gh[t] : 0u;
+    int32_t* seg = entries + PL.entry_base + (int64_t)f * PL.entry_cap;
+    // scatter cursors start at the chunk's first slot in each tile list
+    const int64_t* toff = tile_offset + f * tiles_total + PL.tile_base;
+    const int64_t seg0 = PL.entry_base + (int64_t)f * PL.entry_cap;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = SCATTER ? gh[t] + (uint32_t)(toff[t] - seg0) : 0u;
     __syncthreads();
     const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
     const float4* __restrict__ rec = f ? rec1 : rec0;
-    int32_t* seg = entries + PL.entry_base + (int64_t)f * PL.entry_cap;
     // BIN_ILP particles per thread and step: their record loads and LDS atomic
     // round trips overlap
     constexpr int BIN_ILP = 4;
@@ -221,7 +226,7 @@ template <bool SCATTER>
 __global__ void __launch_bounds__(256)
 order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
            const float* __restrict__ x, const float* __restrict__ y, RenderConfig cfg, uint32_t* __restrict__ hist,
-           int32_t* __restrict__ entries, unsigned n_chunks_total)
+           const int64_t* __restrict__ tile_offset, int32_t* __restrict__ entries, unsigned n_chunks_total)
 {
     extern __shared__ uint32_t lh[];
     const unsigned cb = xcd_contiguous(blockIdx.x, n_chunks_total);
@@ -231,10 +236,12 @@ order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict
     const int chunk = (int)cb - PL.chunk_base;
     const int nt = PL.ntx * PL.nty;
     uint32_t* gh = hist + PL.hist_base + (int64_t)chunk * nt;
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = SCATTER ? gh[t] : 0u;
+    int32_t* seg = entries + PL.entry_base;
+    const int64_t* toff = tile_offset + PL.tile_base;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x)
+        lh[t] = SCATTER ? gh[t] + (uint32_t)(toff[t] - PL.entry_base) : 0u;
     __syncthreads();
     const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
-    int32_t* seg = entries + PL.entry_base;
     for (int i = chunk * cfg.chunk + threadIdx.x; i < i_end; i += blockDim.x) {
         const int64_t g = P.particle_offset + i;
         const uint32_t slot = atomicAdd(&lh[home_block(x[g], y[g], P.W, P.H, PL, cfg)], 1u);
@@ -246,48 +253,73 @@ order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict
     }
 }
 
-// Per (pair, frame): tile totals, exclusive tile offsets (within the pair-frame
-// segment) and, in place, each chunk's starting slot inside every tile list.
+// Per (pair, frame, tile), one thread each: exclusive prefix of the chunk
+// histograms over the chunks, in place (each chunk's first slot inside the
+// tile's list), and the tile's total.  Consecutive threads take consecutive
+// tiles, so every chunk row is read and written with coalesced accesses.
 __global__ void __launch_bounds__(256)
-bin_scan(const PairLayout* __restrict__ L, uint32_t* __restrict__ hist, uint32_t* __restrict__ tile_count,
-         int64_t* __restrict__ tile_offset, int64_t tiles_total)
+scan_chunks(const PairLayout* __restrict__ L, int n_pairs, uint32_t* __restrict__ hist,
+            uint32_t* __restrict__ tile_count, int64_t tiles_total)
 {
-    __shared__ uint32_t s_sum[256];
+    const int f = blockIdx.y;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gt >= tiles_total) return;
+    const int p = find_pair_by_tile(L, n_pairs, gt);
+    const PairLayout PL = L[p];
+    const int nt = PL.ntx * PL.nty;
+    const int t = (int)(gt - PL.tile_base);
+    uint32_t* h = hist + PL.hist_base + (int64_t)f * PL.n_chunks * nt + t;
+    constexpr int U = 8;                 // chunk rows loaded together
+    uint32_t run = 0;
+    for (int c0 = 0; c0 < PL.n_chunks; c0 += U) {
+        uint32_t v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = c0 + k < PL.n_chunks ? h[(int64_t)(c0 + k) * nt] : 0u;
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (c0 + k < PL.n_chunks) h[(int64_t)(c0 + k) * nt] = run;
+            run += v[k];
+        }
+    }
+    tile_count[f * tiles_total + gt] = run;
+}
+
+// Per (pair, frame): exclusive scan of the tile totals -> absolute offsets of
+// the tile lists (the pair-frame segment's base plus the prefix).
+__global__ void __launch_bounds__(256)
+scan_tiles(const PairLayout* __restrict__ L, const uint32_t* __restrict__ tile_count,
+           int64_t* __restrict__ tile_offset, int64_t tiles_total)
+{
+    __shared__ uint32_t s_wave[4];
     const int p = blockIdx.x;
     const int f = blockIdx.y;
     const PairLayout PL = L[p];
     const int nt = PL.ntx * PL.nty;
-    uint32_t* h = hist + PL.hist_base + (int64_t)f * PL.n_chunks * nt;
-    const int per = (nt + 255) / 256;
-    const int t0 = threadIdx.x * per;
-    const int t1 = min(nt, t0 + per);
-    // pass 1: within-tile exclusive prefix over chunks; tile totals; thread sum
-    uint32_t mine = 0;
-    for (int t = t0; t < t1; ++t) {
-        uint32_t run = 0;
-        for (int c = 0; c < PL.n_chunks; ++c) {
-            const uint32_t v = h[(int64_t)c * nt + t];
-            h[(int64_t)c * nt + t] = run;
-            run += v;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t* cnt = tile_count + f * tiles_total + PL.tile_base;
+    int64_t* out = tile_offset + f * tiles_total + PL.tile_base;
+    int64_t carry = PL.entry_base + (int64_t)f * PL.entry_cap;
+    for (int b = 0; b < nt; b += 256) {
+        const int t = b + threadIdx.x;
+        const uint32_t v = t < nt ? cnt[t] : 0u;
+        uint32_t inc = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t x = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += x;
         }
-        tile_count[f * tiles_total + PL.tile_base + t] = run;
-        mine += run;
-    }
-    s_sum[threadIdx.x] = mine;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t add = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0u;
+        if (lane == 63) s_wave[wid] = inc;
         __syncthreads();
-        s_sum[threadIdx.x] += add;
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t sw = s_wave[w];
+            if (w < wid) before += sw;
+            total += sw;
+        }
+        if (t < nt) out[t] = carry + (int64_t)(before + inc - v);
+        carry += total;
         __syncthreads();
-    }
-    uint32_t base = s_sum[threadIdx.x] - mine;
-    // pass 2: tile offsets; shift chunk bases by the tile offset
-    for (int t = t0; t < t1; ++t) {
-        const uint32_t cnt = tile_count[f * tiles_total + PL.tile_base + t];
-        tile_offset[f * tiles_total + PL.tile_base + t] = PL.entry_base + (int64_t)f * PL.entry_cap + base;
-        for (int c = 0; c < PL.n_chunks; ++c) h[(int64_t)c * nt + t] += base;
-        base += cnt;
     }
 }
 
@@ -620,6 +652,15 @@ bool render_shape_supported(int tw, int th)
 
 // ------------------------------------------------------------------ launcher
 
+static void launch_scans(const PairLayout* L, int n_pairs, uint32_t* hist, uint32_t* tile_count,
+                         int64_t* tile_offset, int64_t tiles, int frames, hipStream_t s)
+{
+    hipLaunchKernelGGL(scan_chunks, dim3((unsigned)((tiles + 255) / 256), frames), dim3(256), 0, s, L, n_pairs, hist,
+                       tile_count, tiles);
+    hipLaunchKernelGGL(scan_tiles, dim3((unsigned)n_pairs, frames), dim3(256), 0, s, L, tile_count, tile_offset,
+                       tiles);
+}
+
 template <int TW, int TH>
 static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const RenderArgs& a, const RenderConfig& cfg,
                                 const PairLayout* L, const float4* r0, const float4* r1, const uint32_t* tile_count,
@@ -665,18 +706,17 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
     if (tot.chunks > 0) {
         TimedScope ts("bin_count", s);
-        hipLaunchKernelGGL(bin_pass<false>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s,
-                           a.pairs, L, a.n_pairs, rec0, rec1, cfg, hist, entries, (unsigned)tot.chunks);
+        hipLaunchKernelGGL(bin_pass<false>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s, a.pairs, L,
+                           a.n_pairs, rec0, rec1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
     }
-    {
+    if (tot.tiles > 0) {
         TimedScope ts("bin_scan", s);
-        hipLaunchKernelGGL(bin_scan, dim3((unsigned)a.n_pairs, 2), dim3(256), 0, s, L, hist, tile_count,
-                           tile_offset, tot.tiles);
+        launch_scans(L, a.n_pairs, hist, tile_count, tile_offset, tot.tiles, 2, s);
     }
     if (tot.chunks > 0) {
         TimedScope ts("bin_scatter", s);
-        hipLaunchKernelGGL(bin_pass<true>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s,
-                           a.pairs, L, a.n_pairs, rec0, rec1, cfg, hist, entries, (unsigned)tot.chunks);
+        hipLaunchKernelGGL(bin_pass<true>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s, a.pairs, L,
+                           a.n_pairs, rec0, rec1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
     }
     if (tot.tiles > 0) {
         TimedScope ts("render_tile", s);
@@ -710,11 +750,10 @@ hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float
     if (tot.chunks == 0) return hipGetLastError();
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
     hipLaunchKernelGGL(order_pass<false>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
-                       y, cfg, hist, entries, (unsigned)tot.chunks);
-    hipLaunchKernelGGL(bin_scan, dim3((unsigned)n_pairs, 1), dim3(256), 0, s, L, hist, tile_count, tile_offset,
-                       tot.tiles);
+                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks);
+    launch_scans(L, n_pairs, hist, tile_count, tile_offset, tot.tiles, 1, s);
     hipLaunchKernelGGL(order_pass<true>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
-                       y, cfg, hist, entries, (unsigned)tot.chunks);
+                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks);
     return hipGetLastError();
 }
 

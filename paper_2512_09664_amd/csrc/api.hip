@@ -189,10 +189,10 @@ int64_t flow_span(const synthpix_pair* ph, int32_t n_pairs)
 
 // Backward workspace: particle-major, no bins.
 struct BwdLayout {
-    size_t status, scale, x2, y2, gx2, gy2, sheet, sheet_part, bound_part, fixed, total;
+    size_t status, scale, x2, y2, gx2, gy2, sheet, sheet_part, bound_part, fixed, eblur, total;
 };
 
-BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs)
+BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs, int64_t n_eblur)
 {
     BwdLayout w{};
     size_t o = 0;
@@ -207,8 +207,21 @@ BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs)
     w.sheet_part = o; o = align256(o + sizeof(double) * sp::BWD_SLICES * (size_t)n_pairs);
     w.bound_part = o; o = align256(o + sizeof(float) * 2 * sp::BWD_SLICES * (size_t)n_pairs);
     w.fixed = o; o = align256(o + sizeof(uint64_t) * (size_t)n_flow);
+    w.eblur = o; o = align256(o + sizeof(float) * (size_t)n_eblur);
     w.total = o;
     return w;
+}
+
+// Elements of the blurred-gradient images the backward keeps (B^T dL/dJ, the
+// images' layout) when the blur is wide enough (radius >= 2) for the gather to
+// pay for a per-pixel pass, else none.
+int64_t eblur_span(const synthpix_pair* ph, int32_t n_pairs, int blur_radius)
+{
+    if (blur_radius < 2) return 0;
+    int64_t span = 0;
+    for (int32_t p = 0; p < n_pairs; ++p)
+        span = std::max<int64_t>(span, ph[p].image_offset + 2 * (int64_t)ph[p].H * ph[p].W);
+    return span;
 }
 
 // ceil(log2(samples)) for the fixed-point scale of the flow gradient.
@@ -313,6 +326,8 @@ hipError_t enqueue_order(const synthpix_pair* ph, const synthpix_pair* pd, int32
     const sp::OrderLayout ol = order_layout(n_pairs, T, base);
     out->L = reinterpret_cast<const sp::PairLayout*>(ws + ol.layout);
     out->entries = reinterpret_cast<const int32_t*>(ws + ol.entries);
+    out->log_block = cfg.log_tw;
+    out->blocks = T.tiles;
     return sp::launch_order(pd, n_pairs, x, y, cfg, T, ws, ol, s);
 }
 
@@ -356,7 +371,8 @@ synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t
     const size_t ob = order_bytes(pairs_host, n_pairs);
     if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (backward) {
-        *bytes_out = bwd_layout(span, flow_span(pairs_host, n_pairs), n_pairs).total + ob;
+        *bytes_out = bwd_layout(span, flow_span(pairs_host, n_pairs), n_pairs,
+                                eblur_span(pairs_host, n_pairs, rp->blur_radius)).total + ob;
         return SP_OK;
     }
     const sp::RenderConfig cfg = make_config(*rp, t);
@@ -549,7 +565,8 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
         !dev_ptr_ok(g_sheet) || !dev_ptr_ok(g_flow))
         return fail(SP_ERR_INVALID_ARG, "gradient outputs must be non-NULL, 4-byte aligned device pointers");
     const int64_t n_flow = flow_span(pairs_host, n_pairs);
-    const BwdLayout wl = bwd_layout(span, n_flow, n_pairs);
+    const int64_t n_eblur = eblur_span(pairs_host, n_pairs, rp->blur_radius);
+    const BwdLayout wl = bwd_layout(span, n_flow, n_pairs, n_eblur);
     const size_t ob = order_bytes(pairs_host, n_pairs);
     if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -578,6 +595,7 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.d = d;
     a.I0 = I0;
     a.grad = grad_images;
+    a.eblur = n_eblur ? reinterpret_cast<float*>(ws + wl.eblur) : nullptr;
     a.g_x1 = g_x1;
     a.g_y1 = g_y1;
     a.g_z = g_z;

@@ -83,7 +83,7 @@ __device__ __forceinline__ bool cover_range(float p, float R, int n, int& lo, in
 }
 
 template <int B, int BT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 32 ? 6 : 4)))
 bwd_gather(BwdArgs a, int64_t n_span)
 {
     __shared__ GatherLds<BT> S;
@@ -199,25 +199,44 @@ bwd_gather(BwdArgs a, int64_t n_span)
             const float* __restrict__ gimg = a.grad + img + (int64_t)f * H * W;
             const float(*T)[BT] = S.rx[grp];
             for (int t = tlo + lane; t < thi; t += BG) {
-                const float* __restrict__ col = gimg + (int64_t)(r0 - B) * W + (c0 - B + t);
+                // walk down the column with a row pointer: whole batches of GROWS rows
+                // (their loads issued together), then batches of 4, 2 and 1
+                const float* __restrict__ q = gimg + (int64_t)(r0 - B + ulo) * W + (c0 - B + t);
                 float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
-                for (int u = ulo; u < uhi; u += GROWS) {
-                    // GROWS loads issued together; rows past the patch re-read its last
-                    // row and are weighted by zero
+                int u = ulo;
+#pragma unroll 1
+                for (; u + GROWS <= uhi; u += GROWS) {
                     float e[GROWS];
 #pragma unroll
                     for (int k = 0; k < GROWS; ++k) {
-                        const int uu = u + k < uhi ? u + k : uhi - 1;
-                        e[k] = col[(int64_t)uu * W];
+                        e[k] = *q;
+                        q += W;
                     }
 #pragma unroll
                     for (int k = 0; k < GROWS; ++k) {
-                        const int uu = u + k < uhi ? u + k : uhi - 1;
-                        const float4 ty = S.ty[grp][uu];
-                        const float ek = u + k < uhi ? e[k] : 0.0f;
-                        P0 = __builtin_fmaf(ty.x, ek, P0);
-                        P1 = __builtin_fmaf(ty.y, ek, P1);
-                        P2 = __builtin_fmaf(ty.z, ek, P2);
+                        const float4 ty = S.ty[grp][u + k];
+                        P0 = __builtin_fmaf(ty.x, e[k], P0);
+                        P1 = __builtin_fmaf(ty.y, e[k], P1);
+                        P2 = __builtin_fmaf(ty.z, e[k], P2);
+                    }
+                }
+#pragma unroll
+                for (int nb = GROWS / 2; nb >= 1; nb >>= 1) {
+                    if (uhi - u >= nb) {
+                        float e[GROWS / 2];
+#pragma unroll
+                        for (int k = 0; k < nb; ++k) {
+                            e[k] = *q;
+                            q += W;
+                        }
+#pragma unroll
+                        for (int k = 0; k < nb; ++k) {
+                            const float4 ty = S.ty[grp][u + k];
+                            P0 = __builtin_fmaf(ty.x, e[k], P0);
+                            P1 = __builtin_fmaf(ty.y, e[k], P1);
+                            P2 = __builtin_fmaf(ty.z, e[k], P2);
+                        }
+                        u += nb;
                     }
                 }
                 // blurred column factors of this column, from the raw ones
@@ -266,6 +285,67 @@ bwd_gather(BwdArgs a, int64_t n_span)
     a.gx2[g] = gx2;
     a.gy2[g] = gy2;
     a.sheet[g] = sheet;
+}
+
+// e = B^T dL/dJ for a wide blur, once per pixel: the zero-padded blur's
+// adjoint sums w_k dL/dJ(q + k) over the taps that land inside the image (the
+// same blur, its weights being symmetric).  One 32x32 pixel block of one
+// frame per workgroup, numbered by the home blocks of the advection order
+// (2^lb pixels square, so 4^(lb - 5) sub-blocks each); separable, through LDS.
+template <int B>
+__global__ void __launch_bounds__(256)
+bwd_blur_grad(BwdArgs a, int lb)
+{
+    constexpr int S = 32, SW = S + 2 * B;
+    constexpr int NL = (SW * SW + 255) / 256;        // loads per thread
+    __shared__ float in[SW][SW + 1];
+    __shared__ float hz[SW][S + 1];
+    const int f = blockIdx.y;
+    const int sub_bits = 2 * (lb - 5);
+    const int64_t blk = (int64_t)blockIdx.x >> sub_bits;
+    const int sub = (int)(blockIdx.x & ((1u << sub_bits) - 1u));
+    const int p = find_pair_by_tile(a.order.L, a.n_pairs, blk);
+    const PairLayout PL = a.order.L[p];
+    const int t = (int)(blk - PL.tile_base);
+    const int by = t / PL.ntx, bx = t - by * PL.ntx;
+    const int X0 = (bx << lb) + (sub & ((1 << (lb - 5)) - 1)) * S;
+    const int Y0 = (by << lb) + (sub >> (lb - 5)) * S;
+    const int H = a.pairs[p].H, W = a.pairs[p].W;
+    if (X0 >= W || Y0 >= H) return;
+    const int64_t img = a.pairs[p].image_offset + (int64_t)f * H * W;
+    // all loads of the block in flight together, then into LDS
+    float v[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int k = threadIdx.x + 256 * i;
+        const int r = k / SW, c = k - r * SW;
+        const int y = Y0 - B + r, x = X0 - B + c;
+        v[i] = (k < SW * SW && y >= 0 && y < H && x >= 0 && x < W) ? a.grad[img + (int64_t)y * W + x] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int k = threadIdx.x + 256 * i;
+        if (k < SW * SW) in[k / SW][k % SW] = v[i];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < SW * S; k += 256) {
+        const int r = k / S, c = k - r * S;
+        float h = 0.0f;
+#pragma unroll
+        for (int q = 0; q <= 2 * B; ++q) h = __builtin_fmaf(a.blur_w[q], in[r][c + q], h);
+        hz[r][c] = h;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < S * S / 256; ++i) {
+        const int k = threadIdx.x + 256 * i;
+        const int r = k / S, c = k - r * S;
+        if (Y0 + r >= H || X0 + c >= W) continue;
+        float e = 0.0f;
+#pragma unroll
+        for (int q = 0; q <= 2 * B; ++q) e = __builtin_fmaf(a.blur_w[q], hz[r + q][c], e);
+        a.eblur[img + (int64_t)(Y0 + r) * W + X0 + c] = e;
+    }
 }
 
 // ------------------------------------------------------------------ flow adjoint
@@ -754,7 +834,21 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             if (e != hipSuccess) return e;
         }
         const unsigned gb = (unsigned)((n_span + BPW - 1) / BPW);
-        {
+        if (a.eblur && blur >= 2) {
+            // wide blur: its adjoint once per pixel, then the gather on the
+            // unblurred footprints of B^T dL/dJ (fewer columns per lane group)
+            {
+                TimedScope ts("bwd_blur", s);
+                const unsigned nb = (unsigned)(a.order.blocks << (2 * (a.order.log_block - 5)));
+                if (blur == 2) hipLaunchKernelGGL(bwd_blur_grad<2>, dim3(nb, 2), dim3(256), 0, s, a, a.order.log_block);
+                else hipLaunchKernelGGL(bwd_blur_grad<3>, dim3(nb, 2), dim3(256), 0, s, a, a.order.log_block);
+            }
+            BwdArgs b = a;
+            b.grad = a.eblur;
+            TimedScope ts("bwd_gather", s);
+            if ((int)(3.0f * a.d_max) + 4 <= 32) hipLaunchKernelGGL((bwd_gather<0, 32>), dim3(gb), dim3(256), 0, s, b, n_span);
+            else hipLaunchKernelGGL((bwd_gather<0, 64>), dim3(gb), dim3(256), 0, s, b, n_span);
+        } else {
             TimedScope ts("bwd_gather", s);
             // slots needed: floor(3 d_max) + 4 covered pixels + 4 b padding
             const bool small = (int)(3.0f * a.d_max) + 4 + 4 * blur <= 32;
@@ -766,8 +860,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             switch (blur) {
             case 0: SP_GATHER(0); break;
             case 1: SP_GATHER(1); break;
-            case 2: SP_GATHER(2); break;
-            default: SP_GATHER(3); break;
+            default: return hipErrorInvalidValue;     // wider blurs take the path above
             }
 #undef SP_GATHER
         }

@@ -33,16 +33,6 @@ __device__ __forceinline__ int find_pair_by_chunk(const PairLayout* L, int n_pai
     return lo;
 }
 
-__device__ __forceinline__ int find_pair_by_tile(const PairLayout* L, int n_pairs, int64_t t)
-{
-    int lo = 0, hi = n_pairs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L[mid].tile_base <= t) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // ------------------------------------------------------------------ layout
 
 __global__ void __launch_bounds__(256)
@@ -132,26 +122,6 @@ prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_spa
 }
 
 // ------------------------------------------------------------------ membership
-
-// Tile rectangle touched by one particle record: its support, clipped to the
-// image, grown by the blur apron.  False when the particle adds nothing.
-__device__ __forceinline__ bool tile_rect(const float4 r, int H, int W, const RenderConfig& cfg, int ntx, int nty,
-                                          int& tx0, int& tx1, int& ty0, int& ty1)
-{
-    if (!(r.z > 0.0f)) return false;
-    const float R = 1.5f * r.z;
-    int c0, c1, r0, r1;
-    if (!support_range(r.x, R, W, c0, c1)) return false;
-    if (!support_range(r.y, R, H, r0, r1)) return false;
-    const int b = cfg.apron;
-    tx0 = c0 - b < 0 ? 0 : (c0 - b) >> cfg.log_tw;
-    ty0 = r0 - b < 0 ? 0 : (r0 - b) >> cfg.log_th;
-    tx1 = (c1 + b) >> cfg.log_tw;
-    ty1 = (r1 + b) >> cfg.log_th;
-    tx1 = tx1 > ntx - 1 ? ntx - 1 : tx1;
-    ty1 = ty1 > nty - 1 ? nty - 1 : ty1;
-    return true;
-}
 
 // ------------------------------------------------------------------ count / scatter
 
@@ -682,8 +652,8 @@ static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const Rend
 #undef SP_B
 }
 
-hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot, char* ws,
-                         const WorkspaceLayout& wl, hipStream_t s)
+hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot, char* ws,
+                       const WorkspaceLayout& wl, hipStream_t s)
 {
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + wl.status);
     PairLayout* L = reinterpret_cast<PairLayout*>(ws + wl.layout);
@@ -718,6 +688,21 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
         hipLaunchKernelGGL(bin_pass<true>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s, a.pairs, L,
                            a.n_pairs, rec0, rec1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot, char* ws,
+                         const WorkspaceLayout& wl, hipStream_t s)
+{
+    uint32_t* status = reinterpret_cast<uint32_t*>(ws + wl.status);
+    PairLayout* L = reinterpret_cast<PairLayout*>(ws + wl.layout);
+    uint32_t* tile_count = reinterpret_cast<uint32_t*>(ws + wl.tile_count);
+    int64_t* tile_offset = reinterpret_cast<int64_t*>(ws + wl.tile_offset);
+    int32_t* entries = reinterpret_cast<int32_t*>(ws + wl.entries);
+    float4* rec0 = reinterpret_cast<float4*>(ws + wl.records);
+    float4* rec1 = rec0 + tot.n_span;
+    const hipError_t e = launch_bins(a, cfg, tot, ws, wl, s);
+    if (e != hipSuccess) return e;
     if (tot.tiles > 0) {
         TimedScope ts("render_tile", s);
         const size_t lds = render_lds_bytes(cfg);

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 
+#include "device_math.hpp"
 #include "synthpix.h"
 
 namespace sp {
@@ -38,6 +39,17 @@ struct PairLayout {
     int64_t entry_cap;      // entry slots per frame
 };
 
+// Pair owning a (flattened) tile index.
+__device__ __forceinline__ int find_pair_by_tile(const PairLayout* L, int n_pairs, int64_t t)
+{
+    int lo = 0, hi = n_pairs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 struct RenderConfig {
     int tile_w, tile_h, chunk, cap;
     int log_tw, log_th;     // tile sizes are powers of two
@@ -49,6 +61,26 @@ struct RenderConfig {
 };
 
 // Totals of a batch (host side).
+// Tile rectangle touched by one particle record: its support, clipped to the
+// image, grown by the blur apron.  False when the particle adds nothing.
+__device__ __forceinline__ bool tile_rect(const float4 r, int H, int W, const RenderConfig& cfg, int ntx, int nty,
+                                          int& tx0, int& tx1, int& ty0, int& ty1)
+{
+    if (!(r.z > 0.0f)) return false;
+    const float R = 1.5f * r.z;
+    int c0, c1, r0, r1;
+    if (!support_range(r.x, R, W, c0, c1)) return false;
+    if (!support_range(r.y, R, H, r0, r1)) return false;
+    const int b = cfg.apron;
+    tx0 = c0 - b < 0 ? 0 : (c0 - b) >> cfg.log_tw;
+    ty0 = r0 - b < 0 ? 0 : (r0 - b) >> cfg.log_th;
+    tx1 = (c1 + b) >> cfg.log_tw;
+    ty1 = (r1 + b) >> cfg.log_th;
+    tx1 = tx1 > ntx - 1 ? ntx - 1 : tx1;
+    ty1 = ty1 > nty - 1 ? nty - 1 : ty1;
+    return true;
+}
+
 struct BatchTotals {
     int64_t n_span;         // max(particle_offset + n_max)
     int64_t chunks;         // sum n_chunks
@@ -84,6 +116,8 @@ hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float
 struct AdvectOrder {
     const PairLayout* L;
     const int32_t* entries;
+    int log_block;              // home blocks are 2^log_block pixels square
+    int64_t blocks;             // home blocks over all pairs
 };
 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
@@ -121,6 +155,11 @@ struct EpilogueArgs {
     float blur_w[7];
 };
 
+// Particle records and tile lists of both frames (layout, prep, count, scan,
+// scatter): what the tile renderer and the tile-major backward read.
+hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot, char* ws,
+                       const WorkspaceLayout& wl, hipStream_t s);
+
 size_t render_lds_bytes(const RenderConfig& cfg);
 bool render_shape_supported(int tile_w, int tile_h);
 
@@ -147,6 +186,7 @@ struct BwdArgs {
     const float* d;
     const float* I0;
     const float* grad;           // dL/dJ, the images' layout
+    float* eblur;                // B^T dL/dJ (workspace, the images' layout) for blur radius >= 2
     float* g_x1;
     float* g_y1;
     float* g_z;

@@ -133,9 +133,12 @@ bwd_gather(BwdArgs a, int64_t n_span)
         bool on = valid && cover_range(x, R, W, c0, c1);
         on = on && cover_range(y, R, H, r0, r1);
 
-        // raw factor tables; every slot is written (zeros outside the support)
+        // raw factor tables over the slots the gather reads, 0 .. max(c1 - c0, r1 - r0)
+        // + 4b (zeros outside the support); a group stops after its last one
+        const int n_raw = on ? max(c1 - c0, r1 - r0) + 4 * B + 1 : 0;
 #pragma unroll
         for (int m = 0; m < BT / BG; ++m) {
+            if (BG * m >= n_raw) break;
             const int slot = lane + BG * m;
             const int c = c0 - 2 * B + slot;
             float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
@@ -168,8 +171,10 @@ bwd_gather(BwdArgs a, int64_t n_span)
         if (B > 0) {
             // blurred row tables (the column ones are formed per column in the gather);
             // table slot t is pixel r0 - b + t; raw slot t + 2b - k' holds pixel q - (k' - b)
+            const int n_ty = on ? (r1 - r0 + 1) + 2 * B : 0;
 #pragma unroll
             for (int m = 0; m < BT / BG; ++m) {
+                if (BG * m >= n_ty) break;
                 const int t = lane + BG * m;
                 if (t < BT - 2 * B) {
                     float Y[3] = {0.0f, 0.0f, 0.0f};
@@ -289,21 +294,23 @@ bwd_gather(BwdArgs a, int64_t n_span)
 
 // e = B^T dL/dJ for a wide blur, once per pixel: the zero-padded blur's
 // adjoint sums w_k dL/dJ(q + k) over the taps that land inside the image (the
-// same blur, its weights being symmetric).  One 32x32 pixel block of one
-// frame per workgroup, numbered by the home blocks of the advection order
+// same blur, its weights being symmetric).  One 32x32 pixel block of both
+// frames per workgroup, numbered by the home blocks of the advection order
 // (2^lb pixels square, so 4^(lb - 5) sub-blocks each); separable, through LDS.
 template <int B>
 __global__ void __launch_bounds__(256)
 bwd_blur_grad(BwdArgs a, int lb)
 {
     constexpr int S = 32, SW = S + 2 * B;
-    constexpr int NL = (SW * SW + 255) / 256;        // loads per thread
-    __shared__ float in[SW][SW + 1];
+    constexpr int NL = (SW * SW + 255) / 256;        // loads per thread and frame
+    __shared__ float in[2][SW][SW + 1];
     __shared__ float hz[SW][S + 1];
-    const int f = blockIdx.y;
+    // XCD-contiguous numbering: neighbouring blocks (which share apron rows and
+    // columns) run on one L2
+    const unsigned bid = xcd_contiguous(blockIdx.x, gridDim.x);
     const int sub_bits = 2 * (lb - 5);
-    const int64_t blk = (int64_t)blockIdx.x >> sub_bits;
-    const int sub = (int)(blockIdx.x & ((1u << sub_bits) - 1u));
+    const int64_t blk = (int64_t)bid >> sub_bits;
+    const int sub = (int)(bid & ((1u << sub_bits) - 1u));
     const int p = find_pair_by_tile(a.order.L, a.n_pairs, blk);
     const PairLayout PL = a.order.L[p];
     const int t = (int)(blk - PL.tile_base);
@@ -312,39 +319,48 @@ bwd_blur_grad(BwdArgs a, int lb)
     const int Y0 = (by << lb) + (sub >> (lb - 5)) * S;
     const int H = a.pairs[p].H, W = a.pairs[p].W;
     if (X0 >= W || Y0 >= H) return;
-    const int64_t img = a.pairs[p].image_offset + (int64_t)f * H * W;
-    // all loads of the block in flight together, then into LDS
-    float v[NL];
+    const int64_t img = a.pairs[p].image_offset;
+    const int64_t plane = (int64_t)H * W;
+    // both frames' loads in flight together, then into LDS
+    float v[2][NL];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int k = threadIdx.x + 256 * i;
-        const int r = k / SW, c = k - r * SW;
-        const int y = Y0 - B + r, x = X0 - B + c;
-        v[i] = (k < SW * SW && y >= 0 && y < H && x >= 0 && x < W) ? a.grad[img + (int64_t)y * W + x] : 0.0f;
-    }
+    for (int f = 0; f < 2; ++f)
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int k = threadIdx.x + 256 * i;
-        if (k < SW * SW) in[k / SW][k % SW] = v[i];
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < SW * S; k += 256) {
-        const int r = k / S, c = k - r * S;
-        float h = 0.0f;
+        for (int i = 0; i < NL; ++i) {
+            const int k = threadIdx.x + 256 * i;
+            const int r = k / SW, c = k - r * SW;
+            const int y = Y0 - B + r, x = X0 - B + c;
+            v[f][i] = (k < SW * SW && y >= 0 && y < H && x >= 0 && x < W)
+                          ? a.grad[img + f * plane + (int64_t)y * W + x] : 0.0f;
+        }
 #pragma unroll
-        for (int q = 0; q <= 2 * B; ++q) h = __builtin_fmaf(a.blur_w[q], in[r][c + q], h);
-        hz[r][c] = h;
-    }
-    __syncthreads();
+    for (int f = 0; f < 2; ++f)
 #pragma unroll
-    for (int i = 0; i < S * S / 256; ++i) {
-        const int k = threadIdx.x + 256 * i;
-        const int r = k / S, c = k - r * S;
-        if (Y0 + r >= H || X0 + c >= W) continue;
-        float e = 0.0f;
+        for (int i = 0; i < NL; ++i) {
+            const int k = threadIdx.x + 256 * i;
+            if (k < SW * SW) in[f][k / SW][k % SW] = v[f][i];
+        }
 #pragma unroll
-        for (int q = 0; q <= 2 * B; ++q) e = __builtin_fmaf(a.blur_w[q], hz[r + q][c], e);
-        a.eblur[img + (int64_t)(Y0 + r) * W + X0 + c] = e;
+    for (int f = 0; f < 2; ++f) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < SW * S; k += 256) {
+            const int r = k / S, c = k - r * S;
+            float h = 0.0f;
+#pragma unroll
+            for (int q = 0; q <= 2 * B; ++q) h = __builtin_fmaf(a.blur_w[q], in[f][r][c + q], h);
+            hz[r][c] = h;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < S * S / 256; ++i) {
+            const int k = threadIdx.x + 256 * i;
+            const int r = k / S, c = k - r * S;
+            if (Y0 + r >= H || X0 + c >= W) continue;
+            float e = 0.0f;
+#pragma unroll
+            for (int q = 0; q <= 2 * B; ++q) e = __builtin_fmaf(a.blur_w[q], hz[r + q][c], e);
+            a.eblur[img + f * plane + (int64_t)(Y0 + r) * W + X0 + c] = e;
+        }
     }
 }
 
@@ -520,7 +536,7 @@ constexpr int WIN_NODES = 2048;   // LDS window capacity (nodes; 32 KB of (u, v)
 constexpr int WIN_MARGIN = 3;     // cells added around the particles' starting cells
 
 template <int CK, int SK>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
 {
     __shared__ unsigned long long win[2 * WIN_NODES];
@@ -840,8 +856,8 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             {
                 TimedScope ts("bwd_blur", s);
                 const unsigned nb = (unsigned)(a.order.blocks << (2 * (a.order.log_block - 5)));
-                if (blur == 2) hipLaunchKernelGGL(bwd_blur_grad<2>, dim3(nb, 2), dim3(256), 0, s, a, a.order.log_block);
-                else hipLaunchKernelGGL(bwd_blur_grad<3>, dim3(nb, 2), dim3(256), 0, s, a, a.order.log_block);
+                if (blur == 2) hipLaunchKernelGGL(bwd_blur_grad<2>, dim3(nb), dim3(256), 0, s, a, a.order.log_block);
+                else hipLaunchKernelGGL(bwd_blur_grad<3>, dim3(nb), dim3(256), 0, s, a, a.order.log_block);
             }
             BwdArgs b = a;
             b.grad = a.eblur;

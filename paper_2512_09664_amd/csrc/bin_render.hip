@@ -323,31 +323,40 @@ __host__ __device__ inline RenderLds render_lds(const RenderConfig& c)
     return render_lds_shape(c.tile_w, c.tile_h, c.apron, c.cap, c.wm4);
 }
 
-// Exclusive block scan of two counters (256 threads = 4 waves of 64).
-__device__ __forceinline__ void scan2(int a, int b, int* s_wave, int& ea, int& eb, int& ta, int& tb)
+// Exclusive scan of one counter over a workgroup of 256 threads (4 waves of
+// 64) in which only the first n threads can hold a nonzero value: waves past
+// them skip their in-wave scan.  In-wave inclusive scan with DPP: row shifts
+// by 1, 2, 4, 8 within each row of 16 lanes, then the row broadcasts of lanes
+// 15 and 31 into the rows above.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_add(int v)
 {
-    const int lane = threadIdx.x & 63;
+    return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+
+__device__ __forceinline__ int stage_scan(int v, int n, int* s_wave, int& total)
+{
     const int wid = threadIdx.x >> 6;
-    int ia = a, ib = b;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int xa = __shfl_up(ia, off, 64);
-        const int xb = __shfl_up(ib, off, 64);
-        if (lane >= off) { ia += xa; ib += xb; }
+    int inc = v;
+    if (wid * 64 < n) {
+        inc = dpp_add<0x111, 0xF>(inc);
+        inc = dpp_add<0x112, 0xF>(inc);
+        inc = dpp_add<0x114, 0xF>(inc);
+        inc = dpp_add<0x118, 0xF>(inc);
+        inc = dpp_add<0x142, 0xA>(inc);
+        inc = dpp_add<0x143, 0xC>(inc);
     }
-    if (lane == 63) { s_wave[wid] = ia; s_wave[4 + wid] = ib; }
+    if ((threadIdx.x & 63) == 63) s_wave[wid] = inc;
     __syncthreads();
-    int pa = 0, pb = 0;
-    ta = tb = 0;
+    int before = 0;
+    total = 0;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
-        const int va = s_wave[w], vb = s_wave[4 + w];
-        if (w < wid) { pa += va; pb += vb; }
-        ta += va;
-        tb += vb;
+        const int sw = s_wave[w];
+        if (w < wid) before += sw;
+        total += sw;
     }
-    ea = pa + ia - a;
-    eb = pb + ib - b;
+    return before + inc - v;
 }
 
 __device__ __forceinline__ uint32_t pack_box(int c0, int w, int r0, int h)
@@ -447,14 +456,16 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             box[threadIdx.x] = pack_box(c0, w, r0, h);
             if (w > 0) asum += r.w;
             // zero column factors up to the next multiple of four: the splat adds
-            // whole quads, the columns past the patch adding zero
-            for (int j = w; j < ((w + 3) & ~3); ++j) gx[threadIdx.x * WM + j] = 0.0f;
+            // whole quads, the columns past the patch adding zero (the factor pass
+            // then overwrites the quad's columns inside the patch)
+            if (w & 3)
+                *reinterpret_cast<float4*>(gx + threadIdx.x * WM + (w & ~3)) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
         // work items: one per patch line j < max(w, h); item j carries the j-th
         // column factor (if j < w) and the j-th row factor (if j < h)
         const int m = w > h ? w : h;
-        int em, dummy, tm_, tdummy;
-        scan2(m, 0, s_wave, em, dummy, tm_, tdummy);
+        int tm_;
+        const int em = stage_scan(m, n, s_wave, tm_);
         const uint16_t tag = (uint16_t)(threadIdx.x << 8);
         for (int j = 0; j < m; ++j) items[em + j] = tag | (uint16_t)j;
         __syncthreads();

@@ -23,6 +23,7 @@ if ROOT not in sys.path:
 
 METRIC = "image pairs/s & Gpx/s at 1024²,0.05 ppp; % HBM roofline; batched vs plain"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4   # CUs x SIMDs x GHz / 4 cycles per wave64 instruction = 614.4
 RENDER_SRC = os.path.join(ROOT, "paper_2512_09664_amd", "csrc", "bin_render.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_tile_scale_1024_traffic.txt")
 
@@ -276,11 +277,19 @@ def main():
     rt = kernels.get("render_tile", {"avg_us": float("nan")})
     achieved = out_bytes / (rt["avg_us"] * 1e-6) / 1e9
     traffic = None
+    valu = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = dict(ln.strip().split("=", 1) for ln in f if "=" in ln and not ln.startswith("#"))
         if tr.get("source_sha") == source_sha(RENDER_SRC) and tr.get("workload") == wl.name:
             traffic = int(tr["bytes_per_launch"])
+            if "valu_insts_per_launch" in tr:
+                # VALU issue of the same kernel: wave64 instructions counted by rocprofv3 per
+                # launch over this run's launch time, against one per 4 cycles per SIMD
+                insts = int(tr["valu_insts_per_launch"])
+                rate = insts / (rt["avg_us"] * 1e-6) / 1e9
+                valu = {"insts_per_launch": insts, "achieved": round(rate, 1), "peak": VALU_PEAK_GINST,
+                        "unit": "G wave64 instructions/s", "frac": round(rate / VALU_PEAK_GINST, 4)}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
 
@@ -361,7 +370,7 @@ def main():
             "data": "synthetic", "config": describe(wl), "gpx_per_s": round(gpx_per_s, 2),
             "step_hbm_frac": round(step_hbm_frac, 4), "kernels_us": {k: round(v["avg_us"], 2) for k, v in
                                                                       kernels.items()},
-            "plain": plain, **extras, "roofline": roofline, "cpu_baseline": cpu}
+            "plain": plain, **extras, "roofline": roofline, "valu_issue": valu, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
 

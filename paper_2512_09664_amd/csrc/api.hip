@@ -282,10 +282,15 @@ sp::RenderConfig order_config(const synthpix_pair* ph, int32_t n_pairs)
     int lb = 5;
     for (int32_t p = 0; p < n_pairs; ++p)
         while ((int64_t)((ph[p].W + (1 << lb) - 1) >> lb) * ((ph[p].H + (1 << lb) - 1) >> lb) > 16384) ++lb;
+    // 2048-particle chunks, larger for pairs with many particles (the per-chunk
+    // block histograms would outgrow the particles)
+    int chunk = 2048;
+    for (int32_t p = 0; p < n_pairs; ++p)
+        while (chunk < 16384 && ph[p].n_max / chunk > 512) chunk *= 2;
     sp::RenderConfig c{};
     c.tile_w = c.tile_h = 1 << lb;
     c.log_tw = c.log_th = lb;
-    c.chunk = 2048;
+    c.chunk = chunk;
     c.cap = 32;
     c.apron = 0;
     c.kx = c.ky = 1;     // one entry per particle

@@ -24,7 +24,18 @@ struct FlowView {
     float sx, sy;      // Gw / W, Gh / H (correctly rounded)
 };
 
-__device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, float py)
+// A rectangle of a pair's grid nodes copied to LDS (rows wi0 .., columns wj0 ..,
+// wh x ww nodes, row-major); wh = 0: none.  The nodes themselves are passed
+// separately, as the workgroup's LDS array of (u, v) floats.
+struct FlowWin {
+    int wi0, wj0, wh, ww;
+};
+
+typedef __attribute__((address_space(3))) const float lds_float;   // LDS (group segment) word
+
+__device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, float py,
+                                              const FlowWin& win = FlowWin{0, 0, 0, 0},
+                                              lds_float* lds = nullptr)
 {
     float gx = px * fv.sx - 0.5f;
     float gy = py * fv.sy - 0.5f;
@@ -36,10 +47,21 @@ __device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, floa
     i0 = i0 > fv.Gh - 2 ? fv.Gh - 2 : i0;
     const float fx = gx - (float)j0;
     const float fy = gy - (float)i0;
-    // the cell's two nodes of one grid row are adjacent: one 16-byte load per row
-    const float2* row0 = fv.F + (size_t)i0 * fv.Gw + j0;
-    const float4 r0 = load_pair(row0);
-    const float4 r1 = load_pair(row0 + fv.Gw);
+    // the cell's two nodes of one grid row are adjacent: one 16-byte load per row,
+    // from the LDS window when the cell lies inside it
+    float4 r0, r1;
+    const int li = i0 - win.wi0, lj = j0 - win.wj0;
+    if (li >= 0 && li + 1 < win.wh && lj >= 0 && lj + 1 < win.ww) {
+        // (u, v) nodes as float pairs: row li from node lj on, then row li + 1
+        lds_float* w0 = lds + 2 * (li * win.ww + lj);
+        lds_float* w1 = w0 + 2 * win.ww;
+        r0 = make_float4(w0[0], w0[1], w0[2], w0[3]);
+        r1 = make_float4(w1[0], w1[1], w1[2], w1[3]);
+    } else {
+        const float2* row0 = fv.F + (size_t)i0 * fv.Gw + j0;
+        r0 = load_pair(row0);
+        r1 = load_pair(row0 + fv.Gw);
+    }
     const float2 a = make_float2(r0.x, r0.y), b = make_float2(r0.z, r0.w);
     const float2 c = make_float2(r1.x, r1.y), e = make_float2(r1.z, r1.w);
     float2 out;

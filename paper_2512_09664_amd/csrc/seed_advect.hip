@@ -109,7 +109,7 @@ __device__ __forceinline__ float2 integrate(const FlowView& fv, float px, float 
 // thread overlap those latencies.
 template <int N>
 __device__ __forceinline__ void integrate_n(const FlowView* fv, float* px, float* py, float dt, int substeps,
-                                            int integrator)
+                                            int integrator, const FlowWin* win, lds_float* lds)
 {
     const float h = dt / (float)substeps;
     const float hh = h * 0.5f;
@@ -117,7 +117,7 @@ __device__ __forceinline__ void integrate_n(const FlowView* fv, float* px, float
         if (integrator == SP_EULER) {
             float2 u[N];
 #pragma unroll
-            for (int q = 0; q < N; ++q) u[q] = sample_flow(fv[q], px[q], py[q]);
+            for (int q = 0; q < N; ++q) u[q] = sample_flow(fv[q], px[q], py[q], win[q], lds);
 #pragma unroll
             for (int q = 0; q < N; ++q) {
                 px[q] = __builtin_fmaf(h, u[q].x, px[q]);
@@ -126,16 +126,19 @@ __device__ __forceinline__ void integrate_n(const FlowView* fv, float* px, float
         } else {
             float2 k1[N], k2[N], k3[N], k4[N];
 #pragma unroll
-            for (int q = 0; q < N; ++q) k1[q] = sample_flow(fv[q], px[q], py[q]);
+            for (int q = 0; q < N; ++q) k1[q] = sample_flow(fv[q], px[q], py[q], win[q], lds);
 #pragma unroll
             for (int q = 0; q < N; ++q)
-                k2[q] = sample_flow(fv[q], __builtin_fmaf(hh, k1[q].x, px[q]), __builtin_fmaf(hh, k1[q].y, py[q]));
+                k2[q] = sample_flow(fv[q], __builtin_fmaf(hh, k1[q].x, px[q]), __builtin_fmaf(hh, k1[q].y, py[q]),
+                                    win[q], lds);
 #pragma unroll
             for (int q = 0; q < N; ++q)
-                k3[q] = sample_flow(fv[q], __builtin_fmaf(hh, k2[q].x, px[q]), __builtin_fmaf(hh, k2[q].y, py[q]));
+                k3[q] = sample_flow(fv[q], __builtin_fmaf(hh, k2[q].x, px[q]), __builtin_fmaf(hh, k2[q].y, py[q]),
+                                    win[q], lds);
 #pragma unroll
             for (int q = 0; q < N; ++q)
-                k4[q] = sample_flow(fv[q], __builtin_fmaf(h, k3[q].x, px[q]), __builtin_fmaf(h, k3[q].y, py[q]));
+                k4[q] = sample_flow(fv[q], __builtin_fmaf(h, k3[q].x, px[q]), __builtin_fmaf(h, k3[q].y, py[q]),
+                                    win[q], lds);
 #pragma unroll
             for (int q = 0; q < N; ++q) {
                 const float su = ((k1[q].x + 2.0f * k2[q].x) + 2.0f * k3[q].x) + k4[q].x;
@@ -148,6 +151,8 @@ __device__ __forceinline__ void integrate_n(const FlowView* fv, float* px, float
 }
 
 constexpr int ADVECT_ILP = 2;
+constexpr int ADVECT_WIN_NODES = 2048;   // LDS window of grid nodes (16 KB)
+constexpr int ADVECT_WIN_MARGIN = 4;     // cells added around the starting cells
 
 // SORTED: thread slots follow the home-block order (neighbouring lanes sample
 // neighbouring grid cells, so the bilinear gathers share cache lines); each
@@ -183,7 +188,70 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
             }
         }
     }
-    integrate_n<ADVECT_ILP>(fv, px, py, ap.dt, ap.substeps, ap.integrator);
+    // SORTED: the workgroup's particles start in a compact patch of the image;
+    // the grid nodes around their starting cells (those of the first slot's
+    // pair, grown by a margin) are copied to LDS when they fit
+    __shared__ float2 s_win[ADVECT_WIN_NODES];
+    __shared__ int s_box[4][4];
+    __shared__ int s_pair;
+    FlowWin win[ADVECT_ILP];
+#pragma unroll
+    for (int q = 0; q < ADVECT_ILP; ++q) win[q] = FlowWin{0, 0, 0, 0};
+    if (SORTED) {
+        if (threadIdx.x == 0) s_pair = gi[0] >= 0 ? find_pair_from(pairs, n_pairs, g0, g0) : -1;
+        __syncthreads();
+        const int sp_ = s_pair;
+        int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -1, bj1 = -1;
+        bool mine[ADVECT_ILP];
+#pragma unroll
+        for (int q = 0; q < ADVECT_ILP; ++q) {
+            mine[q] = gi[q] >= 0 && sp_ >= 0 && fv[q].F == flow_view(pairs[sp_], flow).F;
+            if (mine[q]) {
+                const float gx = __builtin_fminf(__builtin_fmaxf(px[q] * fv[q].sx - 0.5f, 0.0f), (float)(fv[q].Gw - 1));
+                const float gy = __builtin_fminf(__builtin_fmaxf(py[q] * fv[q].sy - 0.5f, 0.0f), (float)(fv[q].Gh - 1));
+                bj0 = min(bj0, (int)gx);
+                bj1 = max(bj1, (int)gx);
+                bi0 = min(bi0, (int)gy);
+                bi1 = max(bi1, (int)gy);
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            bi0 = min(bi0, __shfl_xor(bi0, o, 64));
+            bj0 = min(bj0, __shfl_xor(bj0, o, 64));
+            bi1 = max(bi1, __shfl_xor(bi1, o, 64));
+            bj1 = max(bj1, __shfl_xor(bj1, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            s_box[threadIdx.x >> 6][0] = bi0;
+            s_box[threadIdx.x >> 6][1] = bj0;
+            s_box[threadIdx.x >> 6][2] = bi1;
+            s_box[threadIdx.x >> 6][3] = bj1;
+        }
+        __syncthreads();
+        if (sp_ >= 0) {
+            const synthpix_pair Q = pairs[sp_];
+            bi0 = max(min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0])) - ADVECT_WIN_MARGIN, 0);
+            bj0 = max(min(min(s_box[0][1], s_box[1][1]), min(s_box[2][1], s_box[3][1])) - ADVECT_WIN_MARGIN, 0);
+            bi1 = min(max(max(s_box[0][2], s_box[1][2]), max(s_box[2][2], s_box[3][2])) + ADVECT_WIN_MARGIN + 1,
+                      Q.Gh - 1);
+            bj1 = min(max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3])) + ADVECT_WIN_MARGIN + 1,
+                      Q.Gw - 1);
+            const int wh = bi1 - bi0 + 1, ww = bj1 - bj0 + 1;
+            if (bi1 >= bi0 && bj1 >= bj0 && wh * ww <= ADVECT_WIN_NODES) {
+                const float2* F = reinterpret_cast<const float2*>(flow + Q.flow_offset);
+                for (int k = threadIdx.x; k < wh * ww; k += 256) {
+                    const int r = k / ww;
+                    s_win[k] = F[(int64_t)(bi0 + r) * Q.Gw + bj0 + (k - r * ww)];
+                }
+#pragma unroll
+                for (int q = 0; q < ADVECT_ILP; ++q)
+                    if (mine[q]) win[q] = FlowWin{bi0, bj0, wh, ww};
+            }
+        }
+        __syncthreads();
+    }
+    integrate_n<ADVECT_ILP>(fv, px, py, ap.dt, ap.substeps, ap.integrator, win, (lds_float*)s_win);
 #pragma unroll
     for (int q = 0; q < ADVECT_ILP; ++q) {
         if (gi[q] >= 0) {

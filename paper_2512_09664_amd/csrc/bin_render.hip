@@ -534,14 +534,16 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
         for (int k = threadIdx.x; k < RH * Q4; k += 256) {
             const int r = k / Q4;
             const int c = (k % Q4) * 4;
+            // the fixed-point scale rides on the weights: w (v 2^-24) and (w 2^-24) v
+            // are the same binary32 products (exact power-of-two scaling, no underflow)
             const uint32_t* src = acc + r * RW + c;
             float vv[4 + 2 * B];
 #pragma unroll
-            for (int q = 0; q < 4 + 2 * B; ++q) vv[q] = (float)src[q] * FIX;
+            for (int q = 0; q < 4 + 2 * B; ++q) vv[q] = (float)src[q];
             float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f, o3 = 0.0f;
 #pragma unroll
             for (int q = 0; q <= 2 * B; ++q) {
-                const float wq = wb[q];
+                const float wq = wb[q] * FIX;
                 o0 = __builtin_fmaf(wq, vv[q], o0);
                 o1 = __builtin_fmaf(wq, vv[q + 1], o1);
                 o2 = __builtin_fmaf(wq, vv[q + 2], o2);
@@ -601,9 +603,8 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             uint32_t qv[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float t = __builtin_rintf(o[e] * Lq);
-                t = __builtin_fmaxf(t, 0.0f);
-                t = __builtin_fminf(t, Lq);
+                // clamp to [0, L] with one median (the value is finite)
+                const float t = __builtin_amdgcn_fmed3f(__builtin_rintf(o[e] * Lq), 0.0f, Lq);
                 qv[e] = (uint32_t)t;
             }
             uint16_t* dst = reinterpret_cast<uint16_t*>(a.images) + pix;

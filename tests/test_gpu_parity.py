@@ -127,6 +127,34 @@ def test_advect_order_with_large_pairs(ra):
         assert np.array_equal(gx[sl], rx) and np.array_equal(gy[sl], ry), p
 
 
+def test_advect_order_with_many_particles(ra):
+    """A pair with 1.2 M particles (more than 512 blocks of 2048, so the order
+    takes larger blocks of particles) beside a small one, with the grid nodes
+    of most workgroups in their LDS window and a flow strong enough to carry
+    some samples out of it: ordered and index-order launches agree with the
+    mirror bit for bit."""
+    sizes = [(4096, 4096), (40, 56)]
+    rng = np.random.default_rng(11)
+    fl = [wflows.lamb_oseen_grid(rng, H, W, H // 4, W // 4, max_disp=30.0) for (H, W) in sizes]
+    n = [1_200_000, 300]
+    parts = [particles.random_particles(70 + p, n[p], H, W, pad=6) for p, (H, W) in enumerate(sizes)]
+    _say("advect order, 1.2 M particles in one pair")
+    b = gu.batch_for(sizes, [f.shape[:2] for f in fl], n)
+    flow = gu.to_dev(np.concatenate([f.reshape(-1) for f in fl]))
+    x1 = gu.to_dev(np.concatenate([q["x"] for q in parts]))
+    y1 = gu.to_dev(np.concatenate([q["y"] for q in parts]))
+    ap = sp.advect_params(1.0, 4, "rk4")
+    x2, y2 = sp.advect(b, flow, ap, x1, y1)
+    ux2, uy2 = sp.advect(b, flow, ap, x1, y1, ordered=False)
+    torch.cuda.synchronize()
+    assert torch.equal(x2, ux2) and torch.equal(y2, uy2)
+    gx, gy = gu.to_np(x2), gu.to_np(y2)
+    for p, sl in enumerate(gu.pair_slices(b)):
+        H, W = sizes[p]
+        rx, ry = ra.advect(fl[p], H, W, parts[p]["x"], parts[p]["y"], 1.0, 4, "rk4")
+        assert np.array_equal(gx[sl], rx) and np.array_equal(gy[sl], ry), p
+
+
 # ----------------------------------------------------------------------------- render
 
 def _render_case(seed, sizes, n_per, d_range=(1.0, 5.0), zero_frac=0.1, edge=True):

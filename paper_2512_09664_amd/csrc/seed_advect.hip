@@ -240,8 +240,12 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
             const int wh = bi1 - bi0 + 1, ww = bj1 - bj0 + 1;
             if (bi1 >= bi0 && bj1 >= bj0 && wh * ww <= ADVECT_WIN_NODES) {
                 const float2* F = reinterpret_cast<const float2*>(flow + Q.flow_offset);
+                // window row of node k without an integer division: (k + 1/2) / ww lies at
+                // least 1/(2 ww) from an integer and, for k < 2048, the float product errs
+                // by under 2048 * 2^-21 / ww, so truncation gives floor(k / ww)
+                const float inv_ww = 1.0f / (float)ww;
                 for (int k = threadIdx.x; k < wh * ww; k += 256) {
-                    const int r = k / ww;
+                    const int r = (int)(((float)k + 0.5f) * inv_ww);
                     s_win[k] = F[(int64_t)(bi0 + r) * Q.Gw + bj0 + (k - r * ww)];
                 }
 #pragma unroll

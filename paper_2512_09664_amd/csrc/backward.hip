@@ -200,9 +200,12 @@ bwd_gather(BwdArgs a, int64_t n_span)
         }
 
         // gather: sum_q (dL/dJ)_q Ty(r) Tx(c) over the blurred support, inside the
-        // image.  The column factors are constant along a lane's column, so each
-        // lane first forms P_j = sum_r (dL/dJ) Ty_j(r) down its column(s) (three
-        // FMAs per pixel) and applies Tx afterwards.
+        // image.  The column factors are constant along a column, so each lane
+        // first forms P_j = sum_r (dL/dJ) Ty_j(r) down a column, or a slice of one
+        // (three FMAs per pixel), and applies Tx afterwards.  Columns go to lanes
+        // in blocks of 16; a block of m < 16 columns splits its rows into
+        // 16 / m' slices (m' = m rounded up to a power of two), so the lanes a
+        // narrow block would leave idle shorten its walk instead.
         float s0 = 0.0f, s_x = 0.0f, s_y = 0.0f, s_r = 0.0f;
         if (on) {
             const int nt = (c1 - c0 + 1) + 2 * B, nu = (r1 - r0 + 1) + 2 * B;
@@ -212,14 +215,23 @@ bwd_gather(BwdArgs a, int64_t n_span)
             const int uhi = nu < H - r0 + B ? nu : H - r0 + B;
             const float* __restrict__ gimg = a.grad + img + (int64_t)f * H * W;
             const float(*T)[BT] = S.rx[grp];
-            for (int t = tlo + lane; t < thi; t += BG) {
-                // walk down the column with a row pointer: whole batches of GROWS rows
-                // (their loads issued together), then batches of 4, 2 and 1
-                const float* __restrict__ q = gimg + (int64_t)(r0 - B + ulo) * W + (c0 - B + t);
+            const int ncol = thi - tlo, nrow = uhi - ulo;
+            for (int cb = 0; cb < ncol; cb += BG) {
+                const int m = ncol - cb < BG ? ncol - cb : BG;
+                const int lm = m > 8 ? 4 : m > 4 ? 3 : m > 2 ? 2 : m > 1 ? 1 : 0;   // log2 m'
+                const int cl = lane & ((1 << lm) - 1);
+                const int per = (nrow + (BG >> lm) - 1) >> (4 - lm);                // rows per slice
+                const int ua = ulo + (lane >> lm) * per;
+                const int ub = ua + per < uhi ? ua + per : uhi;
+                if (cl >= m || ua >= ub) continue;
+                const int t = tlo + cb + cl;
+                // walk down the column slice with a row pointer: whole batches of GROWS
+                // rows (their loads issued together), then batches of 4, 2 and 1
+                const float* __restrict__ q = gimg + (int64_t)(r0 - B + ua) * W + (c0 - B + t);
                 float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
-                int u = ulo;
+                int u = ua;
 #pragma unroll 1
-                for (; u + GROWS <= uhi; u += GROWS) {
+                for (; u + GROWS <= ub; u += GROWS) {
                     float e[GROWS];
 #pragma unroll
                     for (int k = 0; k < GROWS; ++k) {
@@ -236,7 +248,7 @@ bwd_gather(BwdArgs a, int64_t n_span)
                 }
 #pragma unroll
                 for (int nb = GROWS / 2; nb >= 1; nb >>= 1) {
-                    if (uhi - u >= nb) {
+                    if (ub - u >= nb) {
                         float e[GROWS / 2];
 #pragma unroll
                         for (int k = 0; k < nb; ++k) {

@@ -619,6 +619,10 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.sheet_sigma = rp->sheet_sigma;
     a.d_max = rp->d_max;
     blur_taps(rp->blur_radius, rp->blur_sigma, a.blur_w);
+    for (int32_t p = 0; p < n_pairs; ++p) {
+        a.max_h = std::max(a.max_h, (int)pairs_host[p].H);
+        a.max_w = std::max(a.max_w, (int)pairs_host[p].W);
+    }
     const hipError_t e = sp::launch_backward(a, span, n_flow, rp->advect, rp->blur_radius,
                                              sample_exponent(span, rp->advect), as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "backward launch");

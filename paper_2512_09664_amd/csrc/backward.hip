@@ -315,73 +315,55 @@ bwd_gather(BwdArgs a, int64_t n_span)
 
 // e = B^T dL/dJ for a wide blur, once per pixel: the zero-padded blur's
 // adjoint sums w_k dL/dJ(q + k) over the taps that land inside the image (the
-// same blur, its weights being symmetric).  One 32x32 pixel block of both
-// frames per workgroup, numbered by the home blocks of the advection order
-// (2^lb pixels square, so 4^(lb - 5) sub-blocks each); separable, through LDS.
+// same blur, its weights being symmetric).  A workgroup owns a strip of 32
+// output rows by 256 - 2b output columns of one frame: each thread takes one
+// input column (b apron columns on either side), issues its 32 + 2b loads
+// together and blurs them vertically in registers; the rows then pass through
+// LDS for the horizontal taps.  Rows of 256 floats keep the reads and writes
+// in whole 1 KB segments.  Workgroups are numbered (pair, frame, strip row,
+// strip column) over the batch's largest pair, XCD-contiguously.
 template <int B>
 __global__ void __launch_bounds__(256)
-bwd_blur_grad(BwdArgs a, int lb)
+bwd_blur_grad(BwdArgs a, int nsx, int nsy)
 {
-    constexpr int S = 32, SW = S + 2 * B;
-    constexpr int NL = (SW * SW + 255) / 256;        // loads per thread and frame
-    __shared__ float in[2][SW][SW + 1];
-    __shared__ float hz[SW][S + 1];
-    // XCD-contiguous numbering: neighbouring blocks (which share apron rows and
-    // columns) run on one L2
-    const unsigned bid = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int sub_bits = 2 * (lb - 5);
-    const int64_t blk = (int64_t)bid >> sub_bits;
-    const int sub = (int)(bid & ((1u << sub_bits) - 1u));
-    const int p = find_pair_by_tile(a.order.L, a.n_pairs, blk);
-    const PairLayout PL = a.order.L[p];
-    const int t = (int)(blk - PL.tile_base);
-    const int by = t / PL.ntx, bx = t - by * PL.ntx;
-    const int X0 = (bx << lb) + (sub & ((1 << (lb - 5)) - 1)) * S;
-    const int Y0 = (by << lb) + (sub >> (lb - 5)) * S;
+    constexpr int SH = 32, SO = 256 - 2 * B;
+    __shared__ float vb[SH][256];
+    const int64_t bid = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int64_t per_pair = (int64_t)2 * nsx * nsy;
+    const int p = (int)(bid / per_pair);
+    int rem = (int)(bid - (int64_t)p * per_pair);
+    const int f = rem / (nsx * nsy);
+    rem -= f * nsx * nsy;
+    const int sy = rem / nsx, sx = rem - sy * nsx;
     const int H = a.pairs[p].H, W = a.pairs[p].W;
-    if (X0 >= W || Y0 >= H) return;
-    const int64_t img = a.pairs[p].image_offset;
-    const int64_t plane = (int64_t)H * W;
-    // both frames' loads in flight together, then into LDS
-    float v[2][NL];
+    const int X0 = sx * SO, Y0 = sy * SH;
+    if (X0 >= W || Y0 >= H) return;              // the whole workgroup, before its barrier
+    const int64_t base = a.pairs[p].image_offset + (int64_t)f * H * W;
+    const int t = (int)threadIdx.x;
+    const int x = X0 - B + t;
+    const bool xin = x >= 0 && x < W;
+    float g[SH + 2 * B];
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+    for (int r = 0; r < SH + 2 * B; ++r) {
+        const int y = Y0 - B + r;
+        g[r] = (xin && y >= 0 && y < H) ? a.grad[base + (int64_t)y * W + x] : 0.0f;
+    }
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int k = threadIdx.x + 256 * i;
-            const int r = k / SW, c = k - r * SW;
-            const int y = Y0 - B + r, x = X0 - B + c;
-            v[f][i] = (k < SW * SW && y >= 0 && y < H && x >= 0 && x < W)
-                          ? a.grad[img + f * plane + (int64_t)y * W + x] : 0.0f;
-        }
+    for (int r = 0; r < SH; ++r) {
+        float v = 0.0f;
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+        for (int q = 0; q <= 2 * B; ++q) v = __builtin_fmaf(a.blur_w[q], g[r + q], v);
+        vb[r][t] = v;
+    }
+    __syncthreads();
+    if (t < B || t >= 256 - B || !xin) return;
+    const int nr = H - Y0 < SH ? H - Y0 : SH;
+#pragma unroll 4
+    for (int r = 0; r < nr; ++r) {
+        float e = 0.0f;
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int k = threadIdx.x + 256 * i;
-            if (k < SW * SW) in[f][k / SW][k % SW] = v[f][i];
-        }
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < SW * S; k += 256) {
-            const int r = k / S, c = k - r * S;
-            float h = 0.0f;
-#pragma unroll
-            for (int q = 0; q <= 2 * B; ++q) h = __builtin_fmaf(a.blur_w[q], in[f][r][c + q], h);
-            hz[r][c] = h;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < S * S / 256; ++i) {
-            const int k = threadIdx.x + 256 * i;
-            const int r = k / S, c = k - r * S;
-            if (Y0 + r >= H || X0 + c >= W) continue;
-            float e = 0.0f;
-#pragma unroll
-            for (int q = 0; q <= 2 * B; ++q) e = __builtin_fmaf(a.blur_w[q], hz[r + q][c], e);
-            a.eblur[img + f * plane + (int64_t)(Y0 + r) * W + X0 + c] = e;
-        }
+        for (int q = 0; q <= 2 * B; ++q) e = __builtin_fmaf(a.blur_w[q], vb[r][t - B + q], e);
+        a.eblur[base + (int64_t)(Y0 + r) * W + x] = e;
     }
 }
 
@@ -691,18 +673,18 @@ bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
 // on the transposed velocity Jacobian's max-row-sum over every cell (the
 // bilinear x-derivative is a blend of the cell's two edge differences, so its
 // magnitude is at most the larger one).  Also each slice's float64 sum of the
-// sheet-width terms, in a fixed order.  Blocks (pair, slice); float bits of
+// sheet-width terms, in a fixed order.  Blocks (pair, slice), ns <= BWD_SLICES
+// slices per pair (more for pairs with many particles); float bits of
 // non-negative values order like unsigned integers.
-constexpr int BOUND_SLICES = BWD_SLICES;
-
 __global__ void __launch_bounds__(256)
-bwd_bounds(BwdArgs a)
+bwd_bounds(BwdArgs a, int ns)
 {
     const synthpix_pair P = a.pairs[blockIdx.x];
     const int sl = blockIdx.y;
     float gm = 0.0f;
     double sh = 0.0;
-    for (int64_t i = (int64_t)sl * 256 + threadIdx.x; i < P.n_max; i += (int64_t)BOUND_SLICES * 256) {
+#pragma unroll 4
+    for (int64_t i = (int64_t)sl * 256 + threadIdx.x; i < P.n_max; i += (int64_t)ns * 256) {
         const int64_t g = P.particle_offset + i;
         const float u = a.gx2[g], v = a.gy2[g];
         gm = __builtin_fmaxf(gm, __builtin_fmaxf(__builtin_fabsf(u), __builtin_fabsf(v)));
@@ -712,7 +694,7 @@ bwd_bounds(BwdArgs a)
     const float2* F = reinterpret_cast<const float2*>(a.flow + P.flow_offset);
     const float sx = (float)P.Gw / (float)P.W, sy = (float)P.Gh / (float)P.H;
     float lm = 0.0f;
-    for (int i = sl; i < P.Gh - 1; i += BOUND_SLICES)
+    for (int i = sl; i < P.Gh - 1; i += ns)
         for (int j = threadIdx.x; j < P.Gw - 1; j += 256) {
             const float2 A = F[(int64_t)i * P.Gw + j], B = F[(int64_t)i * P.Gw + j + 1];
             const float2 C = F[(int64_t)(i + 1) * P.Gw + j], E = F[(int64_t)(i + 1) * P.Gw + j + 1];
@@ -742,7 +724,7 @@ bwd_bounds(BwdArgs a)
     }
     if (threadIdx.x == 0) {
         // per-block results (no same-address atomics); bwd_scale reduces them
-        const int64_t k = (int64_t)blockIdx.x * BOUND_SLICES + sl;
+        const int64_t k = (int64_t)blockIdx.x * ns + sl;
         a.bound_part[2 * k] = __builtin_fmaxf(__builtin_fmaxf(red[0][0], red[0][1]),
                                               __builtin_fmaxf(red[0][2], red[0][3]));
         a.bound_part[2 * k + 1] = __builtin_fmaxf(__builtin_fmaxf(red[1][0], red[1][1]),
@@ -759,17 +741,19 @@ bwd_bounds(BwdArgs a)
 // e = 61 - ceil(log2 K) - en no partial sum leaves the int64 range.
 __global__ void __launch_bounds__(256)
 bwd_scale(uint32_t* __restrict__ sc, synthpix_advect_params ap, int en, const double* __restrict__ sheet_part,
-          const float* __restrict__ bound_part, int n_pairs, float* __restrict__ g_sheet)
+          const float* __restrict__ bound_part, int n_pairs, int ns, float* __restrict__ g_sheet)
 {
     // per-pair sheet-width gradient: the slices' float64 sums in slice order
     for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
         double t = 0.0;
-        for (int k = 0; k < BOUND_SLICES; ++k) t += sheet_part[(int64_t)p * BOUND_SLICES + k];
+        // unrolled so that the loads are issued together; the additions stay in slice order
+#pragma unroll 16
+        for (int k = 0; k < ns; ++k) t += sheet_part[(int64_t)p * ns + k];
         g_sheet[p] = (float)t;
     }
     // maxima over all (pair, slice) blocks
     float gm = 0.0f, lm = 0.0f;
-    for (int64_t k = threadIdx.x; k < (int64_t)n_pairs * BOUND_SLICES; k += blockDim.x) {
+    for (int64_t k = threadIdx.x; k < (int64_t)n_pairs * ns; k += blockDim.x) {
         gm = __builtin_fmaxf(gm, bound_part[2 * k]);
         lm = __builtin_fmaxf(lm, bound_part[2 * k + 1]);
     }
@@ -876,9 +860,12 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             // unblurred footprints of B^T dL/dJ (fewer columns per lane group)
             {
                 TimedScope ts("bwd_blur", s);
-                const unsigned nb = (unsigned)(a.order.blocks << (2 * (a.order.log_block - 5)));
-                if (blur == 2) hipLaunchKernelGGL(bwd_blur_grad<2>, dim3(nb), dim3(256), 0, s, a, a.order.log_block);
-                else hipLaunchKernelGGL(bwd_blur_grad<3>, dim3(nb), dim3(256), 0, s, a, a.order.log_block);
+                const int so = 256 - 2 * blur;
+                const int nsx = (a.max_w + so - 1) / so, nsy = (a.max_h + 31) / 32;
+                const int64_t nb = (int64_t)a.n_pairs * 2 * nsx * nsy;
+                if (nb > 0xFFFFFFFFll) return hipErrorInvalidValue;
+                if (blur == 2) hipLaunchKernelGGL(bwd_blur_grad<2>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy);
+                else hipLaunchKernelGGL(bwd_blur_grad<3>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy);
             }
             BwdArgs b = a;
             b.grad = a.eblur;
@@ -903,9 +890,12 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         }
         {
             TimedScope ts("bwd_bounds", s);
-            hipLaunchKernelGGL(bwd_bounds, dim3((unsigned)a.n_pairs, BOUND_SLICES), dim3(256), 0, s, a);
+            // about 3072 particles per slice: 12 per thread
+            const int64_t per = (n_span + (int64_t)a.n_pairs * 3072 - 1) / ((int64_t)a.n_pairs * 3072);
+            const int ns = (int)std::min<int64_t>(std::max<int64_t>(per, 8), BWD_SLICES);
+            hipLaunchKernelGGL(bwd_bounds, dim3((unsigned)a.n_pairs, ns), dim3(256), 0, s, a, ns);
             hipLaunchKernelGGL(bwd_scale, dim3(1), dim3(256), 0, s, a.scale, ap, en, a.sheet_part, a.bound_part,
-                               a.n_pairs, a.g_sheet);
+                               a.n_pairs, ns, a.g_sheet);
         }
         {
             TimedScope ts("bwd_advect", s);

@@ -166,8 +166,8 @@ bool render_shape_supported(int tile_w, int tile_h);
 hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot,
                          char* ws, const WorkspaceLayout& wl, hipStream_t s);
 
-// Particle slices per pair of the backward's bound and sheet-sum pass.
-constexpr int BWD_SLICES = 32;
+// Most particle slices per pair of the backward's bound and sheet-sum pass.
+constexpr int BWD_SLICES = 128;
 
 // Everything the backward kernels read and write.
 struct BwdArgs {
@@ -205,6 +205,7 @@ struct BwdArgs {
     float sheet_sigma;
     float d_max;
     float blur_w[7];
+    int max_h, max_w;            // largest pair height and width of the batch
 };
 
 hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, const synthpix_advect_params& ap,

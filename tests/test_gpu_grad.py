@@ -145,6 +145,39 @@ def test_backward_matches_oracle_gradient(integ, n_sub, blur, sheet, d_range, d_
             assert np.all(G[key][sl][dead] == 0.0)
 
 
+@pytest.mark.parametrize("blur", [2, 3])
+def test_backward_wide_blur_across_strips(ra, blur):
+    """Pairs wider than one strip of the wide blur's adjoint (256 - 2b columns)
+    and with ragged row counts (not multiples of 32): every gradient against the
+    oracle, frame-2 positions from the binary32 mirror."""
+    sizes = [(70, 530), (45, 300)]
+    grids = [(18, 133), (12, 75)]
+    n = 40
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, n, 60 + blur, d_range=(1.0, 4.5))
+    rp = sp.render_params(0.5, 5.0, blur, 0.9, 0.0, 0, 0, 1.0, 2, "rk4")
+    gJ, gJ_dev = _grad_images(batch, 300 + blur)
+    ws = sp.alloc_workspace(batch, rp, backward=True)
+    g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                                workspace=ws)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    G = {k: gu.to_np(v) for k, v in g.items()}
+    for p, (H, W) in enumerate(sizes):
+        x2, y2 = ra.advect(flows[p], H, W, P["x"][p], P["y"][p], 1.0, 2, "rk4")
+        ref = _oracle_pair(P, p, flows, H, W, gJ, batch.host[p].image_offset, rp, blur, (x2, y2))
+        sl = slice(batch.host[p].particle_offset, batch.host[p].particle_offset + n)
+        kink, kink_nodes = _kinks(flows[p], H, W, P["x"][p], P["y"][p], 1.0, 2, "rk4")
+        for key in ("z", "d", "I0"):
+            _close(G[key][sl], ref[key], f"pair {p} {key}")
+        for key in ("x1", "y1"):
+            _close(G[key][sl][~kink], ref[key][~kink], f"pair {p} {key}")
+        fo = batch.host[p].flow_offset
+        gf = G["flow"][fo:fo + flows[p].size].reshape(flows[p].shape)
+        assert np.max(np.abs(gf - ref["flow"])[~kink_nodes]) <= TOL * np.max(np.abs(ref["flow"])), f"pair {p} flow"
+        term_scale = np.sum(np.abs(ref["z"] * P["z"][p])) / np.float32(rp.sheet_sigma)
+        assert abs(G["sheet"][p] - ref["s"]) <= TOL * term_scale, p
+
+
 def test_backward_matches_central_differences():
     """16x16 pair: every per-particle gradient, the sheet width and a set of flow
     nodes against float64 central differences (h = 1e-4) of the smooth forward."""

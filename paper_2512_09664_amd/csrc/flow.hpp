@@ -25,16 +25,19 @@ struct FlowView {
 };
 
 // A rectangle of a pair's grid nodes copied to LDS (rows wi0 .., columns wj0 ..,
-// wh x ww nodes, row-major); wh = 0: none.  The nodes themselves are passed
-// separately, as the workgroup's LDS array of (u, v) floats.
+// wh x ww nodes, row-major, wh and ww >= 1); NO_WIN (a single node, which holds
+// no whole cell) means none.  The nodes themselves are passed separately, as
+// the workgroup's LDS array of (u, v) floats.
 struct FlowWin {
     int wi0, wj0, wh, ww;
 };
 
+constexpr FlowWin NO_WIN = {0, 0, 1, 1};
+
 typedef __attribute__((address_space(3))) const float lds_float;   // LDS (group segment) word
 
 __device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, float py,
-                                              const FlowWin& win = FlowWin{0, 0, 0, 0},
+                                              const FlowWin& win = NO_WIN,
                                               lds_float* lds = nullptr)
 {
     float gx = px * fv.sx - 0.5f;
@@ -51,7 +54,8 @@ __device__ __forceinline__ float2 sample_flow(const FlowView& fv, float px, floa
     // from the LDS window when the cell lies inside it
     float4 r0, r1;
     const int li = i0 - win.wi0, lj = j0 - win.wj0;
-    if (li >= 0 && li + 1 < win.wh && lj >= 0 && lj + 1 < win.ww) {
+    // 0 <= li < wh - 1 and 0 <= lj < ww - 1, each as one unsigned comparison
+    if ((unsigned)li < (unsigned)(win.wh - 1) && (unsigned)lj < (unsigned)(win.ww - 1)) {
         // (u, v) nodes as float pairs: row li from node lj on, then row li + 1
         lds_float* w0 = lds + 2 * (li * win.ww + lj);
         lds_float* w1 = w0 + 2 * win.ww;

@@ -196,7 +196,7 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
     __shared__ int s_pair;
     FlowWin win[ADVECT_ILP];
 #pragma unroll
-    for (int q = 0; q < ADVECT_ILP; ++q) win[q] = FlowWin{0, 0, 0, 0};
+    for (int q = 0; q < ADVECT_ILP; ++q) win[q] = NO_WIN;
     if (SORTED) {
         if (threadIdx.x == 0) s_pair = gi[0] >= 0 ? find_pair_from(pairs, n_pairs, g0, g0) : -1;
         __syncthreads();

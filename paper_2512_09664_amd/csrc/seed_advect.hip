@@ -150,7 +150,7 @@ __device__ __forceinline__ void integrate_n(const FlowView* fv, float* px, float
     }
 }
 
-constexpr int ADVECT_ILP = 2;
+constexpr int ADVECT_ILP = 1;
 constexpr int ADVECT_WIN_NODES = 2048;   // LDS window of grid nodes (16 KB)
 constexpr int ADVECT_WIN_MARGIN = 4;     // cells added around the starting cells
 

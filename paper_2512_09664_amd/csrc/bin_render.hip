@@ -315,8 +315,8 @@ __host__ __device__ inline RenderLds render_lds_shape(int tw, int th, int apron,
     L.tables = cap * wm4;
     size_t work = (size_t)cap * 16                                  // staged (x, y, kappa, Af)
                 + (size_t)cap * 4                                   // staged patch box
-                + 2 * (size_t)L.tables * sizeof(float)              // gx, rs
-                + 2 * (size_t)L.tables * sizeof(uint16_t)           // work items
+                + (size_t)L.tables * sizeof(float)                  // column factors gx
+                + (size_t)L.tables * sizeof(uint16_t)               // work items
                 + 64;                                                // scan scratch
     size_t blur = (size_t)RH * tw * sizeof(float);
     L.bytes = (size_t)L.acc_words * 4 + (work > blur ? work : blur);
@@ -372,7 +372,7 @@ __device__ __forceinline__ uint32_t pack_box(int c0, int w, int r0, int h)
 // Tile renderer, templated on the tile shape and the blur radius (tile-local
 // index arithmetic becomes shifts, blur loops unroll).
 template <int TW, int TH, int B>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
             const float4* __restrict__ rec0, const float4* __restrict__ rec1, EpilogueArgs a, int cap, int wm4,
             const uint32_t* __restrict__ tile_count, const int64_t* __restrict__ tile_offset,
@@ -395,9 +395,8 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     float4* stg = reinterpret_cast<float4*>(acc + lay.acc_words);       // (x, y, kappa, Af)
     uint32_t* box = reinterpret_cast<uint32_t*>(stg + cap);              // c0 | w | r0 | h bytes
     float* gx = reinterpret_cast<float*>(box + cap);
-    float* rs = gx + lay.tables;
-    uint16_t* items = reinterpret_cast<uint16_t*>(rs + lay.tables);     // 2 * tables entries
-    int* s_wave = reinterpret_cast<int*>(items + 2 * lay.tables);
+    uint16_t* items = reinterpret_cast<uint16_t*>(gx + lay.tables);     // tables entries
+    int* s_wave = reinterpret_cast<int*>(items + lay.tables);
     float* tmp = reinterpret_cast<float*>(stg);   // blur scratch, reuses the particle tables
     __shared__ float s_asum[4];
     float asum = 0.0f;
@@ -474,20 +473,17 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
         const uint16_t tag = (uint16_t)(threadIdx.x << 8);
         for (int j = 0; j < m; ++j) items[em + j] = tag | (uint16_t)j;
         __syncthreads();
-        // separable factors: gx per patch column, rs = Af * gy per patch row
-        // (every argument lies in [0, 18.1]: no range check needed)
+        // separable factors: gx per patch column here; the row factor Af * gy of
+        // a patch row is formed by the splat item that adds that row (every
+        // argument lies in [0, 18.1]: no range check needed)
         for (int i = threadIdx.x; i < tm_; i += 256) {
             const int it = items[i];
             const int k = it >> 8, j = it & 255;
-            const float4 sf = stg[k];
             const uint32_t bx = box[k];
             if (j < (int)((bx >> 8) & 255u)) {
+                const float4 sf = stg[k];
                 const float dx = ((float)(rx0 + (int)(bx & 255u) + j) + 0.5f) - sf.x;
                 gx[k * WM + j] = expneg_lt80(sf.z * (dx * dx));
-            }
-            if (j < (int)(bx >> 24)) {
-                const float dy = ((float)(ry0 + (int)((bx >> 16) & 255u) + j) + 0.5f) - sf.y;
-                rs[k * WM + j] = sf.w * expneg_lt80(sf.z * (dy * dy));
             }
         }
         __syncthreads();
@@ -499,7 +495,9 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             const uint32_t bx = box[k];
             if (j >= (int)(bx >> 24)) continue;
             const int pc0 = (int)(bx & 255u), pw = (int)((bx >> 8) & 255u), pr0 = (int)((bx >> 16) & 255u);
-            const float rv = rs[k * WM + j];
+            const float4 sf = stg[k];
+            const float dy = ((float)(ry0 + pr0 + j) + 0.5f) - sf.y;
+            const float rv = sf.w * expneg_lt80(sf.z * (dy * dy));
             const float* gk = gx + k * WM;
             uint32_t* dst = acc + (pr0 + j) * RW + pc0;
             for (int cs0 = 0; cs0 < pw; cs0 += 8) {

@@ -92,7 +92,7 @@ __device__ __forceinline__ bool cover_range(float p, float R, int n, int& lo, in
 }
 
 template <int B, int BT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 32 ? 6 : 4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 32 ? 7 : 4)))
 bwd_gather(BwdArgs a, int64_t n_span)
 {
     __shared__ GatherLds<BT> S;

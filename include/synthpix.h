@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define SYNTHPIX_VERSION 1
+#define SYNTHPIX_VERSION 2
 
 typedef enum {
     SP_OK = 0,
@@ -77,7 +77,9 @@ typedef enum { SP_DIST_UNIFORM = 0, SP_DIST_NORMAL_CLIPPED = 1 } synthpix_dist;
 
 /* Device status bits (workspace word 0). */
 #define SP_STATUS_D_ABOVE_MAX   0x1u   /* a particle had d > d_max; it was not rendered */
-#define SP_STATUS_FIXED_RANGE   0x2u   /* a tile's particles could sum to >= 256 full scale */
+#define SP_STATUS_FIXED_RANGE   0x2u   /* the peaks of the particles covering one pixel row of a
+                                          tile sum to >= 256 full scale: a pixel sum could have
+                                          left the 32-bit fixed-point range */
 
 /* One image pair.  An array of these describes a batch, pairs of different size
  * included.  56 bytes, identical layout on host and device. */
@@ -142,6 +144,14 @@ synthpix_status synthpix_particle_count(int32_t H, int32_t W, double ppp, int32_
 /* The default tiling for a batch. */
 synthpix_status synthpix_default_tiling(const synthpix_pair* pairs_host, int32_t n_pairs,
                                         const synthpix_render_params* rp, synthpix_tiling* out);
+
+/* The tilings a plan's autotuner may choose for these parameters (the default
+ * first): every compiled tile shape x LDS particle capacity whose LDS fits,
+ * with 2048-particle binning blocks, then the binning block sizes it tries for
+ * the fastest of those.  Writes at most max_out entries, the total count to
+ * *n_out. */
+synthpix_status synthpix_tiling_candidates(const synthpix_render_params* rp, synthpix_tiling* out,
+                                           int32_t max_out, int32_t* n_out);
 
 /* Bytes of workspace needed by synthpix_render_pair (backward = 0) or
  * synthpix_render_pair_backward (backward = 1) for this batch and tiling.  The
@@ -221,7 +231,8 @@ synthpix_status synthpix_advect_workspace_size(const synthpix_pair* pairs_host, 
  * rasterization").  Frame 1 uses (x1, y1), frame 2 (x2, y2); z, d, I0 are
  * shared.  Particles with I0 <= 0, d <= 0 or non-finite position add nothing.
  * tiling may be NULL (default); the output does not depend on it.
- * images: device buffer, float or uint16 per rp->bits.
+ * images: device buffer, float or uint16 per rp->bits; only the pairs' image
+ * ranges are written.
  * workspace: device, 256-byte aligned, >= synthpix_workspace_size(..., 0). */
 synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
                                      int32_t n_pairs, const synthpix_tiling* tiling,
@@ -239,9 +250,13 @@ synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synt
  * rp->advect, or both NULL to have them recomputed; footprints and the
  * trajectory are recomputed, nothing else from the forward is needed.
  * grad_images: device floats dL/dJ, same layout as the forward's images.
- * Outputs (device floats, overwritten): g_x1, g_y1, g_z, g_d, g_I0 per particle,
- * g_sheet [n_pairs], g_flow with the flow's layout (zero outside the pairs'
- * grids).  Deterministic: flow-grid sums are 64-bit fixed point.
+ * Outputs (device floats, overwritten): g_x1, g_y1, g_z, g_d, g_I0 per particle
+ * (every index below the batch's particle span is written; indices in no
+ * pair's range get 0), g_sheet [n_pairs] (each pair's sheet width),
+ * g_sheet_total (optional, may be NULL: one float, the gradient with respect
+ * to a sheet width shared by all pairs, the float64 sum of the per-pair terms
+ * in pair order rounded once), g_flow with the flow's layout (zero outside the
+ * pairs' grids).  Deterministic: flow-grid sums are 64-bit fixed point.
  * tiling is unused (may be NULL); workspace: >= synthpix_workspace_size(..., 1). */
 synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host,
                                               const synthpix_pair* pairs_dev, int32_t n_pairs,
@@ -252,42 +267,61 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host,
                                               const synthpix_render_params* rp,
                                               const float* grad_images,
                                               float* g_x1, float* g_y1, float* g_z, float* g_d,
-                                              float* g_I0, float* g_sheet, float* g_flow,
-                                              void* workspace, size_t ws_bytes, void* stream);
+                                              float* g_I0, float* g_sheet, float* g_sheet_total,
+                                              float* g_flow, void* workspace, size_t ws_bytes,
+                                              void* stream);
 
 /* ------------------------------------------------------- batched, captured form */
 
-/* Device buffers of one batch, used by every launch of a plan. */
+/* Device buffers and draw key of one launch of a plan.  synthpix_plan_create
+ * takes the first launch's; synthpix_plan_launch may pass new ones for every
+ * launch.  The plan copies them into a device-side descriptor that the captured
+ * kernels read, so one captured graph serves any buffers of the plan's shapes. */
 typedef struct {
-    const float* flow;          /* every pair's flow grid at pair.flow_offset               */
-    float *x1, *y1, *x2, *y2;   /* particle positions of frame 1 and frame 2                */
-    float *z, *d, *I0;          /* per-particle out-of-plane position, diameter, intensity  */
-    void* images;               /* [pair][frame][H][W], float or uint16 per rp->bits        */
-    int32_t* n_active;          /* optional per-pair outputs of the seed step (may be NULL) */
+    const float* flow;          /* every pair's flow grid at pair.flow_offset (8-byte aligned) */
+    float *x1, *y1, *x2, *y2;   /* particle positions of frame 1 and frame 2                  */
+    float *z, *d, *I0;          /* per-particle out-of-plane position, diameter, intensity    */
+    void* images;               /* [pair][frame][H][W], float or uint16 per rp->bits          */
+    int32_t* n_active;          /* optional per-pair outputs of the seed step (may be NULL)   */
     double* ppp;
+    uint64_t seed;              /* key of every draw of the launch: particles and noise       */
+    uint64_t pair_id_base;      /* added to every pair's pair_id (Philox counter words 2, 3)  */
 } synthpix_batch_io;
 
 typedef struct synthpix_plan synthpix_plan;
 
-/* Build a plan for a fixed batch signature (pair table, parameters, buffers):
+/* Build a plan for a fixed batch signature (pair table and parameters):
  * copies the pair table to plan-owned device memory, sizes and allocates the
- * render workspace, and, if `autotune` != 0, times every compiled tiling
- * candidate (tile shape x LDS particle capacity) on this batch on `stream`
- * and keeps the fastest (all candidates give bit-identical images).  The
+ * render workspace and the device-side io descriptor, and, if `autotune` != 0,
+ * times the compiled tiling candidates (synthpix_tiling_candidates: tile shape
+ * x LDS particle capacity, then the binning block size of the fastest) on this
+ * batch and keeps the fastest (all candidates give bit-identical images).  The
  * whole path -- seed, advect, bin, render, epilogue -- is then captured once
- * into a hipGraph.  This call allocates device memory and synchronises
- * `stream`; it is the set-up call, not the hot path.
- * advance_pair_ids != 0: every launch moves the plan's pair ids on by n_pairs
- * after rendering, so launch k draws the pairs with ids pair_id + k * n_pairs. */
+ * into a hipGraph whose kernels take their buffers, draw key and pair-id
+ * offset from the descriptor.  io: the first launch's buffers (also used while
+ * autotuning, so they must be valid device memory of the batch's sizes).  The
+ * plan draws particles and noise with io->seed (rp->seed is not used).  This
+ * call validates every parameter as the eager calls do, allocates device
+ * memory and synchronises `stream`; it is the set-up call, not the hot path.
+ * advance_pair_ids != 0: every launch moves the descriptor's pair_id_base on
+ * by n_pairs after rendering, so consecutive launches without new io draw the
+ * pairs with ids pair_id + pair_id_base + k * n_pairs. */
 synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_pairs,
-                                     const synthpix_seed_params* sp, uint64_t seed,
-                                     const synthpix_advect_params* ap, const synthpix_render_params* rp,
-                                     const synthpix_batch_io* io, int32_t autotune, int32_t advance_pair_ids,
-                                     void* stream, synthpix_plan** out);
+                                     const synthpix_seed_params* sp, const synthpix_advect_params* ap,
+                                     const synthpix_render_params* rp, const synthpix_batch_io* io,
+                                     int32_t autotune, int32_t advance_pair_ids, void* stream,
+                                     synthpix_plan** out);
 
-/* Replay the captured graph on `stream` (asynchronous; no host work beyond the
- * graph launch, no allocation). */
-synthpix_status synthpix_plan_launch(synthpix_plan* plan, void* stream);
+/* Replay the captured graph on `stream` (asynchronous, no allocation).  io:
+ * NULL replays with the descriptor as it stands (the previous launch's
+ * buffers, pair ids advanced if the plan advances them); otherwise its
+ * pointers are validated on the host and a one-thread kernel stores *io into
+ * the descriptor on `stream` before the graph runs (stream-ordered, so io may
+ * be reused or freed on return).  Buffers must have the plan's sizes. */
+synthpix_status synthpix_plan_launch(synthpix_plan* plan, const synthpix_batch_io* io, void* stream);
+
+/* Device status word of the plan's last launch (see synthpix_read_status). */
+synthpix_status synthpix_plan_read_status(const synthpix_plan* plan, void* stream, uint32_t* flags);
 
 /* The tiling the plan runs with (after autotuning). */
 synthpix_status synthpix_plan_tiling(const synthpix_plan* plan, synthpix_tiling* out);

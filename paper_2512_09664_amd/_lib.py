@@ -73,7 +73,8 @@ class BatchIO(ctypes.Structure):
     _fields_ = [("flow", ctypes.c_void_p), ("x1", ctypes.c_void_p), ("y1", ctypes.c_void_p),
                 ("x2", ctypes.c_void_p), ("y2", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("d", ctypes.c_void_p), ("I0", ctypes.c_void_p), ("images", ctypes.c_void_p),
-                ("n_active", ctypes.c_void_p), ("ppp", ctypes.c_void_p)]
+                ("n_active", ctypes.c_void_p), ("ppp", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+                ("pair_id_base", ctypes.c_uint64)]
 
 
 assert ctypes.sizeof(Pair) == 56
@@ -103,12 +104,15 @@ SIGNATURES = {
     "synthpix_render_pair": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(RenderParams), _P, _P, ctypes.c_size_t, _P],
     "synthpix_render_pair_backward": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
-                                      _P, ctypes.POINTER(RenderParams), _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                      _P, ctypes.POINTER(RenderParams), _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P],
-    "synthpix_plan_create": [_PP, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.c_uint64,
-                             ctypes.POINTER(AdvectParams), ctypes.POINTER(RenderParams), ctypes.POINTER(BatchIO),
-                             ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_void_p)],
-    "synthpix_plan_launch": [_P, _P],
+    "synthpix_tiling_candidates": [ctypes.POINTER(RenderParams), ctypes.POINTER(Tiling), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)],
+    "synthpix_plan_create": [_PP, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.POINTER(AdvectParams),
+                             ctypes.POINTER(RenderParams), ctypes.POINTER(BatchIO), ctypes.c_int32, ctypes.c_int32,
+                             _P, ctypes.POINTER(ctypes.c_void_p)],
+    "synthpix_plan_launch": [_P, ctypes.POINTER(BatchIO), _P],
+    "synthpix_plan_read_status": [_P, _P, ctypes.POINTER(ctypes.c_uint32)],
     "synthpix_plan_tiling": [_P, ctypes.POINTER(Tiling)],
     "synthpix_plan_destroy": [_P],
 }

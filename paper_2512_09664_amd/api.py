@@ -138,6 +138,15 @@ def tiling(tile_w=32, tile_h=32, chunk=4096, cap=128):
     return t
 
 
+def tiling_candidates(rp):
+    """The tilings a plan's autotuner may try (``synthpix_tiling_candidates``)."""
+    n = ctypes.c_int32(0)
+    L.check(L.load().synthpix_tiling_candidates(ctypes.byref(rp), None, 0, ctypes.byref(n)))
+    arr = (L.Tiling * max(n.value, 1))()
+    L.check(L.load().synthpix_tiling_candidates(ctypes.byref(rp), arr, n.value, ctypes.byref(n)))
+    return [arr[i] for i in range(n.value)]
+
+
 def default_tiling(batch: PairBatch, rp):
     t = L.Tiling()
     L.check(L.load().synthpix_default_tiling(batch.host_ptr, batch.n_pairs, ctypes.byref(rp), ctypes.byref(t)))
@@ -233,7 +242,8 @@ def render_pair(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, tile=None, image
     _need_cuda(x1, y1, x2, y2, z, d, I0)
     dev = x1.device
     if images is None:
-        images = torch.empty(batch.n_pixels, dtype=U16 if rp.bits > 0 else torch.float32, device=dev)
+        # zero-filled: the library writes only the pairs' image ranges
+        images = torch.zeros(batch.n_pixels, dtype=U16 if rp.bits > 0 else torch.float32, device=dev)
     if workspace is None:
         workspace = alloc_workspace(batch, rp, tile)
     L.check(L.load().synthpix_render_pair(batch.host_ptr, batch.dev_ptr, batch.n_pairs,
@@ -252,6 +262,7 @@ def render_pair_backward(batch: PairBatch, flow, x1, y1, z, d, I0, rp, grad_imag
     dev = x1.device
     g = {k: torch.empty_like(x1) for k in ("x1", "y1", "z", "d", "I0")}
     g["sheet"] = torch.empty(batch.n_pairs, dtype=torch.float32, device=dev)
+    g["sheet_total"] = torch.empty((), dtype=torch.float32, device=dev)
     g["flow"] = torch.empty_like(flow)
     if workspace is None:
         workspace = alloc_workspace(batch, rp, tile, backward=True)
@@ -259,7 +270,7 @@ def render_pair_backward(batch: PairBatch, flow, x1, y1, z, d, I0, rp, grad_imag
         batch.host_ptr, batch.dev_ptr, batch.n_pairs, ctypes.byref(tile) if tile is not None else None,
         _ptr(flow), _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(z), _ptr(d), _ptr(I0), ctypes.byref(rp),
         _ptr(grad_images), _ptr(g["x1"]), _ptr(g["y1"]), _ptr(g["z"]), _ptr(g["d"]), _ptr(g["I0"]),
-        _ptr(g["sheet"]), _ptr(g["flow"]), _ptr(workspace), workspace.numel(), _stream()))
+        _ptr(g["sheet"]), _ptr(g["sheet_total"]), _ptr(g["flow"]), _ptr(workspace), workspace.numel(), _stream()))
     return g
 
 
@@ -273,29 +284,39 @@ def split_images(batch: PairBatch, images: torch.Tensor):
     return out
 
 
+_IO_KEYS = ("flow", "x1", "y1", "x2", "y2", "z", "d", "I0", "images", "n_active", "ppp")
+
+
+def _batch_io(io: dict, seed_value: int, pair_id_base: int):
+    _need_cuda(*(io[k] for k in ("flow", "x1", "y1", "x2", "y2", "z", "d", "I0", "images")))
+    b = L.BatchIO()
+    for k in _IO_KEYS:
+        t = io.get(k)
+        setattr(b, k, t.data_ptr() if t is not None else None)
+    b.seed = int(seed_value)
+    b.pair_id_base = int(pair_id_base)
+    return b
+
+
 class Plan:
     """A batch signature captured once (``synthpix_plan_create``) and replayed
     as one HIP graph per call (``synthpix_plan_launch``).
 
-    ``io`` holds the device tensors every launch reads and writes: flow, x1,
-    y1, x2, y2, z, d, I0, images and optionally n_active, ppp.  The tensors
-    must stay alive (and unmoved) as long as the plan does.
+    ``io`` holds the device tensors of the first launch: flow, x1, y1, x2, y2,
+    z, d, I0, images and optionally n_active, ppp.  ``launch`` replays into the
+    same tensors, or into new ones of the same sizes if given.  Every tensor a
+    launch uses must stay alive until the stream has run it.
     """
 
     def __init__(self, batch: PairBatch, sp, seed_value: int, ap, rp, io: dict, autotune: bool = False,
                  advance_pair_ids: bool = False):
-        _need_cuda(*(io[k] for k in ("flow", "x1", "y1", "x2", "y2", "z", "d", "I0", "images")))
         self.io = dict(io)
-        b = L.BatchIO()
-        for k in ("flow", "x1", "y1", "x2", "y2", "z", "d", "I0", "images", "n_active", "ppp"):
-            t = io.get(k)
-            setattr(b, k, t.data_ptr() if t is not None else None)
-        self._b = b
+        self.rp = rp
+        self._b = _batch_io(io, seed_value, 0)
         h = ctypes.c_void_p(None)
-        L.check(L.load().synthpix_plan_create(batch.host_ptr, batch.n_pairs, ctypes.byref(sp), int(seed_value),
-                                              ctypes.byref(ap), ctypes.byref(rp), ctypes.byref(b),
-                                              1 if autotune else 0, 1 if advance_pair_ids else 0, _stream(),
-                                              ctypes.byref(h)))
+        L.check(L.load().synthpix_plan_create(batch.host_ptr, batch.n_pairs, ctypes.byref(sp), ctypes.byref(ap),
+                                              ctypes.byref(rp), ctypes.byref(self._b), 1 if autotune else 0,
+                                              1 if advance_pair_ids else 0, _stream(), ctypes.byref(h)))
         self._h = h
 
     @property
@@ -304,8 +325,21 @@ class Plan:
         L.check(L.load().synthpix_plan_tiling(self._h, ctypes.byref(t)))
         return t
 
-    def launch(self):
-        L.check(L.load().synthpix_plan_launch(self._h, _stream()))
+    def launch(self, io: Optional[dict] = None, seed_value: Optional[int] = None, pair_id_base: int = 0):
+        """Replay the plan.  With ``io`` (and ``seed_value``), the launch reads and
+        writes those tensors with that key and pair-id offset instead."""
+        if io is None:
+            L.check(L.load().synthpix_plan_launch(self._h, None, _stream()))
+            return
+        b = _batch_io(io, self._b.seed if seed_value is None else seed_value, pair_id_base)
+        L.check(L.load().synthpix_plan_launch(self._h, ctypes.byref(b), _stream()))
+
+    def read_status(self) -> int:
+        flags = ctypes.c_uint32(0)
+        st = L.load().synthpix_plan_read_status(self._h, _stream(), ctypes.byref(flags))
+        if st not in (L.SP_OK, L.SP_ERR_DEVICE_STATUS):
+            L.check(st)
+        return flags.value
 
     def close(self):
         if self._h is not None and self._h.value:
@@ -341,7 +375,7 @@ class _RenderImages(torch.autograd.Function):
         flow, x1, y1, x2, y2, z, d, I0, sheet = ctx.saved_tensors
         g = render_pair_backward(ctx.batch, flow, x1, y1, z, d, I0, ctx.rp, grad.contiguous(), ctx.tile,
                                  x2=x2, y2=y2)
-        g_sheet = g["sheet"].sum().to(sheet.dtype).reshape(sheet.shape)
+        g_sheet = g["sheet_total"].to(sheet.dtype).reshape(sheet.shape)
         return g["flow"], g["x1"], g["y1"], g["z"], g["d"], g["I0"], g_sheet, None, None, None
 
 

@@ -233,6 +233,32 @@ int sample_exponent(int64_t n_span, const synthpix_advect_params& ap)
     return e;
 }
 
+// Seeding parameters and the particle-count rule n_max = floor(H W ppp_hi + 1/2).
+synthpix_status check_seed_params(const synthpix_seed_params* sp_, const synthpix_pair* ph, int32_t n_pairs)
+{
+    if (!sp_) return fail(SP_ERR_INVALID_ARG, "seed params must be non-NULL");
+    const synthpix_seed_params& q = *sp_;
+    if (!(q.ppp_lo > 0.0 && q.ppp_lo <= q.ppp_hi && q.ppp_hi <= 1.0))
+        return fail(SP_ERR_INVALID_ARG, "ppp range must satisfy 0 < lo <= hi <= 1");
+    if (q.d_dist != SP_DIST_UNIFORM && q.d_dist != SP_DIST_NORMAL_CLIPPED)
+        return fail(SP_ERR_INVALID_ARG, "unknown diameter distribution %d", q.d_dist);
+    if (q.d_dist == SP_DIST_UNIFORM && !(q.d_a > 0.0f && q.d_a <= q.d_b && std::isfinite(q.d_b)))
+        return fail(SP_ERR_INVALID_ARG, "uniform diameter range must satisfy 0 < d_a <= d_b");
+    if (q.d_dist == SP_DIST_NORMAL_CLIPPED &&
+        !(q.d_b >= 0.0f && q.d_lo > 0.0f && q.d_lo <= q.d_hi && std::isfinite(q.d_hi) && std::isfinite(q.d_a)))
+        return fail(SP_ERR_INVALID_ARG, "normal diameter needs std >= 0 and 0 < d_lo <= d_hi");
+    if (!(q.I0_lo >= 0.0f && q.I0_lo <= q.I0_hi && std::isfinite(q.I0_hi)))
+        return fail(SP_ERR_INVALID_ARG, "intensity range must satisfy 0 <= lo <= hi");
+    if (!(q.z_lo <= q.z_hi && std::isfinite(q.z_lo) && std::isfinite(q.z_hi)))
+        return fail(SP_ERR_INVALID_ARG, "z range must satisfy lo <= hi, finite");
+    for (int32_t p = 0; p < n_pairs; ++p) {
+        const double hw = (double)ph[p].H * (double)ph[p].W;
+        if ((double)ph[p].n_max != std::floor(hw * q.ppp_hi + 0.5))
+            return fail(SP_ERR_INVALID_ARG, "pair %d: n_max %d is not floor(H W ppp_hi + 1/2)", p, ph[p].n_max);
+    }
+    return SP_OK;
+}
+
 synthpix_status check_advect_params(const synthpix_advect_params* ap)
 {
     if (!ap) return fail(SP_ERR_INVALID_ARG, "advect params must be non-NULL");
@@ -246,9 +272,11 @@ synthpix_status check_advect_params(const synthpix_advect_params* ap)
 hipError_t enqueue_render(const synthpix_pair* pairs_dev, int32_t n_pairs, const sp::RenderConfig& cfg,
                           const sp::BatchTotals& T, const sp::WorkspaceLayout& wl, const float* x1, const float* y1,
                           const float* x2, const float* y2, const float* z, const float* d, const float* I0,
-                          const synthpix_render_params& rp, void* images, void* workspace, hipStream_t stream)
+                          const synthpix_render_params& rp, void* images, void* workspace, hipStream_t stream,
+                          const synthpix_batch_io* iod = nullptr)
 {
     sp::RenderArgs a{};
+    a.iod = iod;
     a.pairs = pairs_dev;
     a.n_pairs = n_pairs;
     a.x[0] = x1; a.y[0] = y1; a.x[1] = x2; a.y[1] = y2;
@@ -323,7 +351,8 @@ size_t order_bytes(const synthpix_pair* ph, int32_t n_pairs)
 // Builds the home-block order of (x, y) in `ws` at byte offset `base` and
 // returns it for the advection launch.
 hipError_t enqueue_order(const synthpix_pair* ph, const synthpix_pair* pd, int32_t n_pairs, const float* x,
-                         const float* y, char* ws, size_t base, hipStream_t s, sp::AdvectOrder* out)
+                         const float* y, char* ws, size_t base, hipStream_t s, sp::AdvectOrder* out,
+                         const synthpix_batch_io* iod = nullptr)
 {
     const sp::RenderConfig cfg = order_config(ph, n_pairs);
     sp::BatchTotals T;
@@ -333,7 +362,7 @@ hipError_t enqueue_order(const synthpix_pair* ph, const synthpix_pair* pd, int32
     out->entries = reinterpret_cast<const int32_t*>(ws + ol.entries);
     out->log_block = cfg.log_tw;
     out->blocks = T.tiles;
-    return sp::launch_order(pd, n_pairs, x, y, cfg, T, ws, ol, s);
+    return sp::launch_order(pd, n_pairs, x, y, cfg, T, ws, ol, s, iod);
 }
 
 extern "C" {
@@ -441,29 +470,10 @@ synthpix_status synthpix_seed(const synthpix_pair* pairs_host, const synthpix_pa
     int64_t span;
     synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
     if (st) return st;
-    if (!sp_) return fail(SP_ERR_INVALID_ARG, "seed params must be non-NULL");
+    if ((st = check_seed_params(sp_, pairs_host, n_pairs))) return st;
     const synthpix_seed_params& q = *sp_;
-    if (!(q.ppp_lo > 0.0 && q.ppp_lo <= q.ppp_hi && q.ppp_hi <= 1.0))
-        return fail(SP_ERR_INVALID_ARG, "ppp range must satisfy 0 < lo <= hi <= 1");
-    if (q.d_dist != SP_DIST_UNIFORM && q.d_dist != SP_DIST_NORMAL_CLIPPED)
-        return fail(SP_ERR_INVALID_ARG, "unknown diameter distribution %d", q.d_dist);
-    if (q.d_dist == SP_DIST_UNIFORM && !(q.d_a > 0.0f && q.d_a <= q.d_b && std::isfinite(q.d_b)))
-        return fail(SP_ERR_INVALID_ARG, "uniform diameter range must satisfy 0 < d_a <= d_b");
-    if (q.d_dist == SP_DIST_NORMAL_CLIPPED &&
-        !(q.d_b >= 0.0f && q.d_lo > 0.0f && q.d_lo <= q.d_hi && std::isfinite(q.d_hi) && std::isfinite(q.d_a)))
-        return fail(SP_ERR_INVALID_ARG, "normal diameter needs std >= 0 and 0 < d_lo <= d_hi");
-    if (!(q.I0_lo >= 0.0f && q.I0_lo <= q.I0_hi && std::isfinite(q.I0_hi)))
-        return fail(SP_ERR_INVALID_ARG, "intensity range must satisfy 0 <= lo <= hi");
-    if (!(q.z_lo <= q.z_hi && std::isfinite(q.z_lo) && std::isfinite(q.z_hi)))
-        return fail(SP_ERR_INVALID_ARG, "z range must satisfy lo <= hi, finite");
     if (!dev_ptr_ok(x) || !dev_ptr_ok(y) || !dev_ptr_ok(z) || !dev_ptr_ok(d) || !dev_ptr_ok(I0))
         return fail(SP_ERR_INVALID_ARG, "x, y, z, d, I0 must be non-NULL, 4-byte aligned device pointers");
-    for (int32_t p = 0; p < n_pairs; ++p) {
-        const double hw = (double)pairs_host[p].H * (double)pairs_host[p].W;
-        if ((double)pairs_host[p].n_max != std::floor(hw * q.ppp_hi + 0.5))
-            return fail(SP_ERR_INVALID_ARG, "pair %d: n_max %d is not floor(H W ppp_hi + 1/2)", p,
-                        pairs_host[p].n_max);
-    }
     const hipError_t e = sp::launch_seed(pairs_dev, n_pairs, span, q, seed, x, y, z, d, I0, n_active_dev, ppp_dev,
                                          as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "seed launch");
@@ -550,8 +560,8 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
                                               const float* y2, const float* z, const float* d,
                                               const float* I0, const synthpix_render_params* rp,
                                               const float* grad_images, float* g_x1, float* g_y1, float* g_z,
-                                              float* g_d, float* g_I0, float* g_sheet, float* g_flow,
-                                              void* workspace, size_t ws_bytes, void* stream)
+                                              float* g_d, float* g_I0, float* g_sheet, float* g_sheet_total,
+                                              float* g_flow, void* workspace, size_t ws_bytes, void* stream)
 {
     int64_t span;
     synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
@@ -569,6 +579,8 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     if (!dev_ptr_ok(g_x1) || !dev_ptr_ok(g_y1) || !dev_ptr_ok(g_z) || !dev_ptr_ok(g_d) || !dev_ptr_ok(g_I0) ||
         !dev_ptr_ok(g_sheet) || !dev_ptr_ok(g_flow))
         return fail(SP_ERR_INVALID_ARG, "gradient outputs must be non-NULL, 4-byte aligned device pointers");
+    if (g_sheet_total && !dev_ptr_ok(g_sheet_total))
+        return fail(SP_ERR_INVALID_ARG, "g_sheet_total must be NULL or a 4-byte aligned device pointer");
     const int64_t n_flow = flow_span(pairs_host, n_pairs);
     const int64_t n_eblur = eblur_span(pairs_host, n_pairs, rp->blur_radius);
     const BwdLayout wl = bwd_layout(span, n_flow, n_pairs, n_eblur);
@@ -607,6 +619,7 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.g_d = g_d;
     a.g_I0 = g_I0;
     a.g_sheet = g_sheet;
+    a.g_sheet_total = g_sheet_total;
     a.g_flow = g_flow;
     a.gx2 = reinterpret_cast<float*>(ws + wl.gx2);
     a.gy2 = reinterpret_cast<float*>(ws + wl.gy2);
@@ -639,11 +652,11 @@ struct synthpix_plan {
     int32_t n_pairs = 0;
     std::vector<synthpix_pair> pairs_host;
     synthpix_pair* pairs_dev = nullptr;
+    synthpix_batch_io* io_dev = nullptr;   // the descriptor the captured kernels read
     synthpix_seed_params sp{};
-    uint64_t seed = 0;
     synthpix_advect_params ap{};
     synthpix_render_params rp{};
-    synthpix_batch_io io{};
+    synthpix_batch_io io{};                // the creation io (autotuning runs on it)
     synthpix_tiling tiling{};
     int advance = 0;
     int64_t span = 0;
@@ -656,32 +669,53 @@ struct synthpix_plan {
 
 namespace {
 
-// The whole path for one batch on `s`.
+// Pointer checks of one launch's io (flow: 8-byte nodes; images per the output type).
+synthpix_status check_io(const synthpix_batch_io* io, int bits)
+{
+    if (!io) return fail(SP_ERR_INVALID_ARG, "io must be non-NULL");
+    if (!io->flow || !aligned(io->flow, 8)) return fail(SP_ERR_INVALID_ARG, "io flow must be 8-byte aligned");
+    if (!dev_ptr_ok(io->x1) || !dev_ptr_ok(io->y1) || !dev_ptr_ok(io->x2) || !dev_ptr_ok(io->y2) ||
+        !dev_ptr_ok(io->z) || !dev_ptr_ok(io->d) || !dev_ptr_ok(io->I0))
+        return fail(SP_ERR_INVALID_ARG, "io particle buffers must be non-NULL, 4-byte aligned device pointers");
+    if (io->x1 == io->x2 || io->y1 == io->y2) return fail(SP_ERR_INVALID_ARG, "io x2/y2 must not alias x1/y1");
+    if (!io->images || !aligned(io->images, bits ? 2 : 4))
+        return fail(SP_ERR_INVALID_ARG, "io images must be a non-NULL, aligned device pointer");
+    if ((io->n_active && !aligned(io->n_active, 4)) || (io->ppp && !aligned(io->ppp, 8)))
+        return fail(SP_ERR_INVALID_ARG, "io n_active / ppp must be NULL or aligned");
+    return SP_OK;
+}
+
+// The whole path for one batch on `s`, every buffer, the key and the pair-id
+// offset taken from the plan's device-side descriptor.
 hipError_t enqueue_batch(synthpix_plan* P, const synthpix_tiling& t, hipStream_t s, bool with_advance)
 {
-    hipError_t e = sp::launch_seed(P->pairs_dev, P->n_pairs, P->span, P->sp, P->seed, P->io.x1, P->io.y1, P->io.z,
-                                   P->io.d, P->io.I0, P->io.n_active, P->io.ppp, s);
+    const synthpix_batch_io& io = P->io;
+    const synthpix_batch_io* iod = P->io_dev;
+    hipError_t e = sp::launch_seed(P->pairs_dev, P->n_pairs, P->span, P->sp, io.seed, io.x1, io.y1, io.z, io.d,
+                                   io.I0, io.n_active, io.ppp, s, iod);
     if (e != hipSuccess) return e;
     sp::AdvectOrder order{nullptr, nullptr};
-    e = enqueue_order(P->pairs_host.data(), P->pairs_dev, P->n_pairs, P->io.x1, P->io.y1,
-                      static_cast<char*>(P->workspace), 0, s, &order);
+    e = enqueue_order(P->pairs_host.data(), P->pairs_dev, P->n_pairs, io.x1, io.y1, static_cast<char*>(P->workspace),
+                      0, s, &order, iod);
     if (e != hipSuccess) return e;
-    e = sp::launch_advect(P->pairs_dev, P->n_pairs, P->span, P->io.flow, P->ap, P->io.x1, P->io.y1, P->io.x2,
-                          P->io.y2, s, order);
+    e = sp::launch_advect(P->pairs_dev, P->n_pairs, P->span, io.flow, P->ap, io.x1, io.y1, io.x2, io.y2, s, order,
+                          iod);
     if (e != hipSuccess) return e;
     const sp::RenderConfig cfg = make_config(P->rp, t);
     sp::BatchTotals T;
     if (batch_totals(P->pairs_host.data(), P->n_pairs, cfg, &T) != SP_OK) return hipErrorInvalidValue;
     const sp::WorkspaceLayout wl = workspace_layout(P->n_pairs, T, 0, P->pairs_host.data());
-    e = enqueue_render(P->pairs_dev, P->n_pairs, cfg, T, wl, P->io.x1, P->io.y1, P->io.x2, P->io.y2, P->io.z,
-                       P->io.d, P->io.I0, P->rp, P->io.images, P->workspace, s);
+    e = enqueue_render(P->pairs_dev, P->n_pairs, cfg, T, wl, io.x1, io.y1, io.x2, io.y2, io.z, io.d, io.I0, P->rp,
+                       io.images, P->workspace, s, iod);
     if (e != hipSuccess) return e;
-    if (with_advance && P->advance) e = sp::launch_advance(P->pairs_dev, P->n_pairs, (uint64_t)P->n_pairs, s);
+    if (with_advance && P->advance) e = sp::launch_advance(P->io_dev, (uint64_t)P->n_pairs, s);
     return e;
 }
 
-// Every compiled tiling that fits this batch's parameters, default first.
-std::vector<synthpix_tiling> tiling_candidates(const synthpix_render_params& rp)
+const int CHUNK_CANDIDATES[] = {1024, 4096, 8192};
+
+// Tile shape x LDS capacity candidates (2048-particle binning blocks), default first.
+std::vector<synthpix_tiling> shape_candidates(const synthpix_render_params& rp)
 {
     std::vector<synthpix_tiling> out;
     out.push_back(default_tiling());
@@ -704,6 +738,7 @@ void plan_free(synthpix_plan* P)
     if (P->graph) hipGraphDestroy(P->graph);
     if (P->capture) hipStreamDestroy(P->capture);
     if (P->workspace) hipFree(P->workspace);
+    if (P->io_dev) hipFree(P->io_dev);
     if (P->pairs_dev) hipFree(P->pairs_dev);
     delete P;
 }
@@ -712,22 +747,34 @@ void plan_free(synthpix_plan* P)
 
 extern "C" {
 
+synthpix_status synthpix_tiling_candidates(const synthpix_render_params* rp, synthpix_tiling* out, int32_t max_out,
+                                           int32_t* n_out)
+{
+    if (!n_out || (max_out > 0 && !out)) return fail(SP_ERR_INVALID_ARG, "out and n_out must be non-NULL");
+    synthpix_status st = check_render_params(rp);
+    if (st) return st;
+    std::vector<synthpix_tiling> c = shape_candidates(*rp);
+    for (int ch : CHUNK_CANDIDATES) c.push_back(synthpix_tiling{c[0].tile_w, c[0].tile_h, ch, c[0].cap});
+    for (int32_t i = 0; i < max_out && i < (int32_t)c.size(); ++i) out[i] = c[i];
+    *n_out = (int32_t)c.size();
+    return SP_OK;
+}
+
 synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_pairs,
-                                     const synthpix_seed_params* sp_, uint64_t seed,
-                                     const synthpix_advect_params* ap, const synthpix_render_params* rp,
-                                     const synthpix_batch_io* io, int32_t autotune, int32_t advance_pair_ids,
-                                     void* stream, synthpix_plan** out)
+                                     const synthpix_seed_params* sp_, const synthpix_advect_params* ap,
+                                     const synthpix_render_params* rp, const synthpix_batch_io* io,
+                                     int32_t autotune, int32_t advance_pair_ids, void* stream, synthpix_plan** out)
 {
     if (!out) return fail(SP_ERR_INVALID_ARG, "out must be non-NULL");
     *out = nullptr;
     int64_t span;
     synthpix_status st = check_pairs(pairs_host, pairs_host, n_pairs, &span);
     if (st) return st;
-    if (!sp_ || !ap || !rp || !io) return fail(SP_ERR_INVALID_ARG, "parameter structs and io must be non-NULL");
+    if ((st = check_seed_params(sp_, pairs_host, n_pairs))) return st;
+    if ((st = check_advect_params(ap))) return st;
     if ((st = check_render_params(rp))) return st;
-    if (!io->flow || !dev_ptr_ok(io->x1) || !dev_ptr_ok(io->y1) || !dev_ptr_ok(io->x2) || !dev_ptr_ok(io->y2) ||
-        !dev_ptr_ok(io->z) || !dev_ptr_ok(io->d) || !dev_ptr_ok(io->I0) || !io->images)
-        return fail(SP_ERR_INVALID_ARG, "io buffers must be non-NULL, aligned device pointers");
+    if ((st = check_io(io, rp->bits))) return st;
+    if (order_bytes(pairs_host, n_pairs) == 0) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     const synthpix_tiling t0 = default_tiling();
     {
         sp::BatchTotals T;
@@ -737,7 +784,6 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
     P->n_pairs = n_pairs;
     P->pairs_host.assign(pairs_host, pairs_host + n_pairs);
     P->sp = *sp_;
-    P->seed = seed;
     P->ap = *ap;
     P->rp = *rp;
     P->io = *io;
@@ -746,20 +792,29 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
     hipStream_t s = as_stream(stream);
     hipError_t e = hipGetDevice(&P->device);
     if (e == hipSuccess) e = hipMalloc(&P->pairs_dev, sizeof(synthpix_pair) * (size_t)n_pairs);
+    if (e == hipSuccess) e = hipMalloc(&P->io_dev, sizeof(synthpix_batch_io));
     if (e == hipSuccess)
         e = hipMemcpy(P->pairs_dev, pairs_host, sizeof(synthpix_pair) * (size_t)n_pairs, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = sp::launch_store_io(P->io_dev, *io, s);
     if (e != hipSuccess) {
         plan_free(P);
         return hip_fail(e, "plan set-up");
     }
-    // workspace for the largest candidate
-    std::vector<synthpix_tiling> cands = autotune ? tiling_candidates(*rp) : std::vector<synthpix_tiling>{t0};
+    // workspace for the largest candidate (every shape with every binning block size)
+    std::vector<synthpix_tiling> shapes = autotune ? shape_candidates(*rp) : std::vector<synthpix_tiling>{t0};
     size_t ws = order_bytes(pairs_host, n_pairs);   // the advection order shares the render workspace
     std::vector<synthpix_tiling> ok;
-    for (const auto& t : cands) {
+    for (const auto& t : shapes) {
         sp::BatchTotals T;
         if (batch_totals(pairs_host, n_pairs, make_config(*rp, t), &T) != SP_OK) continue;
         ws = std::max(ws, workspace_layout(n_pairs, T, 0, pairs_host).total);
+        if (autotune)
+            for (int ch : CHUNK_CANDIDATES) {
+                synthpix_tiling tc = t;
+                tc.chunk = ch;
+                if (batch_totals(pairs_host, n_pairs, make_config(*rp, tc), &T) == SP_OK)
+                    ws = std::max(ws, workspace_layout(n_pairs, T, 0, pairs_host).total);
+            }
         ok.push_back(t);
     }
     g_err.clear();
@@ -774,21 +829,22 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
         return hip_fail(e, "plan workspace");
     }
     P->tiling = ok[0];
-    if (ok.size() > 1) {
-        // time each candidate's render of this batch (seed/advect once, render warm-up + 3 runs)
+    if (autotune) {
+        // time each candidate's render of this batch (seed/advect once, render warm-up + 3 runs):
+        // first every shape x capacity, then the binning block sizes for the fastest
         e = enqueue_batch(P, ok[0], s, false);
         hipEvent_t a = nullptr, b = nullptr;
         if (e == hipSuccess) e = hipEventCreate(&a);
         if (e == hipSuccess) e = hipEventCreate(&b);
         float best = 1e30f;
-        for (size_t i = 0; i < ok.size() && e == hipSuccess; ++i) {
-            const sp::RenderConfig cfg = make_config(*rp, ok[i]);
+        auto time_one = [&](const synthpix_tiling& t) {
+            const sp::RenderConfig cfg = make_config(*rp, t);
             sp::BatchTotals T;
-            batch_totals(pairs_host, n_pairs, cfg, &T);
+            if (batch_totals(pairs_host, n_pairs, cfg, &T) != SP_OK) return;
             const sp::WorkspaceLayout wl = workspace_layout(n_pairs, T, 0, pairs_host);
             auto run = [&]() {
                 return enqueue_render(P->pairs_dev, n_pairs, cfg, T, wl, io->x1, io->y1, io->x2, io->y2, io->z,
-                                      io->d, io->I0, *rp, io->images, P->workspace, s);
+                                      io->d, io->I0, *rp, io->images, P->workspace, s, P->io_dev);
             };
             e = run();
             if (e == hipSuccess) e = hipEventRecord(a, s);
@@ -799,8 +855,16 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
             if (e == hipSuccess && ms < best) {
                 best = ms;
-                P->tiling = ok[i];
+                P->tiling = t;
             }
+        };
+        for (size_t i = 0; i < ok.size() && e == hipSuccess; ++i) time_one(ok[i]);
+        const synthpix_tiling shape_best = P->tiling;
+        for (int ch : CHUNK_CANDIDATES) {
+            if (e != hipSuccess) break;
+            synthpix_tiling tc = shape_best;
+            tc.chunk = ch;
+            time_one(tc);
         }
         if (a) hipEventDestroy(a);
         if (b) hipEventDestroy(b);
@@ -827,12 +891,24 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
     return SP_OK;
 }
 
-synthpix_status synthpix_plan_launch(synthpix_plan* plan, void* stream)
+synthpix_status synthpix_plan_launch(synthpix_plan* plan, const synthpix_batch_io* io, void* stream)
 {
     if (!plan || !plan->exec) return fail(SP_ERR_INVALID_ARG, "plan must be a created plan");
+    if (io) {
+        const synthpix_status st = check_io(io, plan->rp.bits);
+        if (st) return st;
+        const hipError_t e = sp::launch_store_io(plan->io_dev, *io, as_stream(stream));
+        if (e != hipSuccess) return hip_fail(e, "io descriptor store");
+    }
     const hipError_t e = hipGraphLaunch(plan->exec, as_stream(stream));
     if (e != hipSuccess) return hip_fail(e, "graph launch");
     return SP_OK;
+}
+
+synthpix_status synthpix_plan_read_status(const synthpix_plan* plan, void* stream, uint32_t* flags)
+{
+    if (!plan || !plan->workspace) return fail(SP_ERR_INVALID_ARG, "plan must be a created plan");
+    return synthpix_read_status(plan->workspace, stream, flags);
 }
 
 synthpix_status synthpix_plan_tiling(const synthpix_plan* plan, synthpix_tiling* out)

@@ -287,7 +287,18 @@ bwd_gather(BwdArgs a, int64_t n_span)
         group_sync();
     }
 
-    if (!in_pair || lane != 0) return;
+    if (lane != 0) return;
+    if (!in_pair) {
+        // a slot in no pair's particle range (a gap of the packed arrays): zero gradients
+        if (g < n_span) {
+            a.g_x1[g] = 0.0f;
+            a.g_y1[g] = 0.0f;
+            a.g_z[g] = 0.0f;
+            a.g_d[g] = 0.0f;
+            a.g_I0[g] = 0.0f;
+        }
+        return;
+    }
     float gx1 = 0.0f, gy1 = 0.0f, gx2 = 0.0f, gy2 = 0.0f, gd = 0.0f, gz = 0.0f, gI0 = 0.0f, sheet = 0.0f;
     if (valid) {
         const float s = a.sheet_sigma;
@@ -741,16 +752,31 @@ bwd_bounds(BwdArgs a, int ns)
 // e = 61 - ceil(log2 K) - en no partial sum leaves the int64 range.
 __global__ void __launch_bounds__(256)
 bwd_scale(uint32_t* __restrict__ sc, synthpix_advect_params ap, int en, const double* __restrict__ sheet_part,
-          const float* __restrict__ bound_part, int n_pairs, int ns, float* __restrict__ g_sheet)
+          const float* __restrict__ bound_part, int n_pairs, int ns, float* __restrict__ g_sheet,
+          float* __restrict__ g_sheet_total)
 {
-    // per-pair sheet-width gradient: the slices' float64 sums in slice order
-    for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
+    // per-pair sheet-width gradient: the slices' float64 sums in slice order; each
+    // thread takes a contiguous run of pairs, and the shared-sheet total adds
+    // the runs' float64 sums in a fixed tree, so it too is reproducible
+    __shared__ double s_tot[256];
+    const int per = (n_pairs + 255) / 256;
+    const int pa = (int)threadIdx.x * per, pb = min(n_pairs, pa + per);
+    double run = 0.0;
+    for (int p = pa; p < pb; ++p) {
         double t = 0.0;
         // unrolled so that the loads are issued together; the additions stay in slice order
 #pragma unroll 16
         for (int k = 0; k < ns; ++k) t += sheet_part[(int64_t)p * ns + k];
         g_sheet[p] = (float)t;
+        run += t;
     }
+    s_tot[threadIdx.x] = run;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) s_tot[threadIdx.x] += s_tot[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && g_sheet_total) *g_sheet_total = (float)s_tot[0];
     // maxima over all (pair, slice) blocks
     float gm = 0.0f, lm = 0.0f;
     for (int64_t k = threadIdx.x; k < (int64_t)n_pairs * ns; k += blockDim.x) {
@@ -804,13 +830,17 @@ bwd_scale(uint32_t* __restrict__ sc, synthpix_advect_params ap, int en, const do
 }
 
 __global__ void bwd_init(unsigned long long* __restrict__ fixed, int64_t n, uint32_t* __restrict__ status,
-                         uint32_t* __restrict__ sc)
+                         uint32_t* __restrict__ sc, float* __restrict__ g_sheet, int n_pairs,
+                         float* __restrict__ g_sheet_total)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 4) {
         status[t] = 0u;
         sc[t] = 0u;
     }
+    // sheet gradients of a batch without particles (otherwise overwritten later)
+    if (t < n_pairs) g_sheet[t] = 0.0f;
+    if (t == 0 && g_sheet_total) *g_sheet_total = 0.0f;
     for (int64_t k = t; k < n; k += (int64_t)gridDim.x * blockDim.x) fixed[k] = 0ull;
 }
 
@@ -845,8 +875,10 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
 {
     {
         TimedScope ts("bwd_init", s);
-        const int64_t blocks = std::min<int64_t>((n_flow + 255) / 256 + 1, 4096);
-        hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.status, a.scale);
+        const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n_flow + 255) / 256 + 1, (a.n_pairs + 255) / 256),
+                                                 65536);
+        hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.status, a.scale,
+                           a.g_sheet, a.n_pairs, a.g_sheet_total);
     }
     if (n_span > 0) {
         if (a.recompute_x2) {
@@ -895,7 +927,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             const int ns = (int)std::min<int64_t>(std::max<int64_t>(per, 8), BWD_SLICES);
             hipLaunchKernelGGL(bwd_bounds, dim3((unsigned)a.n_pairs, ns), dim3(256), 0, s, a, ns);
             hipLaunchKernelGGL(bwd_scale, dim3(1), dim3(256), 0, s, a.scale, ap, en, a.sheet_part, a.bound_part,
-                               a.n_pairs, ns, a.g_sheet);
+                               a.n_pairs, ns, a.g_sheet, a.g_sheet_total);
         }
         {
             TimedScope ts("bwd_advect", s);

@@ -105,6 +105,15 @@ prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_spa
     const int p = find_pair_from(pairs, n_pairs, g0, g);
     const int64_t i = g - pairs[p].particle_offset;
     if (i < 0 || i >= pairs[p].n_max) return;
+    if (a.iod) {
+        a.x[0] = a.iod->x1;
+        a.y[0] = a.iod->y1;
+        a.x[1] = a.iod->x2;
+        a.y[1] = a.iod->y2;
+        a.z = a.iod->z;
+        a.d = a.iod->d;
+        a.I0 = a.iod->I0;
+    }
     const float cs = 0.5f / (a.sheet_sigma * a.sheet_sigma);
     const float z = a.z[g], d = a.d[g], I0 = a.I0[g];
     const float x1 = a.x[0][g], y1 = a.y[0][g], x2 = a.x[1][g], y2 = a.y[1][g];
@@ -201,9 +210,14 @@ template <bool SCATTER>
 __global__ void __launch_bounds__(256)
 order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
            const float* __restrict__ x, const float* __restrict__ y, RenderConfig cfg, uint32_t* __restrict__ hist,
-           const int64_t* __restrict__ tile_offset, int32_t* __restrict__ entries, unsigned n_chunks_total)
+           const int64_t* __restrict__ tile_offset, int32_t* __restrict__ entries, unsigned n_chunks_total,
+           const synthpix_batch_io* __restrict__ iod)
 {
     extern __shared__ uint32_t lh[];
+    if (iod) {
+        x = iod->x1;
+        y = iod->y1;
+    }
     const unsigned cb = xcd_contiguous(blockIdx.x, n_chunks_total);
     const int p = find_pair_by_chunk(L, n_pairs, cb);
     const synthpix_pair P = pairs[p];
@@ -398,8 +412,11 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     uint16_t* items = reinterpret_cast<uint16_t*>(gx + lay.tables);     // tables entries
     int* s_wave = reinterpret_cast<int*>(items + lay.tables);
     float* tmp = reinterpret_cast<float*>(stg);   // blur scratch, reuses the particle tables
-    __shared__ float s_asum[4];
-    float asum = 0.0f;
+    // fixed-point range bound: a difference array over the region's rows of the
+    // staged particles' integer peaks (each particle's peak added over the rows
+    // its patch covers).  Every term a particle adds to a pixel is at most its
+    // peak, so a row's prefix sum bounds every pixel sum of that row.
+    __shared__ unsigned long long s_rows[RH + 1];
 
     // one (frame, tile) item per workgroup; XCD-contiguous numbering keeps
     // neighbouring tiles (which share particles) on one L2
@@ -409,7 +426,12 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     const int p = find_pair_by_tile(L, n_pairs, tile);
     const int pW = pairs[p].W, pH = pairs[p].H;
     const int64_t p_off = pairs[p].particle_offset, p_img = pairs[p].image_offset;
-    const uint64_t pid = pairs[p].pair_id;
+    uint64_t pid = pairs[p].pair_id;
+    if (a.iod) {
+        a.images = a.iod->images;
+        a.seed = a.iod->seed;
+        pid += a.iod->pair_id_base;
+    }
     const int64_t tile_base = L[p].tile_base;
     const int ntx = L[p].ntx;
     const int tl = (int)(tile - tile_base);
@@ -423,6 +445,7 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
 
     for (int k = threadIdx.x; k < (lay.acc_words >> 2); k += 256)
         reinterpret_cast<uint4*>(acc)[k] = make_uint4(0u, 0u, 0u, 0u);
+    for (int k = threadIdx.x; k <= RH; k += 256) s_rows[k] = 0ull;
 
     // the record of a thread's particle in the next pass is loaded one pass ahead,
     // so its two dependent loads overlap the current pass's factor and splat work
@@ -458,7 +481,11 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             }
             stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (r.z * r.z), r.w);
             box[threadIdx.x] = pack_box(c0, w, r0, h);
-            if (w > 0) asum += r.w;
+            if (w > 0) {
+                const unsigned long long pk = (unsigned long long)r.w;
+                atomicAdd(&s_rows[r0], pk);
+                atomicAdd(&s_rows[r0 + h], 0ull - pk);
+            }
             // zero column factors up to the next multiple of four: the splat adds
             // whole quads, the columns past the patch adding zero (the factor pass
             // then overwrites the quad's columns inside the patch)
@@ -516,14 +543,29 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             }
         }
     }
-    // the sum of all staged peaks bounds every pixel's sum: flag a tile where it
-    // could reach 2^32 (float sum, compared with a margin for its rounding)
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) asum += __shfl_xor(asum, o, 64);
-    if ((threadIdx.x & 63) == 0) s_asum[threadIdx.x >> 6] = asum;
+    // prefix sums of the row bounds (wave 0): flag a row whose bound reaches 2^32
     __syncthreads();
-    if (threadIdx.x == 0 && (s_asum[0] + s_asum[1]) + (s_asum[2] + s_asum[3]) >= 4294000000.0f)
-        atomicOr(status, SP_STATUS_FIXED_RANGE);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        unsigned long long carry = 0ull, top = 0ull;
+        for (int c = 0; c <= RH; c += 64) {
+            unsigned long long v = c + lane <= RH ? s_rows[c + lane] : 0ull;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned long long u = __shfl_up(v, o, 64);
+                if (lane >= o) v += u;
+            }
+            v += carry;
+            top = v > top ? v : top;
+            carry = __shfl(v, 63, 64);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const unsigned long long u = __shfl_xor(top, o, 64);
+            top = u > top ? u : top;
+        }
+        if (lane == 0 && top >= (1ull << 32)) atomicOr(status, SP_STATUS_FIXED_RANGE);
+    }
 
     // fixed point -> float happens as the blur / store passes read the accumulator
     constexpr float FIX = 0x1p-24f;
@@ -657,6 +699,7 @@ static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const Rend
     ea.noise_sigma = a.noise_sigma;
     ea.bits = a.bits;
     ea.seed = a.seed;
+    ea.iod = a.iod;
     for (int q = 0; q < 7; ++q) ea.blur_w[q] = a.blur_w[q];
 #define SP_B(B_)                                                                                                 \
     case B_:                                                                                                     \
@@ -737,7 +780,7 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
 
 hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float* x, const float* y,
                         const RenderConfig& cfg, const BatchTotals& tot, char* ws, const OrderLayout& ol,
-                        hipStream_t s)
+                        hipStream_t s, const synthpix_batch_io* iod)
 {
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + ol.status);
     PairLayout* L = reinterpret_cast<PairLayout*>(ws + ol.layout);
@@ -750,10 +793,10 @@ hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float
     if (tot.chunks == 0) return hipGetLastError();
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
     hipLaunchKernelGGL(order_pass<false>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
-                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks);
+                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks, iod);
     launch_scans(L, n_pairs, hist, tile_count, tile_offset, tot.tiles, 1, s);
     hipLaunchKernelGGL(order_pass<true>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
-                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks);
+                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks, iod);
     return hipGetLastError();
 }
 

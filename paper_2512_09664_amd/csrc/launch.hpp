@@ -108,9 +108,12 @@ struct OrderLayout {
     size_t status, layout, tile_count, tile_offset, hist, entries, total;
 };
 
+// A captured plan's kernels read their buffers, draw key and pair-id offset from
+// a device-side descriptor (iod); eager calls pass the buffers directly and a
+// null descriptor.
 hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float* x, const float* y,
                         const RenderConfig& cfg, const BatchTotals& tot, char* ws, const OrderLayout& ol,
-                        hipStream_t s);
+                        hipStream_t s, const synthpix_batch_io* iod = nullptr);
 
 // The order a launch of the advection kernel follows (null: particle index order).
 struct AdvectOrder {
@@ -122,13 +125,20 @@ struct AdvectOrder {
 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
                        const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
-                       float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s);
+                       float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s,
+                       const synthpix_batch_io* iod = nullptr);
 
-hipError_t launch_advance(synthpix_pair* pairs_dev, int n_pairs, uint64_t step, hipStream_t s);
+// Moves a descriptor's pair_id_base on by `step` (the next batch of pairs).
+hipError_t launch_advance(synthpix_batch_io* iod, uint64_t step, hipStream_t s);
+
+// Stores *io into the device-side descriptor (one thread; the value travels as
+// a kernel argument, so the call is stream-ordered and io may be reused at once).
+hipError_t launch_store_io(synthpix_batch_io* iod, const synthpix_batch_io& io, hipStream_t s);
 
 hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
                          const synthpix_advect_params& ap, const float* x1, const float* y1, float* x2,
-                         float* y2, hipStream_t s, AdvectOrder order = AdvectOrder{nullptr, nullptr});
+                         float* y2, hipStream_t s, AdvectOrder order = AdvectOrder{nullptr, nullptr},
+                         const synthpix_batch_io* iod = nullptr);
 
 struct RenderArgs {
     const synthpix_pair* pairs;
@@ -144,6 +154,7 @@ struct RenderArgs {
     int bits;
     uint64_t seed;
     float blur_w[7];
+    const synthpix_batch_io* iod;   // captured plans: buffers, key and pair-id offset (else null)
 };
 
 // What the tile renderer's epilogue needs (kept small: kernel arguments live in SGPRs).
@@ -153,6 +164,7 @@ struct EpilogueArgs {
     float noise_sigma;
     int bits;
     float blur_w[7];
+    const synthpix_batch_io* iod;
 };
 
 // Particle records and tile lists of both frames (layout, prep, count, scan,
@@ -193,6 +205,7 @@ struct BwdArgs {
     float* g_d;
     float* g_I0;
     float* g_sheet;
+    float* g_sheet_total;        // optional (null): the sum over pairs
     float* g_flow;
     float* gx2;                  // dL/dx2, dL/dy2 (workspace)
     float* gy2;

@@ -16,10 +16,10 @@
 namespace sp {
 
 // The pair's drawn ppp and active-particle count (Philox stream 5, index 0).
-__device__ __forceinline__ int pair_active(const synthpix_pair& P, const synthpix_seed_params& prm, uint64_t seed,
-                                           double* ppp_out)
+__device__ __forceinline__ int pair_active(const synthpix_pair& P, uint64_t pid, const synthpix_seed_params& prm,
+                                           uint64_t seed, double* ppp_out)
 {
-    const u32x4 w = draw(0u, STREAM_PAIR, P.pair_id, seed);
+    const u32x4 w = draw(0u, STREAM_PAIR, pid, seed);
     const double ppp = prm.ppp_lo + (prm.ppp_hi - prm.ppp_lo) * (double)u24(w.a);
     const double na = floor((double)P.H * (double)P.W * ppp + 0.5);
     *ppp_out = ppp;
@@ -28,12 +28,20 @@ __device__ __forceinline__ int pair_active(const synthpix_pair& P, const synthpi
 
 __global__ void __launch_bounds__(256)
 pair_scalars_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, synthpix_seed_params prm,
-                    uint64_t seed, int32_t* __restrict__ n_active_out, double* __restrict__ ppp_out)
+                    uint64_t seed, int32_t* __restrict__ n_active_out, double* __restrict__ ppp_out,
+                    const synthpix_batch_io* __restrict__ iod)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_pairs) return;
+    uint64_t base = 0;
+    if (iod) {
+        seed = iod->seed;
+        base = iod->pair_id_base;
+        n_active_out = iod->n_active;
+        ppp_out = iod->ppp;
+    }
     double ppp;
-    const int na = pair_active(pairs[p], prm, seed, &ppp);
+    const int na = pair_active(pairs[p], pairs[p].pair_id + base, prm, seed, &ppp);
     if (n_active_out) n_active_out[p] = na;
     if (ppp_out) ppp_out[p] = ppp;
 }
@@ -42,7 +50,7 @@ __global__ void __launch_bounds__(256)
 seed_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span,
             synthpix_seed_params prm, uint64_t seed,
             float* __restrict__ x, float* __restrict__ y, float* __restrict__ z,
-            float* __restrict__ d, float* __restrict__ I0)
+            float* __restrict__ d, float* __restrict__ I0, const synthpix_batch_io* __restrict__ iod)
 {
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t g = g0 + threadIdx.x;
@@ -52,12 +60,22 @@ seed_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span
     const int64_t i64 = g - P.particle_offset;
     if (i64 < 0 || i64 >= P.n_max) return;
     const uint32_t i = (uint32_t)i64;
+    uint64_t pid = P.pair_id;
+    if (iod) {
+        x = iod->x1;
+        y = iod->y1;
+        z = iod->z;
+        d = iod->d;
+        I0 = iod->I0;
+        seed = iod->seed;
+        pid += iod->pair_id_base;
+    }
 
     double ppp;
-    const int n_active = pair_active(P, prm, seed, &ppp);
+    const int n_active = pair_active(P, pid, prm, seed, &ppp);
 
-    const u32x4 gw = draw(i, STREAM_GEOM, P.pair_id, seed);
-    const u32x4 hw = draw(i, STREAM_PHOTO, P.pair_id, seed);
+    const u32x4 gw = draw(i, STREAM_GEOM, pid, seed);
+    const u32x4 hw = draw(i, STREAM_PHOTO, pid, seed);
     x[g] = u24(gw.a) * (float)P.W;
     y[g] = u24(gw.b) * (float)P.H;
     z[g] = __builtin_fmaf(prm.z_hi - prm.z_lo, u24(gw.c), prm.z_lo);
@@ -162,8 +180,16 @@ __global__ void __launch_bounds__(256)
 advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span,
               const float* __restrict__ flow, synthpix_advect_params ap,
               const float* __restrict__ x1, const float* __restrict__ y1,
-              float* __restrict__ x2, float* __restrict__ y2, AdvectOrder order)
+              float* __restrict__ x2, float* __restrict__ y2, AdvectOrder order,
+              const synthpix_batch_io* __restrict__ iod)
 {
+    if (iod) {
+        flow = iod->flow;
+        x1 = iod->x1;
+        y1 = iod->y1;
+        x2 = iod->x2;
+        y2 = iod->y2;
+    }
     // consecutive particle blocks (same pair, same flow grid) stay on one XCD
     const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * (256 * ADVECT_ILP);
     const int64_t base = g0 + threadIdx.x;
@@ -265,50 +291,61 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
     }
 }
 
-// Moves a batch's pair table on to the next batch of the same shape: every
-// pair_id grows by `step` (the batch size), so replays draw fresh particles.
-__global__ void advance_pair_ids(synthpix_pair* __restrict__ pairs, int n_pairs, uint64_t step)
+// Moves a captured plan's descriptor on to the next batch of the same shape:
+// the pair-id offset grows by `step` (the batch size), so replays draw fresh
+// particles.
+__global__ void advance_pair_ids(synthpix_batch_io* __restrict__ iod, uint64_t step)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n_pairs) pairs[p].pair_id += step;
+    if (threadIdx.x == 0) iod->pair_id_base += step;
 }
 
-hipError_t launch_advance(synthpix_pair* pairs_dev, int n_pairs, uint64_t step, hipStream_t s)
+__global__ void store_io(synthpix_batch_io* __restrict__ iod, synthpix_batch_io io)
 {
-    hipLaunchKernelGGL(advance_pair_ids, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, pairs_dev,
-                       n_pairs, step);
+    if (threadIdx.x == 0) *iod = io;
+}
+
+hipError_t launch_advance(synthpix_batch_io* iod, uint64_t step, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_pair_ids, dim3(1), dim3(64), 0, s, iod, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_io(synthpix_batch_io* iod, const synthpix_batch_io& io, hipStream_t s)
+{
+    hipLaunchKernelGGL(store_io, dim3(1), dim3(64), 0, s, iod, io);
     return hipGetLastError();
 }
 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
                        const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
-                       float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s)
+                       float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s,
+                       const synthpix_batch_io* iod)
 {
     TimedScope ts("seed", s);
-    if (n_active || ppp)
+    if (n_active || ppp || iod)
         hipLaunchKernelGGL(pair_scalars_kernel, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, pairs_dev,
-                           n_pairs, prm, seed, n_active, ppp);
+                           n_pairs, prm, seed, n_active, ppp, iod);
     if (n_span > 0) {
         const int64_t blocks = (n_span + 255) / 256;
         hipLaunchKernelGGL(seed_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
-                           prm, seed, x, y, z, d, I0);
+                           prm, seed, x, y, z, d, I0, iod);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
                          const synthpix_advect_params& ap, const float* x1, const float* y1, float* x2,
-                         float* y2, hipStream_t s, AdvectOrder order)
+                         float* y2, hipStream_t s, AdvectOrder order, const synthpix_batch_io* iod)
 {
     if (n_span <= 0) return hipSuccess;
     const int64_t blocks = (n_span + 256 * ADVECT_ILP - 1) / (256 * ADVECT_ILP);
     TimedScope ts("advect", s);
     if (order.entries)
         hipLaunchKernelGGL(advect_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
-                           flow, ap, x1, y1, x2, y2, order);
+                           flow, ap, x1, y1, x2, y2, order, iod);
     else
         hipLaunchKernelGGL(advect_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
-                           flow, ap, x1, y1, x2, y2, order);
+                           flow, ap, x1, y1, x2, y2, order, iod);
     return hipGetLastError();
 }
 

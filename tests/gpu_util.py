@@ -47,13 +47,18 @@ def params_of(wl, bits=None, noise=None):
 
 
 def run_pipeline(wl, bits=None, noise=None, tile=None):
-    """seed -> advect -> render on the GPU; returns (batch, flows, particles, x2, y2, images)."""
+    """seed -> advect -> render on the GPU; returns (batch, flows, particles, x2, y2, images).
+    The device status word must come back clear (no diameter above d_max, no
+    row whose peaks could leave the fixed-point range)."""
     flows, batch, flow_dev = workload_inputs(wl)
     sprm, aprm, rprm = params_of(wl, bits, noise)
     P = sp.seed(batch, sprm, wl.seed)
     x2, y2 = sp.advect(batch, flow_dev, aprm, P["x"], P["y"])
-    img = sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, tile)
+    ws = sp.alloc_workspace(batch, rprm, tile)
+    img = sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, tile, workspace=ws)
     torch.cuda.synchronize()
+    flags = sp.read_status(ws)
+    assert flags == 0, f"device status {flags:#x} on {wl.name}"
     return batch, flows, P, x2, y2, img
 
 

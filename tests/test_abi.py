@@ -164,31 +164,76 @@ def test_advect_and_render_validation(L):
 
 
 def test_plan_validation(L):
+    """synthpix_plan_create refuses what the eager calls refuse (seed, advect and
+    render parameters, io pointers) before touching the device."""
     lib = L.load()
-    pairs = _pairs(L, [(64, 64, 16, 16, 100)])
+    pairs = _pairs(L, [(64, 64, 16, 16, 82)])
     sp = L.SeedParams(0.02, 0.02, 0, 1.0, 5.0, 0.0, 0.0, 0.8, 1.0, -1.0, 1.0)
     ap = L.AdvectParams(1.0, 1, 0)
     rp = _rp(L)
     fake = [0x1000 * (k + 1) for k in range(9)]
     io = L.BatchIO(*fake)
     h = ctypes.c_void_p()
-    args = (pairs, 1, ctypes.byref(sp), 0, ctypes.byref(ap), ctypes.byref(rp))
-    assert lib.synthpix_plan_create(*args, ctypes.byref(io), 0, 0, None, None) == L.SP_ERR_INVALID_ARG
-    assert lib.synthpix_plan_create(*args, None, 0, 0, None, ctypes.byref(h)) == L.SP_ERR_INVALID_ARG
+
+    def create(pairs_=pairs, n=1, sp_=sp, ap_=ap, rp_=rp, io_=io, out=ctypes.byref(h)):
+        return lib.synthpix_plan_create(pairs_, n, ctypes.byref(sp_) if sp_ is not None else None,
+                                        ctypes.byref(ap_) if ap_ is not None else None, ctypes.byref(rp_),
+                                        ctypes.byref(io_) if io_ is not None else None, 0, 0, None, out)
+
+    assert create(out=None) == L.SP_ERR_INVALID_ARG
+    assert create(io_=None) == L.SP_ERR_INVALID_ARG
+    assert create(n=0) == L.SP_ERR_INVALID_ARG
+    assert create(sp_=None) == L.SP_ERR_INVALID_ARG
+    assert create(ap_=None) == L.SP_ERR_INVALID_ARG
     bad_io = L.BatchIO(*fake)
     bad_io.flow = None
-    assert lib.synthpix_plan_create(*args, ctypes.byref(bad_io), 0, 0, None,
-                                    ctypes.byref(h)) == L.SP_ERR_INVALID_ARG
+    assert create(io_=bad_io) == L.SP_ERR_INVALID_ARG
+    bad_io = L.BatchIO(*fake)
+    bad_io.flow = 0x1004                                # not 8-byte aligned
+    assert create(io_=bad_io) == L.SP_ERR_INVALID_ARG
+    assert b"flow" in lib.synthpix_last_error()
+    bad_io = L.BatchIO(*fake)
+    bad_io.x2 = bad_io.x1                               # aliasing
+    assert create(io_=bad_io) == L.SP_ERR_INVALID_ARG
     bad_rp = _rp(L)
     bad_rp.bits = 17
-    assert lib.synthpix_plan_create(pairs, 1, ctypes.byref(sp), 0, ctypes.byref(ap), ctypes.byref(bad_rp),
-                                    ctypes.byref(io), 0, 0, None, ctypes.byref(h)) == L.SP_ERR_INVALID_ARG
-    assert lib.synthpix_plan_create(pairs, 0, ctypes.byref(sp), 0, ctypes.byref(ap), ctypes.byref(rp),
-                                    ctypes.byref(io), 0, 0, None, ctypes.byref(h)) == L.SP_ERR_INVALID_ARG
+    assert create(rp_=bad_rp) == L.SP_ERR_INVALID_ARG
+    for bad_ap in (L.AdvectParams(1.0, 1, 7), L.AdvectParams(1.0, 0, 0), L.AdvectParams(float("nan"), 1, 0)):
+        assert create(ap_=bad_ap) == L.SP_ERR_INVALID_ARG
+    for bad_sp in (L.SeedParams(0.02, 0.03, 0, 1.0, 5.0, 0.0, 0.0, 0.8, 1.0, -1.0, 1.0),   # n_max rule
+                   L.SeedParams(0.0, 0.02, 0, 1.0, 5.0, 0.0, 0.0, 0.8, 1.0, -1.0, 1.0),    # ppp_lo = 0
+                   L.SeedParams(0.02, 0.02, 9, 1.0, 5.0, 0.0, 0.0, 0.8, 1.0, -1.0, 1.0)):  # distribution
+        assert create(sp_=bad_sp) == L.SP_ERR_INVALID_ARG
     assert not h.value
-    assert lib.synthpix_plan_launch(None, None) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_plan_launch(None, None, None) == L.SP_ERR_INVALID_ARG
     assert lib.synthpix_plan_tiling(None, None) == L.SP_ERR_INVALID_ARG
+    flags = ctypes.c_uint32()
+    assert lib.synthpix_plan_read_status(None, None, ctypes.byref(flags)) == L.SP_ERR_INVALID_ARG
     assert lib.synthpix_plan_destroy(None) == L.SP_OK
+
+
+def test_tiling_candidates(L):
+    """The autotuner's candidate list: the default first, every entry a valid,
+    compiled tiling, the binning block sizes after the shapes."""
+    lib = L.load()
+    rp = _rp(L)
+    n = ctypes.c_int32()
+    assert lib.synthpix_tiling_candidates(ctypes.byref(rp), None, 0, ctypes.byref(n)) == 0
+    assert n.value >= 10
+    arr = (L.Tiling * n.value)()
+    assert lib.synthpix_tiling_candidates(ctypes.byref(rp), arr, n.value, ctypes.byref(n)) == 0
+    d = L.Tiling()
+    assert lib.synthpix_default_tiling(None, 0, ctypes.byref(rp), ctypes.byref(d)) == 0
+    assert (arr[0].tile_w, arr[0].tile_h, arr[0].chunk, arr[0].cap) == (d.tile_w, d.tile_h, d.chunk, d.cap)
+    pairs = _pairs(L, [(256, 256, 64, 64, 1311)])
+    chunks = set()
+    for t in arr:
+        size = ctypes.c_size_t()
+        assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(rp), ctypes.byref(t), 0, ctypes.byref(size)) == 0
+        chunks.add(t.chunk)
+    assert chunks >= {1024, 2048, 4096, 8192}
+    bad = _rp(L, sheet_sigma=-1.0)
+    assert lib.synthpix_tiling_candidates(ctypes.byref(bad), arr, n.value, ctypes.byref(n)) == L.SP_ERR_INVALID_ARG
 
 
 def test_backward_validation(L):
@@ -202,9 +247,9 @@ def test_backward_validation(L):
     assert n.value >= 5 * 4 * 100 + 8 * 2 * 16 * 16
     args = [pairs, fake, 1, None, fake, fake, fake, None, None] + [fake] * 3
 
-    def call(rp_, ws=ctypes.c_void_p(0x100000), nbytes=1 << 30, grad=fake):
+    def call(rp_, ws=ctypes.c_void_p(0x100000), nbytes=1 << 30, grad=fake, total=None):
         return lib.synthpix_render_pair_backward(*args, ctypes.byref(rp_), grad, fake, fake, fake, fake, fake,
-                                                 fake, fake, ws, nbytes, None)
+                                                 fake, total, fake, ws, nbytes, None)
 
     rp.bits = 12
     assert call(rp) == L.SP_ERR_UNSUPPORTED
@@ -215,6 +260,8 @@ def test_backward_validation(L):
     assert call(rp, grad=None) == L.SP_ERR_INVALID_ARG
     assert call(rp, nbytes=n.value - 1) == L.SP_ERR_WORKSPACE
     assert call(rp, ws=ctypes.c_void_p(0x100010)) == L.SP_ERR_WORKSPACE
+    assert call(rp, total=ctypes.c_void_p(0x1002)) == L.SP_ERR_INVALID_ARG     # misaligned shared-sheet output
     half = [pairs, fake, 1, None, fake, fake, fake, fake, None] + [fake] * 3   # x2 without y2
     assert lib.synthpix_render_pair_backward(*half, ctypes.byref(rp), fake, fake, fake, fake, fake, fake, fake,
-                                             fake, ctypes.c_void_p(0x100000), 1 << 30, None) == L.SP_ERR_INVALID_ARG
+                                             None, fake, ctypes.c_void_p(0x100000), 1 << 30,
+                                             None) == L.SP_ERR_INVALID_ARG

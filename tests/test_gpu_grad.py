@@ -248,7 +248,74 @@ def test_backward_is_deterministic_and_autograd_agrees():
     for name, key in (("x", "x1"), ("y", "y1"), ("z", "z"), ("d", "d"), ("I0", "I0")):
         assert torch.equal(inp[name].grad, g[key]), key
     assert torch.equal(fl.grad, g["flow"])
-    assert torch.allclose(sheet.grad, g["sheet"].sum())
+    # the shared-sheet gradient is summed by the library (float64, fixed order)
+    assert torch.equal(sheet.grad, g["sheet_total"])
+    assert abs(float(g["sheet_total"]) - float(g["sheet"].double().sum())) <= 1e-6 * float(g["sheet"].abs().sum())
+
+
+def test_backward_with_gaps_matches_packed():
+    """A batch whose particle, image and flow arrays leave unused gaps before
+    every pair: the in-pair gradients equal those of the packed batch bit for
+    bit, and every gap slot below the particle span comes back 0 (the output
+    memory is filled with NaN first, so unwritten slots would show)."""
+    sizes, grids, m = [(40, 48), (24, 20), (31, 17)], [(10, 12), (8, 7), (6, 5)], 30
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, m, 13)
+    rp = sp.render_params(0.5, 5.0, 1, 0.7, 0.0, 0, 0, 1.0, 2, "rk4")
+    gJ, gJ_dev = _grad_images(batch, 17)
+    ref = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev)
+    gaps = (5, 12, 4)
+    gb = sp.PairBatch.build(sizes, grids, [m] * 3, device=gu.DEV, gaps=gaps)
+
+    def spread(a, n_total, gap, sizes_):
+        out = np.full(n_total, np.nan, np.float32)
+        o = 0
+        for p, k in enumerate(sizes_):
+            o += gap
+            out[o:o + k] = a[sum(sizes_[:p]):sum(sizes_[:p]) + k]
+            o += k
+        return out
+
+    n_sizes = [m] * 3
+    gdev = {k: gu.to_dev(np.nan_to_num(spread(np.concatenate(P[k]), gb.n_particles, gaps[0], n_sizes), nan=0.0))
+            for k in P}
+    pix = [2 * H * W for (H, W) in sizes]
+    gJg = gu.to_dev(np.nan_to_num(spread(gJ, gb.n_pixels, gaps[1], pix), nan=0.0))
+    fl = [2 * a * b for (a, b) in grids]
+    gflow = gu.to_dev(np.nan_to_num(spread(np.concatenate([f.reshape(-1) for f in flows]), gb.n_flow, gaps[2], fl),
+                                    nan=0.0))
+    for _ in range(3):     # NaN-filled blocks for the caching allocator to hand out next
+        junk = torch.full((gb.n_particles,), float("nan"), device=gu.DEV)
+        del junk
+    got = sp.render_pair_backward(gb, gflow, gdev["x"], gdev["y"], gdev["z"], gdev["d"], gdev["I0"], rp, gJg)
+    torch.cuda.synchronize()
+    for key in ("x1", "y1", "z", "d", "I0"):
+        g = gu.to_np(got[key])
+        r = gu.to_np(ref[key])
+        o = 0
+        for p in range(3):
+            assert np.all(g[o:o + gaps[0]] == 0.0), (key, p)
+            o += gaps[0]
+            assert np.array_equal(g[o:o + m], r[p * m:(p + 1) * m]), (key, p)
+            o += m
+    assert torch.equal(got["sheet"], ref["sheet"]) and torch.equal(got["sheet_total"], ref["sheet_total"])
+    gf, rf = gu.to_np(got["flow"]), gu.to_np(ref["flow"])
+    o = ro = 0
+    for p in range(3):
+        assert np.all(gf[o:o + gaps[2]] == 0.0)
+        o += gaps[2]
+        assert np.array_equal(gf[o:o + fl[p]], rf[ro:ro + fl[p]]), p
+        o += fl[p]
+        ro += fl[p]
+    # forward on the gapped layout: pairs' images equal the packed ones, gaps stay 0
+    img_g = gu.to_np(sp.render_images(gb, gflow, gdev["x"], gdev["y"], gdev["z"], gdev["d"], gdev["I0"], 0.5, rp))
+    img_r = gu.to_np(sp.render_images(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], 0.5, rp))
+    o = ro = 0
+    for p in range(3):
+        assert np.all(img_g[o:o + gaps[1]] == 0.0)
+        o += gaps[1]
+        assert np.array_equal(img_g[o:o + pix[p]], img_r[ro:ro + pix[p]]), p
+        o += pix[p]
+        ro += pix[p]
 
 
 def test_backward_full_size_pairs(ra):

@@ -34,6 +34,8 @@ def _io(batch, flow_dev, bits):
 
 
 def _eager(batch, flow_dev, sprm, aprm, rprm, seed, tile=None):
+    rprm = type(rprm).from_buffer_copy(rprm)
+    rprm.seed = seed                        # a plan keys particles and noise with one seed
     P = sp.seed(batch, sprm, seed)
     x2, y2 = sp.advect(batch, flow_dev, aprm, P["x"], P["y"])
     img = sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, tile)
@@ -97,4 +99,38 @@ def test_plan_advances_pair_ids():
         bk = batch_for(wl.sizes, [f.shape[:2] for f in flows], batch.n_max, ids)
         _, _, _, img = _eager(bk, flow_dev, sprm, aprm, rprm, wl.seed)
         assert _same(io["images"], img), f"launch {k}"
+    plan.close()
+
+
+def test_plan_launch_into_new_buffers():
+    """One captured plan replayed into a second set of tensors with another key
+    and pair-id offset, then back into the first: every launch equals the eager
+    calls on the same buffers, ids and key, and leaves the other set untouched."""
+    wl = _workload()
+    flows, batch, flow_dev = workload_inputs(wl)
+    sprm, aprm, rprm = params_of(wl)
+    io1 = _io(batch, flow_dev, wl.bits)
+    io2 = _io(batch, flow_dev, wl.bits)
+    plan = sp.Plan(batch, sprm, wl.seed, aprm, rprm, io1)
+    n = batch.n_pairs
+    for k in range(2):
+        io1["images"].zero_()
+        io2["images"].zero_()
+        plan.launch(io2, seed_value=5 + k, pair_id_base=100 * (k + 1))
+        torch.cuda.synchronize()
+        bk = batch_for(wl.sizes, [f.shape[:2] for f in flows], batch.n_max, [100 * (k + 1) + p for p in range(n)])
+        P, x2, _, img = _eager(bk, flow_dev, sprm, aprm, rprm, 5 + k)
+        assert _same(io2["images"], img) and _same(io2["x1"], P["x"]) and _same(io2["x2"], x2), k
+        assert _same(io2["n_active"], P["n_active"])
+        assert not io1["images"].any()
+        assert plan.read_status() == 0
+    # a launch without io replays the last descriptor
+    io2["images"].zero_()
+    plan.launch()
+    torch.cuda.synchronize()
+    assert _same(io2["images"], img)
+    plan.launch(io1, seed_value=wl.seed, pair_id_base=0)
+    torch.cuda.synchronize()
+    _, _, _, img1 = _eager(batch, flow_dev, sprm, aprm, rprm, wl.seed)
+    assert _same(io1["images"], img1)
     plan.close()

@@ -152,6 +152,124 @@ def uneven_batched_vs_per_pair(sp, torch, np, dev, steps=5):
     return out
 
 
+def measured_peaks(sp, torch, dev):
+    """Ceilings measured on this device by the library's probe kernels: HBM
+    store and copy rates over 1 GiB, and the wave64 instruction issue rates of
+    float32 FMA chains, v_sin chains and 32x32->64 multiply chains at eight
+    waves per SIMD."""
+    out = {}
+    big = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    small = torch.empty(4096, dtype=torch.uint8, device=dev)
+    for kind, buf, iters, unit in (("store", big, 0, "GB/s"), ("copy", big, 0, "GB/s"),
+                                   ("fma", small, 4096, "G wave64 instructions/s"),
+                                   ("trans", small, 1024, "G wave64 instructions/s"),
+                                   ("mul64", small, 2048, "G wave64 instructions/s")):
+        sp.probe(kind, buf, iters)                    # warm-up
+        torch.cuda.synchronize()
+        sp.timing_read(None)
+        sp.timing_enable(True)
+        work = 0.0
+        for _ in range(5):
+            work = sp.probe(kind, buf, iters)
+        torch.cuda.synchronize()
+        sp.timing_enable(False)
+        ms, n = sp.timing_read("probe_" + kind)
+        out[kind] = {"rate": round(work * n / (ms * 1e-3) / 1e9, 1), "unit": unit}
+    del big, small
+    torch.cuda.empty_cache()
+    return out
+
+
+def render_only_us(sp, torch, batch, P, x2, y2, rprm, images, ws, reps=20):
+    """Average render_tile launch time (us) of `reps` renders of the same particles."""
+    sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, images, ws)
+    torch.cuda.synchronize()
+    sp.timing_read(None)
+    sp.timing_enable(True)
+    for _ in range(reps):
+        sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, images, ws)
+    torch.cuda.synchronize()
+    sp.timing_enable(False)
+    ms, n = sp.timing_read("render_tile")
+    sp.timing_read(None)
+    return 1000.0 * ms / n
+
+
+def latency_plain_256(sp, torch, np, dev, reps=200):
+    """One 256x256 pair (0.02 ppp, Euler, fp32 images): microseconds per pair for
+    eager seed -> advect -> render calls and for a graph-captured plan replay."""
+    from workloads import get_workload
+    wl = get_workload("plain_256")
+    flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
+    P = sp.seed(batch, sprm, wl.seed)
+    x2 = torch.empty_like(P["x"])
+    y2 = torch.empty_like(P["y"])
+    images = torch.empty(batch.n_pixels, dtype=torch.float32, device=dev)
+    ws = sp.alloc_workspace(batch, rprm)
+
+    def step():
+        sp.seed(batch, sprm, wl.seed, out=P)
+        sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2, ws)
+        sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, images, ws)
+
+    for _ in range(10):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / reps
+    io = _plan_io(sp, torch, batch, flow, wl.bits, dev)
+    plan = sp.Plan(batch, sprm, wl.seed, aprm, rprm, io, autotune=False, advance_pair_ids=True)
+    for _ in range(10):
+        plan.launch()
+    graph = _time_plan(torch, plan, reps)
+    plan.close()
+    return {"eager_us_per_pair": round(1e6 * eager, 1), "graph_us_per_pair": round(1e6 * graph, 1)}
+
+
+def fp64_error(sp, torch, np, dev):
+    """Error of the float images (noise off, no integer codes) against the
+    all-float64 oracle pipeline (float64 seed, advection, render and blur),
+    relative to each image's peak: max and mean over two pairs each of
+    plain_256, scale_1024 and dense_2048."""
+    from oracle import pipeline as opipe
+    from workloads import get_workload
+    out = {}
+    for name in ("plain_256", "scale_1024", "dense_2048"):
+        wl = get_workload(name).with_(bits=0, noise_sigma=0.0)
+        wl = wl.with_(sizes=wl.sizes[:2])
+        flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
+        P = sp.seed(batch, sprm, wl.seed)
+        x2, y2 = sp.advect(batch, flow, aprm, P["x"], P["y"])
+        img = sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm)
+        torch.cuda.synchronize()
+        got = img.cpu().numpy()
+        mx, sm, cnt = 0.0, 0.0, 0
+        for p in range(wl.n_pairs):
+            H, W = wl.sizes[p]
+            o = batch.host[p].image_offset
+            ref = opipe.generate_pair(wl, p, flows[p], H, W)["J"]
+            e = np.abs(got[o:o + 2 * H * W].astype(np.float64) - ref.reshape(-1)) / float(ref.max())
+            mx = max(mx, float(e.max()))
+            sm += float(e.sum())
+            cnt += e.size
+        out[name] = {"pairs": wl.n_pairs, "max_rel_peak": float(f"{mx:.3e}"), "mean_rel_peak": float(f"{sm / cnt:.3e}")}
+    return out
+
+
+def _oracle_pair(args):
+    """Worker of the all-core CPU baseline: one pair through the float64 oracle."""
+    name, p, flow = args
+    from oracle import pipeline as opipe
+    from workloads import get_workload
+    wl = get_workload(name)
+    H, W = wl.sizes[p]
+    opipe.generate_pair(wl, p, flow, H, W)
+    return p
+
+
 def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
     """Advect + render forward vs the backward from dL/dJ, on float images:
     grad_512 (64 pairs of 512^2, RK4 x4, 3x3 blur) or dense_2048 (32 pairs of
@@ -278,10 +396,12 @@ def main():
     achieved = out_bytes / (rt["avg_us"] * 1e-6) / 1e9
     traffic = None
     valu = None
+    prof = {}
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = dict(ln.strip().split("=", 1) for ln in f if "=" in ln and not ln.startswith("#"))
         if tr.get("source_sha") == source_sha(RENDER_SRC) and tr.get("workload") == wl.name:
+            prof = tr
             traffic = int(tr["bytes_per_launch"])
             if "valu_insts_per_launch" in tr:
                 # VALU issue of the same kernel: wave64 instructions counted by rocprofv3 per
@@ -335,6 +455,15 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 copies of {nbytes} bytes")
 
+    # the same renders with the noise off: the noise's share of the renderer
+    rt_noise_on = render_only_us(sp, torch, batch, P, x2, y2, rprm, images, ws)
+    rprm_quiet = sp.render_params(wl.sheet_sigma, wl.d_max, wl.blur_radius, wl.blur_sigma, 0.0, wl.bits,
+                                  wl.seed, wl.dt, wl.substeps, wl.integrator)
+    rt_noise_off = render_only_us(sp, torch, batch, P, x2, y2, rprm_quiet, images, ws)
+    flags = sp.read_status(ws)
+    if flags:
+        raise RuntimeError(f"device status flags {flags:#x}")
+
     extras = {}
     if not args.no_extras:
         extras["graph_plan"] = plan_throughput(sp, torch, np, dev, wl, flows, flow, batch, sprm, aprm, rprm)
@@ -349,20 +478,61 @@ def main():
         log(f"[bench] dense_2048: {extras['dense_2048']}")
         extras["dense_2048_grad"] = gradient_cost(sp, torch, np, dev, "dense_2048", steps=5)
         log(f"[bench] dense_2048_grad: {extras['dense_2048_grad']}")
+        extras["plain_256_latency"] = latency_plain_256(sp, torch, np, dev)
+        log(f"[bench] plain_256 latency: {extras['plain_256_latency']}")
+        extras["fp64_err"] = fp64_error(sp, torch, np, dev)
+        log(f"[bench] fp64_err: {extras['fp64_err']}")
+    peaks = measured_peaks(sp, torch, dev)
+    log(f"[bench] measured peaks: {peaks}")
+    roofline["measured_peak"] = peaks["store"]["rate"]
+    roofline["frac_of_measured"] = round(achieved / peaks["store"]["rate"], 4)
+    noise = {"render_tile_us_noise_on": round(rt_noise_on, 2), "render_tile_us_noise_off": round(rt_noise_off, 2),
+             "hbm_frac_noise_on": round(out_bytes / (rt_noise_on * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+             "hbm_frac_noise_off": round(out_bytes / (rt_noise_off * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    if valu is not None:
+        # against the issue rate the FMA probe sustains on this device; the nominal
+        # one-instruction-per-four-cycles figure is kept beside it
+        valu["nominal_peak"] = valu["peak"]
+        valu["frac_of_nominal"] = valu["frac"]
+        valu["peak"] = peaks["fma"]["rate"]
+        valu["frac"] = round(valu["achieved"] / peaks["fma"]["rate"], 4)
+        if prof.get("valu_busy_pct"):
+            valu["valu_busy"] = round(float(prof["valu_busy_pct"]) / 100.0, 4)
+    trans = None
+    if prof.get("trans_insts_per_launch"):
+        tr_n = int(prof["trans_insts_per_launch"])
+        tr_rate = tr_n / (rt["avg_us"] * 1e-6) / 1e9
+        trans = {"insts_per_launch": tr_n, "achieved": round(tr_rate, 1), "peak": peaks["trans"]["rate"],
+                 "unit": "G wave64 instructions/s", "frac": round(tr_rate / peaks["trans"]["rate"], 4),
+                 "share_of_valu": round(tr_n / valu["insts_per_launch"], 4) if valu else None}
 
     cpu = None
     if not args.no_cpu_baseline:
+        import multiprocessing as mp
         from oracle import pipeline as opipe
         n = min(args.cpu_sample_pairs, wl.n_pairs)
-        log(f"[bench] timing the float64 CPU oracle on {n} pairs")
+        host_cpus = os.cpu_count() or 1
+        log(f"[bench] timing the float64 CPU oracle on {n} pairs, one process")
         t0 = time.perf_counter()
         for p in range(n):
             H, W = wl.sizes[p]
             opipe.generate_pair(wl, p, flows[p], H, W)
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(n / dt, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-               "sample": f"{n} of {wl.n_pairs} pairs of {wl.name}, full path (seed, RK4 advect, render, blur, "
-                         f"noise, codes) in float64 NumPy, one process, {dt:.1f} s"}
+        dt1 = time.perf_counter() - t0
+        # all cores: one process per core (at most 16, the host share of one GPU), pairs spread over them
+        workers = max(1, min(host_cpus, 16))
+        n_pool = min(wl.n_pairs, 2 * workers)
+        log(f"[bench] timing the float64 CPU oracle on {n_pool} pairs, {workers} processes")
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(workers, initializer=os.environ.__setitem__, initargs=("OMP_NUM_THREADS", "1")) as pool:
+            pool.map(_oracle_pair, [(wl.name, 0, flows[0])] * workers)          # start-up and imports
+            t0 = time.perf_counter()
+            pool.map(_oracle_pair, [(wl.name, p, flows[p]) for p in range(n_pool)], chunksize=1)
+            dtp = time.perf_counter() - t0
+        cpu = {"value": round(n_pool / dtp, 4), "unit": "pairs/s", "cores": workers, "kind": "oracle",
+               "host_cpus": host_cpus, "per_core": round(n / dt1, 4),
+               "sample": f"{n_pool} of {wl.n_pairs} pairs of {wl.name} over {workers} processes ({dtp:.1f} s); "
+                         f"per_core: {n} pairs in one process ({dt1:.1f} s); full path (seed, RK4 advect, render, "
+                         f"blur, noise, codes) in float64 NumPy"}
 
     line = {"metric": METRIC, "value": round(pairs_per_s, 1), "unit": "pairs/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -370,7 +540,8 @@ def main():
             "data": "synthetic", "config": describe(wl), "gpx_per_s": round(gpx_per_s, 2),
             "step_hbm_frac": round(step_hbm_frac, 4), "kernels_us": {k: round(v["avg_us"], 2) for k, v in
                                                                       kernels.items()},
-            "plain": plain, **extras, "roofline": roofline, "valu_issue": valu, "cpu_baseline": cpu}
+            "plain": plain, **extras, "noise_split": noise, "measured_peaks": peaks, "roofline": roofline,
+            "valu_issue": valu, "transcendental": trans, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
 

@@ -94,6 +94,7 @@ SIGNATURES = {
     "synthpix_read_status": [_P, _P, ctypes.POINTER(ctypes.c_uint32)],
     "synthpix_timing_enable": [ctypes.c_int32],
     "synthpix_timing_read": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "synthpix_probe": [ctypes.c_int32, _P, ctypes.c_size_t, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)],
     "synthpix_bin_views_of": [_PP, ctypes.c_int32, ctypes.POINTER(RenderParams), ctypes.POINTER(Tiling),
                               ctypes.POINTER(BinViews)],
     "synthpix_seed": [_PP, _P, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.c_uint64,

@@ -229,6 +229,19 @@ def timing_read(name: Optional[str] = None):
     return ms.value, n.value
 
 
+PROBES = {"store": 0, "copy": 1, "fma": 2, "trans": 3, "mul64": 4}
+
+
+def probe(kind: str, buf: torch.Tensor, iters: int = 0) -> float:
+    """One ``synthpix_probe`` launch on the current stream; returns its unit
+    count (bytes moved, or wave64 VALU instructions of the probe loop)."""
+    _need_cuda(buf)
+    work = ctypes.c_double(0.0)
+    L.check(L.load().synthpix_probe(PROBES[kind], _ptr(buf), buf.numel() * buf.element_size(), iters, _stream(),
+                                    ctypes.byref(work)))
+    return work.value
+
+
 def read_status(workspace: torch.Tensor) -> int:
     flags = ctypes.c_uint32(0)
     st = L.load().synthpix_read_status(_ptr(workspace), _stream(), ctypes.byref(flags))

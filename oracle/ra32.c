@@ -334,3 +334,236 @@ void ra_quantise(const float* v, size_t n, int bits, uint16_t* q)
         q[i] = (uint16_t)t;
     }
 }
+
+/* ============================================================ full model */
+/*
+ * Binary32 mirror of the full per-particle model (Eq. 1 with sigma_x = d / 4,
+ * sigma_y = d_y / 4 and rho; frame-2 parameter variation; per-frame hiding;
+ * the out-of-focus sheet law of Remark 1; out-of-plane motion).
+ */
+
+#define RHO_MAX 0.99f
+
+float ra_sin2pi(float u)
+{
+    float t = u * 4.0f;
+    float kf = rintf(t);
+    float f = t - kf;
+    float x = f * (float)1.57079632679489661923;
+    float x2 = x * x;
+    float c = fmaf(x2, (float)(1.0 / 40320.0), (float)(-1.0 / 720.0));
+    c = fmaf(x2, c, (float)(1.0 / 24.0));
+    c = fmaf(x2, c, -0.5f);
+    c = fmaf(x2, c, 1.0f);
+    float s = fmaf(x2, (float)(1.0 / 362880.0), (float)(-1.0 / 5040.0));
+    s = fmaf(x2, s, (float)(1.0 / 120.0));
+    s = fmaf(x2, s, (float)(-1.0 / 6.0));
+    s = fmaf(x2, s, 1.0f);
+    s = x * s;
+    switch (((int)kf) & 3) {
+    case 0: return s;
+    case 1: return c;
+    case 2: return -s;
+    default: return -c;
+    }
+}
+
+/* Second diameter and correlation (stream 6): d_y from the diameter
+ * distribution (uniform: word 0; clipped normal: Box-Muller of words 1, 2),
+ * rho = rho_lo + (rho_hi - rho_lo) u(word 3). */
+void ra_seed_shape(int n_max, uint64_t pid, uint64_t seed, int d_normal, const float dp[4], float rho_lo,
+                   float rho_hi, float* dy, float* rho)
+{
+    uint32_t w[4];
+    for (int i = 0; i < n_max; ++i) {
+        draw((uint32_t)i, 6u, pid, seed, w);
+        if (!d_normal) {
+            dy[i] = fmaf(dp[1] - dp[0], u24(w[0]), dp[0]);
+        } else {
+            float R = sqrtf(-2.0f * ra_ln(u24o(w[1])));
+            float v = fmaf(dp[1], R * ra_cos2pi(u24(w[2])), dp[0]);
+            v = fmaxf(v, dp[2]);
+            dy[i] = fminf(v, dp[3]);
+        }
+        rho[i] = fmaf(rho_hi - rho_lo, u24(w[3]), rho_lo);
+    }
+}
+
+/* Per-frame parameters.  In: frame-1 d, dy, rho, I0.  Out: I0_1 (frame 1 after
+ * hiding) and d2, dy2, rho2, I0_2 (frame 2).  jit = (diameters, rho,
+ * intensity) standard deviations; a zero one leaves the parameter as is. */
+void ra_frame_params(int n, uint64_t pid, uint64_t seed, const float jit[3], float hide_p, float d_max,
+                     const float* d, const float* dy, const float* rho, const float* I0,
+                     float* I0_1, float* d2, float* dy2, float* rho2, float* I0_2)
+{
+    uint32_t w[4];
+    for (int i = 0; i < n; ++i) {
+        float a = d[i], b = dy[i], r = rho[i], I = I0[i];
+        if (jit[0] > 0.0f || jit[1] > 0.0f || jit[2] > 0.0f) {
+            draw((uint32_t)i, 2u, pid, seed, w);
+            float R0 = sqrtf(-2.0f * ra_ln(u24o(w[0])));
+            float R1 = sqrtf(-2.0f * ra_ln(u24o(w[2])));
+            float n0 = R0 * ra_cos2pi(u24(w[1]));
+            float n1 = R0 * ra_sin2pi(u24(w[1]));
+            float n2 = R1 * ra_cos2pi(u24(w[3]));
+            float n3 = R1 * ra_sin2pi(u24(w[3]));
+            if (jit[0] > 0.0f) {
+                a = fminf(fmaxf(fmaf(jit[0], n0, a), 0.0f), d_max);
+                b = fminf(fmaxf(fmaf(jit[0], n1, b), 0.0f), d_max);
+            }
+            if (jit[1] > 0.0f) r = fminf(fmaxf(fmaf(jit[1], n2, r), -RHO_MAX), RHO_MAX);
+            if (jit[2] > 0.0f) I = I > 0.0f ? fmaxf(fmaf(jit[2], n3, I), 0.0f) : 0.0f;
+        }
+        float I1 = I0[i];
+        if (hide_p > 0.0f) {
+            draw((uint32_t)i, 7u, pid, seed, w);
+            if (u24(w[0]) < hide_p) I1 = 0.0f;
+            if (u24(w[1]) < hide_p) I = 0.0f;
+        }
+        I0_1[i] = I1;
+        d2[i] = a;
+        dy2[i] = b;
+        rho2[i] = r;
+        I0_2[i] = I;
+    }
+}
+
+/* Peak of a particle: I0 S(z).  law 0: Gaussian sheet S = E(z^2 / (2 s^2))
+ * (c = 0.5 / (s s)); law 1: Remark 1, S = exp(-k v^shape) with
+ * v = z^2 (2 / (DZ0 DZ0)), k = 1 / sqrt(2 pi): v^shape = E(-(shape ln v))
+ * (v below the smallest normal float counts as 0; shape ln v >= 80 gives S = 0). */
+float ra_peak(float I0, float z, int law, float sheet_sigma, float dz0, float shape)
+{
+    if (law == 0) return I0 * ra_E((z * z) * (0.5f / (sheet_sigma * sheet_sigma)));
+    const float c2 = 2.0f / (dz0 * dz0);
+    const float v = (z * z) * c2;
+    float p = 0.0f;
+    if (v >= 0x1p-126f) {
+        const float a = shape * ra_ln(v);
+        if (!(a < 80.0f)) return 0.0f;
+        p = ra_E(-a);
+    }
+    return I0 * ra_E((float)0.39894228040143267794 * p);
+}
+
+void ra_peaks(int n, const float* I0, const float* z, int law, float sheet_sigma, float dz0, float shape,
+              float* A)
+{
+    for (int i = 0; i < n; ++i) A[i] = ra_peak(I0[i], z[i], law, sheet_sigma, dz0, shape);
+}
+
+/* Fixed-point exposure of the full model from per-particle peaks A.
+ * om = 1 - rho^2 (one fmaf), kx = 8 / (om (d d)), ky = 8 / (om (dy dy)).
+ * rho == 0: separable, t = (Af E(ky dy^2)) E(kx dx^2), as the isotropic path.
+ * rho != 0: kxy = (-16 rho) / (om (d dy)); per row a = kxy dy, b = ky (dy dy);
+ * per pixel q = max(fmaf(dx, fmaf(kx, dx, a), b), 0), t = Af E(q).
+ * Patch: |dx| <= 1.5 d, |dy| <= 1.5 d_y. */
+void ra_render_model_fixed(int H, int W, int n, const float* x, const float* y, const float* A,
+                           const float* d, const float* dy, const float* rho, uint32_t* acc)
+{
+    memset(acc, 0, sizeof(uint32_t) * (size_t)H * (size_t)W);
+    float gxt[1024];
+    for (int i = 0; i < n; ++i) {
+        if (!(A[i] > 0.0f) || !(d[i] > 0.0f) || !(dy[i] > 0.0f) || !isfinite(x[i]) || !isfinite(y[i])) continue;
+        int c0, c1, r0, r1;
+        if (!ra_support_range(x[i], 1.5f * d[i], W, &c0, &c1)) continue;
+        if (!ra_support_range(y[i], 1.5f * dy[i], H, &r0, &r1)) continue;
+        if (c1 - c0 >= 1024) continue;
+        const float Af = fminf(A[i] * 16777216.0f, 4294967040.0f);
+        const float r = rho[i];
+        const float om = fmaf(-r, r, 1.0f);
+        const float kx = 8.0f / (om * (d[i] * d[i]));
+        const float ky = 8.0f / (om * (dy[i] * dy[i]));
+        if (r == 0.0f) {
+            for (int c = c0; c <= c1; ++c) {
+                float dx = ((float)c + 0.5f) - x[i];
+                gxt[c - c0] = ra_E(kx * (dx * dx));
+            }
+            for (int rr = r0; rr <= r1; ++rr) {
+                float ddy = ((float)rr + 0.5f) - y[i];
+                float rs = Af * ra_E(ky * (ddy * ddy));
+                uint32_t* row = acc + (size_t)rr * W;
+                for (int c = c0; c <= c1; ++c) row[c] += quant(rs * gxt[c - c0]);
+            }
+        } else {
+            const float kxy = (-16.0f * r) / (om * (d[i] * dy[i]));
+            for (int rr = r0; rr <= r1; ++rr) {
+                float ddy = ((float)rr + 0.5f) - y[i];
+                float a = kxy * ddy;
+                float b = ky * (ddy * ddy);
+                uint32_t* row = acc + (size_t)rr * W;
+                for (int c = c0; c <= c1; ++c) {
+                    float dx = ((float)c + 0.5f) - x[i];
+                    float q = fmaxf(fmaf(dx, fmaf(kx, dx, a), b), 0.0f);
+                    row[c] += quant(Af * ra_E(q));
+                }
+            }
+        }
+    }
+}
+
+/* Scalar bilinear sample of a cell-centred [Gh][Gw] grid (same registration
+ * and clamping as the (u, v) grid). */
+static float sample_scalar(const float* G, int Gh, int Gw, float sx, float sy, float px, float py)
+{
+    float gx = px * sx - 0.5f;
+    float gy = py * sy - 0.5f;
+    gx = fminf(fmaxf(gx, 0.0f), (float)(Gw - 1));
+    gy = fminf(fmaxf(gy, 0.0f), (float)(Gh - 1));
+    int j0 = (int)floorf(gx);
+    int i0 = (int)floorf(gy);
+    if (j0 > Gw - 2) j0 = Gw - 2;
+    if (i0 > Gh - 2) i0 = Gh - 2;
+    float fx = gx - (float)j0;
+    float fy = gy - (float)i0;
+    const float* a = G + (size_t)i0 * Gw + j0;
+    const float* c = a + Gw;
+    float top = fmaf(fx, a[1] - a[0], a[0]);
+    float bot = fmaf(fx, c[1] - c[0], c[0]);
+    return fmaf(fy, bot - top, top);
+}
+
+/* Out-of-plane motion: z2 = z1 + integral of w along the in-plane trajectory,
+ * with the stages of ra_advect (Euler: z = fmaf(h, w, z); RK4: z = fmaf(h,
+ * (((w1 + 2 w2) + 2 w3) + w4) / 6, z), w_k sampled at the k-th stage position). */
+void ra_advect_z(const float* F, const float* Gw_, int Gh, int Gw, int H, int W, int n, const float* x1,
+                 const float* y1, const float* z1, float dt, int substeps, int rk4, float* z2)
+{
+    const float sx = (float)Gw / (float)W;
+    const float sy = (float)Gh / (float)H;
+    const float h = dt / (float)substeps;
+    const float hh = h * 0.5f;
+    for (int i = 0; i < n; ++i) {
+        float px = x1[i], py = y1[i], pz = z1[i];
+        for (int s = 0; s < substeps; ++s) {
+            if (!rk4) {
+                float u, v;
+                sample(F, Gh, Gw, sx, sy, px, py, &u, &v);
+                float w = sample_scalar(Gw_, Gh, Gw, sx, sy, px, py);
+                px = fmaf(h, u, px);
+                py = fmaf(h, v, py);
+                pz = fmaf(h, w, pz);
+            } else {
+                float k1u, k1v, k2u, k2v, k3u, k3v, k4u, k4v;
+                sample(F, Gh, Gw, sx, sy, px, py, &k1u, &k1v);
+                float w1 = sample_scalar(Gw_, Gh, Gw, sx, sy, px, py);
+                float ax = fmaf(hh, k1u, px), ay = fmaf(hh, k1v, py);
+                sample(F, Gh, Gw, sx, sy, ax, ay, &k2u, &k2v);
+                float w2 = sample_scalar(Gw_, Gh, Gw, sx, sy, ax, ay);
+                float bx = fmaf(hh, k2u, px), by = fmaf(hh, k2v, py);
+                sample(F, Gh, Gw, sx, sy, bx, by, &k3u, &k3v);
+                float w3 = sample_scalar(Gw_, Gh, Gw, sx, sy, bx, by);
+                float cx = fmaf(h, k3u, px), cy = fmaf(h, k3v, py);
+                sample(F, Gh, Gw, sx, sy, cx, cy, &k4u, &k4v);
+                float w4 = sample_scalar(Gw_, Gh, Gw, sx, sy, cx, cy);
+                float su = ((k1u + 2.0f * k2u) + 2.0f * k3u) + k4u;
+                float sv = ((k1v + 2.0f * k2v) + 2.0f * k3v) + k4v;
+                float sw = ((w1 + 2.0f * w2) + 2.0f * w3) + w4;
+                px = fmaf(h, su / 6.0f, px);
+                py = fmaf(h, sv / 6.0f, py);
+                pz = fmaf(h, sw / 6.0f, pz);
+            }
+        }
+        z2[i] = pz;
+    }
+}

@@ -59,6 +59,21 @@ def load():
     L.ra_fixed_to_float.argtypes = [_u32p, ctypes.c_size_t, _f32p]
     L.ra_blur.argtypes = [_f32p, ctypes.c_int, ctypes.c_int, _f32p, ctypes.c_int, _f32p, _f32p]
     L.ra_quantise.argtypes = [_f32p, ctypes.c_size_t, ctypes.c_int, _u16p]
+    L.ra_sin2pi.argtypes = [ctypes.c_float]
+    L.ra_sin2pi.restype = ctypes.c_float
+    L.ra_seed_shape.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, _f32p,
+                                ctypes.c_float, ctypes.c_float, _f32p, _f32p]
+    L.ra_frame_params.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, _f32p, ctypes.c_float,
+                                  ctypes.c_float, _f32p, _f32p, _f32p, _f32p, _f32p, _f32p, _f32p, _f32p, _f32p]
+    L.ra_peak.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                          ctypes.c_float]
+    L.ra_peak.restype = ctypes.c_float
+    L.ra_peaks.argtypes = [ctypes.c_int, _f32p, _f32p, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, _f32p]
+    L.ra_render_model_fixed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _f32p, _f32p, _f32p, _f32p,
+                                        _f32p, _f32p, _u32p]
+    L.ra_advect_z.argtypes = [_f32p, _f32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              _f32p, _f32p, _f32p, ctypes.c_float, ctypes.c_int, ctypes.c_int, _f32p]
     _lib = L
     return L
 
@@ -173,4 +188,88 @@ def generate_pair_noiseless(wl, pair_index, flow, H, W, pair_id=None):
     out = {"particles": P, "x2": x2, "y2": y2, "J": J}
     if wl.bits > 0:
         out["codes"] = quantise(J, wl.bits)
+    return out
+
+
+# ------------------------------------------------------------------ full model
+
+LAWS = {"gauss": 0, "remark1": 1}
+
+
+def sin2pi(u: float) -> float:
+    return float(load().ra_sin2pi(float(u)))
+
+
+def seed_shape(n_max, pair_id, seed, d_dist, d_params, rho):
+    n = int(n_max)
+    dp = np.zeros(4, dtype=np.float32)
+    dp[:len(d_params)] = d_params
+    dy = np.zeros(n, dtype=np.float32)
+    r = np.zeros(n, dtype=np.float32)
+    load().ra_seed_shape(n, int(pair_id), int(seed), 1 if d_dist == "normal" else 0, dp, float(rho[0]),
+                         float(rho[1]), dy, r)
+    return dy, r
+
+
+def frame_params(d, dy, rho, I0, pair_id, seed, jitter=(0.0, 0.0, 0.0), hide_p=0.0, d_max=16.0):
+    d, dy, rho, I0 = _f(d), _f(dy), _f(rho), _f(I0)
+    n = d.size
+    I1, d2, dy2, r2, I2 = (np.zeros(n, dtype=np.float32) for _ in range(5))
+    load().ra_frame_params(n, int(pair_id), int(seed), _f(jitter), float(hide_p), float(d_max), d, dy, rho, I0,
+                           I1, d2, dy2, r2, I2)
+    return (d, dy, rho, I1), (d2, dy2, r2, I2)
+
+
+def peaks(I0, z, law="gauss", sheet_sigma=0.5, dz0=1.0, shape=1.0):
+    I0 = _f(I0)
+    A = np.zeros_like(I0)
+    load().ra_peaks(I0.size, I0, _f(z), LAWS[law], float(sheet_sigma), float(dz0), float(shape), A)
+    return A
+
+
+def render_model(x, y, A, d, dy, rho, H, W):
+    acc = np.zeros(H * W, dtype=np.uint32)
+    x = _f(x)
+    load().ra_render_model_fixed(int(H), int(W), x.size, x, _f(y), _f(A), _f(d), _f(dy), _f(rho), acc)
+    return fixed_to_float(acc.reshape(H, W))
+
+
+def advect_z(flow, wgrid, H, W, x1, y1, z1, dt, substeps, integrator):
+    flow = _f(flow)
+    wgrid = _f(wgrid)
+    x1 = _f(x1)
+    z2 = np.zeros_like(x1)
+    load().ra_advect_z(flow, wgrid, flow.shape[0], flow.shape[1], int(H), int(W), x1.size, x1, _f(y1), _f(z1),
+                       float(dt), int(substeps), 1 if integrator == "rk4" else 0, z2)
+    return z2
+
+
+def generate_pair_model(m, H, W, pair_id, seed, flow, wgrid=None, blur_w=None, bits=0):
+    """Binary32 pair under the full model (no noise): exposures J (blurred when
+    blur_w is given) and, for bits > 0, the codes.  ``m`` as in
+    ``oracle.model.generate_pair``."""
+    from . import seed as sd
+    n_max = sd.particle_count(H, W, m["ppp"][1])
+    P = seed_pair(H, W, n_max, m["ppp"], pair_id, seed, m["d_dist"], m["d_params"], m["I0"], m["z"])
+    if m.get("anisotropic"):
+        dy, rho = seed_shape(n_max, pair_id, seed, m["d_dist"], m["d_params"], m["rho"])
+    else:
+        dy, rho = P["d"].copy(), np.zeros(n_max, dtype=np.float32)
+    x2, y2 = advect(flow, H, W, P["x"], P["y"], m["dt"], m["substeps"], m["integrator"])
+    z2 = advect_z(flow, wgrid, H, W, P["x"], P["y"], P["z"], m["dt"], m["substeps"], m["integrator"]) \
+        if wgrid is not None else P["z"].copy()
+    f1, f2 = frame_params(P["d"], dy, rho, P["I0"], pair_id, seed, m.get("jitter", (0.0, 0.0, 0.0)),
+                          m.get("hide_p", 0.0), m.get("d_max", 16.0))
+    law = m.get("law", "gauss")
+    frames = []
+    for (xf, yf, zf, f) in ((P["x"], P["y"], P["z"], f1), (x2, y2, z2, f2)):
+        A = peaks(f[3], zf, law, m.get("sheet_sigma", 0.5), m.get("dz0", 1.0), m.get("shape", 1.0))
+        img = render_model(xf, yf, A, f[0], f[1], f[2], H, W)
+        if blur_w is not None:
+            img = blur(img, blur_w)
+        frames.append(img)
+    J = np.stack(frames)
+    out = {"particles": P, "dy": dy, "rho": rho, "x2": x2, "y2": y2, "z2": z2, "frame1": f1, "frame2": f2, "J": J}
+    if bits > 0:
+        out["codes"] = quantise(J, bits)
     return out

@@ -160,7 +160,7 @@ def measured_peaks(sp, torch, dev):
     out = {}
     big = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     small = torch.empty(4096, dtype=torch.uint8, device=dev)
-    for kind, buf, iters, unit in (("store", big, 0, "GB/s"), ("copy", big, 0, "GB/s"),
+    for kind, buf, iters, unit in (("store", big, 0, "GB/s"), ("store_nt", big, 0, "GB/s"), ("copy", big, 0, "GB/s"),
                                    ("fma", small, 4096, "G wave64 instructions/s"),
                                    ("trans", small, 1024, "G wave64 instructions/s"),
                                    ("mul64", small, 2048, "G wave64 instructions/s")):
@@ -257,6 +257,11 @@ def fp64_error(sp, torch, np, dev):
             cnt += e.size
         out[name] = {"pairs": wl.n_pairs, "max_rel_peak": float(f"{mx:.3e}"), "mean_rel_peak": float(f"{sm / cnt:.3e}")}
     return out
+
+
+def _one_thread():
+    """Pool initializer: one BLAS/OpenMP thread per worker process."""
+    os.environ["OMP_NUM_THREADS"] = "1"
 
 
 def _oracle_pair(args):
@@ -484,8 +489,9 @@ def main():
         log(f"[bench] fp64_err: {extras['fp64_err']}")
     peaks = measured_peaks(sp, torch, dev)
     log(f"[bench] measured peaks: {peaks}")
-    roofline["measured_peak"] = peaks["store"]["rate"]
-    roofline["frac_of_measured"] = round(achieved / peaks["store"]["rate"], 4)
+    store_peak = max(peaks["store"]["rate"], peaks["store_nt"]["rate"])
+    roofline["measured_peak"] = store_peak
+    roofline["frac_of_measured"] = round(achieved / store_peak, 4)
     noise = {"render_tile_us_noise_on": round(rt_noise_on, 2), "render_tile_us_noise_off": round(rt_noise_off, 2),
              "hbm_frac_noise_on": round(out_bytes / (rt_noise_on * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
              "hbm_frac_noise_off": round(out_bytes / (rt_noise_off * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -523,7 +529,7 @@ def main():
         n_pool = min(wl.n_pairs, 2 * workers)
         log(f"[bench] timing the float64 CPU oracle on {n_pool} pairs, {workers} processes")
         ctx = mp.get_context("spawn")
-        with ctx.Pool(workers, initializer=os.environ.__setitem__, initargs=("OMP_NUM_THREADS", "1")) as pool:
+        with ctx.Pool(workers, initializer=_one_thread) as pool:
             pool.map(_oracle_pair, [(wl.name, 0, flows[0])] * workers)          # start-up and imports
             t0 = time.perf_counter()
             pool.map(_oracle_pair, [(wl.name, p, flows[p]) for p in range(n_pool)], chunksize=1)

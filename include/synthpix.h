@@ -200,17 +200,19 @@ synthpix_status synthpix_timing_read(const char* name, double* total_ms, int64_t
  *   SP_PROBE_TRANS  the same with v_sin_f32 (transcendental rate)
  *   SP_PROBE_MUL64  the same with a 32 x 32 -> 64-bit multiply and a xor (the
  *                   Philox round's multiply)
+ *   SP_PROBE_STORE_NT  as SP_PROBE_STORE with non-temporal stores
  * buf: device memory of `bytes` bytes (store, copy; 16-byte aligned) or of at
  * least 1 KiB (the ALU probes never write it).  iters: a positive multiple of 4
  * (ALU probes).  *work_out: bytes moved (store: written; copy: read + written)
  * or wave64 VALU instructions of the probe loop.  The launch is timed like the
  * library's other kernels ("probe_store", "probe_copy", "probe_fma",
- * "probe_trans", "probe_mul64"). */
+ * "probe_trans", "probe_mul64", "probe_store_nt"). */
 #define SP_PROBE_STORE 0
 #define SP_PROBE_COPY  1
 #define SP_PROBE_FMA   2
 #define SP_PROBE_TRANS 3
 #define SP_PROBE_MUL64 4
+#define SP_PROBE_STORE_NT 5
 synthpix_status synthpix_probe(int32_t kind, void* buf, size_t bytes, int32_t iters, void* stream,
                                double* work_out);
 

@@ -433,10 +433,11 @@ synthpix_status synthpix_probe(int32_t kind, void* buf, size_t bytes, int32_t it
                                double* work_out)
 {
     if (!work_out || !buf) return fail(SP_ERR_INVALID_ARG, "buf and work_out must be non-NULL");
-    if (kind < SP_PROBE_STORE || kind > SP_PROBE_MUL64) return fail(SP_ERR_INVALID_ARG, "unknown probe kind %d", kind);
-    if (kind <= SP_PROBE_COPY && (!aligned(buf, 16) || bytes < 32))
+    if (kind < SP_PROBE_STORE || kind > SP_PROBE_STORE_NT) return fail(SP_ERR_INVALID_ARG, "unknown probe kind %d", kind);
+    const bool mem = kind <= SP_PROBE_COPY || kind == SP_PROBE_STORE_NT;
+    if (mem && (!aligned(buf, 16) || bytes < 32))
         return fail(SP_ERR_INVALID_ARG, "store/copy probes need a 16-byte aligned buffer of >= 32 bytes");
-    if (kind > SP_PROBE_COPY && (bytes < 1024 || iters <= 0 || (iters & 3)))
+    if (!mem && (bytes < 1024 || iters <= 0 || (iters & 3)))
         return fail(SP_ERR_INVALID_ARG, "ALU probes need >= 1 KiB of buffer and iters a positive multiple of 4");
     const hipError_t e = sp::launch_probe(kind, buf, bytes, iters, as_stream(stream), work_out);
     if (e != hipSuccess) return hip_fail(e, "probe launch");

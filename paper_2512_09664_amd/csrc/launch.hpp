@@ -224,7 +224,7 @@ struct BwdArgs {
 hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, const synthpix_advect_params& ap,
                            int blur, int en, hipStream_t s);
 
-// Peak-rate probes (store, copy, fma, trans, mul64 = kinds 0..4); *work gets
+// Peak-rate probes (store, copy, fma, trans, mul64, store_nt = kinds 0..5); *work gets
 // the launch's bytes or wave64 instructions.
 hipError_t launch_probe(int kind, void* buf, size_t bytes, int iters, hipStream_t s, double* work);
 

@@ -13,12 +13,26 @@ namespace {
 
 constexpr int PROBE_CHAINS = 8;     // independent dependency chains per thread
 
-// Streaming store of zeros: every thread writes 16-byte vectors, grid-stride.
+typedef unsigned int vec4u __attribute__((ext_vector_type(4)));
+
+// Streaming store of zeros: each workgroup writes 16 KiB runs (four 16-byte
+// vectors per thread, the workgroup's 4 KiB rows one after another), grid-stride
+// over the runs; NT: non-temporal stores (no cache allocation).
+template <bool NT>
 __global__ void __launch_bounds__(256) probe_store(uint4* __restrict__ dst, size_t n16)
 {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-        dst[i] = make_uint4(0u, 0u, 0u, 0u);
+    const size_t run = 4 * 256;
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t b = (size_t)blockIdx.x * run; b < n16; b += (size_t)gridDim.x * run) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const size_t i = b + (size_t)k * 256 + threadIdx.x;
+            if (i < n16) {
+                if (NT) __builtin_nontemporal_store(vec4u{0u, 0u, 0u, 0u}, reinterpret_cast<vec4u*>(dst + i));
+                else dst[i] = z;
+            }
+        }
+    }
 }
 
 // Streaming copy of the first half of the buffer into the second half.
@@ -90,7 +104,7 @@ __global__ void __launch_bounds__(256) probe_mul64(uint32_t* __restrict__ sink, 
 }  // namespace
 
 // Enqueues one probe; *work gets the launch's unit count: bytes moved to or
-// from HBM (store: written bytes; copy: read + written), or the wave64 VALU
+// from HBM (store, store_nt: written bytes; copy: read + written), or the wave64 VALU
 // instructions of the probe's loop (fma: FMAs; trans: v_sin; mul64: the
 // multiply and xor pairs).  iters must be a multiple of 4 (the loops are
 // unrolled by four).
@@ -98,11 +112,16 @@ hipError_t launch_probe(int kind, void* buf, size_t bytes, int iters, hipStream_
 {
     const int cus = device_cu_count();
     switch (kind) {
-    case 0: {
+    case 0: case 5: {
         const size_t n16 = bytes / 16;
-        const unsigned grid = (unsigned)std::min<size_t>((n16 + 255) / 256, (size_t)cus * 32);
-        TimedScope ts("probe_store", s);
-        hipLaunchKernelGGL(probe_store, dim3(grid), dim3(256), 0, s, static_cast<uint4*>(buf), n16);
+        const unsigned grid = (unsigned)std::min<size_t>((n16 + 1023) / 1024, (size_t)cus * 16);
+        if (kind == 0) {
+            TimedScope ts("probe_store", s);
+            hipLaunchKernelGGL(probe_store<false>, dim3(grid), dim3(256), 0, s, static_cast<uint4*>(buf), n16);
+        } else {
+            TimedScope ts("probe_store_nt", s);
+            hipLaunchKernelGGL(probe_store<true>, dim3(grid), dim3(256), 0, s, static_cast<uint4*>(buf), n16);
+        }
         *work = (double)(n16 * 16);
         break;
     }

@@ -296,6 +296,29 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host,
                                               float* g_flow, void* workspace, size_t ws_bytes,
                                               void* stream);
 
+/* Allocation-free form of synthpix_render_pair, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same inputs, outputs and results as
+ * synthpix_render_pair (bit-identical images), but the workspace is a
+ * library-held static device array of SYNTHPIX_STATIC_SCRATCH_BYTES, one per
+ * device, resolved on the first call on each device and held until the
+ * process ends.  Calls nothing that allocates.  A batch whose workspace
+ * (synthpix_workspace_size) exceeds the array is refused with
+ * SP_ERR_WORKSPACE before anything is enqueued.  Every call on a device shares
+ * that device's array: calls that overlap on one device (different streams, or
+ * host threads, without ordering between them) race and are not supported.
+ * status_out: optional device uint32 that receives the call's device status
+ * word (SP_STATUS_* bits), copied stream-ordered after the render; NULL drops
+ * it. */
+#define SYNTHPIX_STATIC_SCRATCH_BYTES (64u << 20)
+synthpix_status synthpix_render_pair_noalloc(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                             int32_t n_pairs, const synthpix_tiling* tiling,
+                                             const float* x1, const float* y1,
+                                             const float* x2, const float* y2,
+                                             const float* z, const float* d, const float* I0,
+                                             const synthpix_render_params* rp, void* images,
+                                             uint32_t* status_out, void* stream);
+
 /* ------------------------------------------------------- batched, captured form */
 
 /* Device buffers and draw key of one launch of a plan.  synthpix_plan_create

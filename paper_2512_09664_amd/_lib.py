@@ -104,6 +104,8 @@ SIGNATURES = {
     "synthpix_advect_workspace_size": [_PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "synthpix_render_pair": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
                              ctypes.POINTER(RenderParams), _P, _P, ctypes.c_size_t, _P],
+    "synthpix_render_pair_noalloc": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
+                                     ctypes.POINTER(RenderParams), _P, _P, _P],
     "synthpix_render_pair_backward": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
                                       _P, ctypes.POINTER(RenderParams), _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P],

@@ -267,6 +267,20 @@ def render_pair(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, tile=None, image
     return images
 
 
+def render_pair_noalloc(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, images, tile=None, status=None):
+    """Run ``synthpix_render_pair_noalloc`` into the caller's ``images`` (the
+    library's static scratch is the workspace; nothing is allocated).
+    ``status``: optional int32/uint32 device tensor of one element that receives
+    the device status word."""
+    _need_cuda(x1, y1, x2, y2, z, d, I0, images, status)
+    L.check(L.load().synthpix_render_pair_noalloc(batch.host_ptr, batch.dev_ptr, batch.n_pairs,
+                                                  ctypes.byref(tile) if tile is not None else None,
+                                                  _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(z), _ptr(d),
+                                                  _ptr(I0), ctypes.byref(rp), _ptr(images), _ptr(status),
+                                                  _stream()))
+    return images
+
+
 def render_pair_backward(batch: PairBatch, flow, x1, y1, z, d, I0, rp, grad_images, tile=None, workspace=None,
                          x2=None, y2=None):
     """Run ``synthpix_render_pair_backward``; returns dict of gradients.  Pass the

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -659,6 +660,88 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
 
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ static scratch
+
+// Library-held workspace of synthpix_render_pair_noalloc: one copy per device,
+// held until the process ends.  Host code never uses the array's name as an
+// address (on the host it is a stand-in, not device memory): each device's
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current.
+static __device__ __align__(256) unsigned char scratch[SYNTHPIX_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's scratch address (resolved on the first call per device).
+synthpix_status scratch_of_current_device(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(SP_ERR_UNSUPPORTED, "device %d: at most %d devices", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SP_OK;
+}
+
+}  // namespace
+
+extern "C" synthpix_status synthpix_render_pair_noalloc(const synthpix_pair* pairs_host,
+                                                        const synthpix_pair* pairs_dev, int32_t n_pairs,
+                                                        const synthpix_tiling* tiling, const float* x1,
+                                                        const float* y1, const float* x2, const float* y2,
+                                                        const float* z, const float* d, const float* I0,
+                                                        const synthpix_render_params* rp, void* images,
+                                                        uint32_t* status_out, void* stream)
+{
+    int64_t span;
+    synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
+    if (st) return st;
+    if ((st = check_render_params(rp))) return st;
+    const synthpix_tiling t = tiling ? *tiling : default_tiling();
+    if ((st = check_tiling(t))) return st;
+    if (!dev_ptr_ok(x1) || !dev_ptr_ok(y1) || !dev_ptr_ok(x2) || !dev_ptr_ok(y2) || !dev_ptr_ok(z) ||
+        !dev_ptr_ok(d) || !dev_ptr_ok(I0))
+        return fail(SP_ERR_INVALID_ARG, "particle arrays must be non-NULL, 4-byte aligned device pointers");
+    if (!images || !aligned(images, rp->bits ? 2 : 4))
+        return fail(SP_ERR_INVALID_ARG, "images must be a non-NULL, aligned device pointer");
+    if (status_out && !aligned(status_out, 4))
+        return fail(SP_ERR_INVALID_ARG, "status_out must be NULL or a 4-byte aligned device pointer");
+    const sp::RenderConfig cfg = make_config(*rp, t);
+    sp::BatchTotals T;
+    if ((st = batch_totals(pairs_host, n_pairs, cfg, &T))) return st;
+    const sp::WorkspaceLayout wl = workspace_layout(n_pairs, T, 0, pairs_host);
+    if (wl.total > (size_t)SYNTHPIX_STATIC_SCRATCH_BYTES)
+        return fail(SP_ERR_WORKSPACE,
+                    "batch needs %zu bytes of workspace; the static scratch holds %zu (split the batch or use "
+                    "synthpix_render_pair with a caller workspace)",
+                    wl.total, (size_t)SYNTHPIX_STATIC_SCRATCH_BYTES);
+    if (sp::render_lds_bytes(cfg) > 160 * 1024)
+        return fail(SP_ERR_UNSUPPORTED, "tiling needs %zu bytes of LDS per workgroup (max 163840)",
+                    sp::render_lds_bytes(cfg));
+    void* ws = nullptr;
+    if ((st = scratch_of_current_device(&ws))) return st;
+    // every part of the workspace the kernels read is written earlier in the same
+    // call (the status words are cleared by the layout kernel), so the previous
+    // call's contents need no clearing
+    hipError_t e = enqueue_render(pairs_dev, n_pairs, cfg, T, wl, x1, y1, x2, y2, z, d, I0, *rp, images, ws,
+                                  as_stream(stream));
+    if (e == hipSuccess && status_out)
+        e = hipMemcpyAsync(status_out, static_cast<char*>(ws) + wl.status, sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return SP_OK;
+}
 
 // ------------------------------------------------------------------ plans
 

@@ -57,3 +57,13 @@ def advect(flow, H: int, W: int, x, y, dt: float = 1.0, substeps: int = 1,
         else:
             raise ValueError(integrator)
     return px, py
+
+
+def flow_field(flow, H: int, W: int):
+    """Ground-truth flow [H, W, 2]: the field sampled at every pixel centre
+    (the flow_fields a sampler returns next to the images, Section 2 "Usage")."""
+    cx = np.arange(W, dtype=np.float64) + 0.5
+    cy = np.arange(H, dtype=np.float64) + 0.5
+    px, py = np.meshgrid(cx, cy)
+    u, v = sample(flow, H, W, px, py)
+    return np.stack([u, v], axis=-1)

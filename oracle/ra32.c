@@ -567,3 +567,18 @@ void ra_advect_z(const float* F, const float* Gw_, int Gh, int Gw, int H, int W,
         z2[i] = pz;
     }
 }
+
+/* Ground-truth flow field: the (u, v) grid sampled at every pixel centre
+ * (c + 1/2, r + 1/2), as the advection samples it; out [H][W][2]. */
+void ra_flow_field(const float* F, int Gh, int Gw, int H, int W, float* out)
+{
+    const float sx = (float)Gw / (float)W;
+    const float sy = (float)Gh / (float)H;
+    for (int r = 0; r < H; ++r)
+        for (int c = 0; c < W; ++c) {
+            float u, v;
+            sample(F, Gh, Gw, sx, sy, (float)c + 0.5f, (float)r + 0.5f, &u, &v);
+            out[2 * ((size_t)r * W + c)] = u;
+            out[2 * ((size_t)r * W + c) + 1] = v;
+        }
+}

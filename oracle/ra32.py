@@ -74,6 +74,7 @@ def load():
                                         _f32p, _f32p, _u32p]
     L.ra_advect_z.argtypes = [_f32p, _f32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                               _f32p, _f32p, _f32p, ctypes.c_float, ctypes.c_int, ctypes.c_int, _f32p]
+    L.ra_flow_field.argtypes = [_f32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _f32p]
     _lib = L
     return L
 
@@ -272,4 +273,12 @@ def generate_pair_model(m, H, W, pair_id, seed, flow, wgrid=None, blur_w=None, b
     out = {"particles": P, "dy": dy, "rho": rho, "x2": x2, "y2": y2, "z2": z2, "frame1": f1, "frame2": f2, "J": J}
     if bits > 0:
         out["codes"] = quantise(J, bits)
+    return out
+
+
+def flow_field(flow, H, W):
+    """[H, W, 2] binary32 field at the pixel centres."""
+    flow = _f(flow)
+    out = np.zeros((H, W, 2), dtype=np.float32)
+    load().ra_flow_field(flow, flow.shape[0], flow.shape[1], int(H), int(W), out.reshape(-1))
     return out

@@ -121,3 +121,29 @@ def test_binary32_mirror_tracks_float64(ra, integrator, n):
     rx, ry = ra.advect(F, H, W, P["x"], P["y"], 1.0, n, integrator)
     assert np.max(np.abs(rx - x2)) < 1e-4 and np.max(np.abs(ry - y2)) < 1e-4
     assert np.max(np.hypot(x2 - P["x"], y2 - P["y"])) > 1.0   # the flow actually moved them
+
+
+def test_flow_field_pins():
+    from oracle import ra32
+    H, W, Gh, Gw = 48, 64, 12, 16
+    # uniform grid: every pixel carries the grid's value exactly
+    flow = np.zeros((Gh, Gw, 2))
+    flow[..., 0], flow[..., 1] = 2.5, -1.25
+    f = adv.flow_field(flow, H, W)
+    assert np.all(f[..., 0] == 2.5) and np.all(f[..., 1] == -1.25)
+    assert np.array_equal(ra32.flow_field(flow, H, W), f.astype(np.float32))
+    # affine field: reproduced exactly inside the node hull; pixel centres that
+    # coincide with nodes carry the node values
+    jx = (np.arange(Gw) + 0.5) * W / Gw
+    iy = (np.arange(Gh) + 0.5) * H / Gh
+    flow[..., 0] = 0.03 * jx[None, :] - 0.02 * iy[:, None] + 0.5
+    flow[..., 1] = -0.01 * jx[None, :] + 0.04 * iy[:, None]
+    f = adv.flow_field(flow, H, W)
+    px, py = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    inside = (px >= jx[0]) & (px <= jx[-1]) & (py >= iy[0]) & (py <= iy[-1])
+    assert np.max(np.abs(f[..., 0] - (0.03 * px - 0.02 * py + 0.5))[inside]) < 1e-12
+    assert np.max(np.abs(f[..., 1] - (-0.01 * px + 0.04 * py))[inside]) < 1e-12
+    # the binary32 mirror within rounding of the definition
+    rng = np.random.default_rng(0)
+    flow = rng.normal(0, 3, (Gh, Gw, 2))
+    assert np.max(np.abs(ra32.flow_field(flow, H, W) - adv.flow_field(flow.astype(np.float32), H, W))) < 1e-5

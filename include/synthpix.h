@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define SYNTHPIX_VERSION 2
+#define SYNTHPIX_VERSION 3
 
 typedef enum {
     SP_OK = 0,
@@ -76,10 +76,19 @@ typedef enum { SP_EULER = 0, SP_RK4 = 1 } synthpix_integrator;
 typedef enum { SP_DIST_UNIFORM = 0, SP_DIST_NORMAL_CLIPPED = 1 } synthpix_dist;
 
 /* Device status bits (workspace word 0). */
-#define SP_STATUS_D_ABOVE_MAX   0x1u   /* a particle had d > d_max; it was not rendered */
+#define SP_STATUS_D_ABOVE_MAX   0x1u   /* a particle had d (or d_y) > d_max; it was not rendered */
 #define SP_STATUS_FIXED_RANGE   0x2u   /* the peaks of the particles covering one pixel row of a
                                           tile sum to >= 256 full scale: a pixel sum could have
                                           left the 32-bit fixed-point range */
+#define SP_STATUS_BAD_SHAPE     0x4u   /* a particle had |rho| > 0.99; it was not rendered */
+#define SP_STATUS_HIST_TARGET   0x8u   /* histogram adjustment: the target's total is 0 or >= 2^32;
+                                          the images were left unchanged */
+#define SP_STATUS_HIST_CODE     0x10u  /* histogram adjustment: a stored code >= 2^bits was taken
+                                          as 2^bits - 1 */
+
+/* Laser-sheet laws of the peak intensity. */
+#define SP_SHEET_GAUSS   0   /* I0 exp(-z^2 / (2 s^2)), s = sheet_sigma                           */
+#define SP_SHEET_REMARK1 1   /* I0 exp(-(1/sqrt(2 pi)) |2 z^2 / DZ0^2|^shape) (Remark 1, q = I0)   */
 
 /* One image pair.  An array of these describes a batch, pairs of different size
  * included.  56 bytes, identical layout on host and device. */
@@ -120,9 +129,29 @@ typedef struct {
     float    blur_sigma;        /* > 0 when blur_radius > 0                                      */
     float    noise_sigma;       /* >= 0; additive N(0, sigma^2) full-scale units after the blur  */
     int32_t  bits;              /* 0: float images; 1..16: uint16 codes of that depth            */
-    uint64_t seed;              /* key of the noise draws                                        */
+    uint64_t seed;              /* key of the noise, frame-2 variation and hiding draws          */
     synthpix_advect_params advect;  /* used by the backward to recompute frame-2 positions  */
+    /* The full particle model (all zero: the isotropic Gaussian-sheet path).  Frame 2
+     * varies each particle parameter by a zero-mean Gaussian (the sentence after
+     * Eq. 1): d and d_y by jitter_d (clipped to [0, d_max]), rho by jitter_rho
+     * (clipped to [-0.99, 0.99]), I0 by jitter_I0 (clipped at 0; masked particles
+     * stay dark).  Each particle is hidden (intensity 0) in each frame with
+     * probability hide_p (Section 2, "Considerations on the aggregation"). */
+    float    hide_p;            /* [0, 1]                                                         */
+    float    jitter_d;          /* >= 0, pixels                                                   */
+    float    jitter_rho;        /* >= 0                                                           */
+    float    jitter_I0;         /* >= 0, full-scale units                                         */
+    int32_t  sheet_law;         /* SP_SHEET_GAUSS or SP_SHEET_REMARK1                             */
+    float    sheet_dz0;         /* SP_SHEET_REMARK1: laser-sheet thickness DZ0 (> 0)              */
+    float    sheet_shape;       /* SP_SHEET_REMARK1: shape factor (> 0)                           */
 } synthpix_render_params;
+
+/* Optional per-particle inputs of the full model (any pointer may be NULL). */
+typedef struct {
+    const float* dy;            /* second diameter d_y: sigma_y = d_y / 4 (NULL: d_y = d)        */
+    const float* rho;           /* correlation of Eq. 1, |rho| <= 0.99 (NULL: 0)                  */
+    const float* z2;            /* frame-2 out-of-plane position (NULL: frame 1's z)              */
+} synthpix_particle_extras;
 
 /* Screen tiling used by the renderer.  Tiles are tile_w x tile_h pixels, one of
  * 8x8, 16x16, 32x16, 32x32, 64x16, 64x32, 64x64, 128x32.  NULL selects the
@@ -237,6 +266,12 @@ synthpix_status synthpix_seed(const synthpix_pair* pairs_host, const synthpix_pa
  * `substeps` steps of explicit Euler or classical RK4.
  * flow: device floats holding every pair's grid at pair.flow_offset.
  * x1, y1 -> x2, y2: device float arrays (x2/y2 may not alias x1/y1).
+ * wflow, z1, z2: all NULL (planar motion) or all set: the three-dimensional
+ * motion of Remark 1's particles, z2 = z1 + the integral of the out-of-plane
+ * velocity w along the in-plane trajectory (same integrator stages); wflow
+ * holds each pair's [Gh][Gw] w grid (sheet units per frame, registered like
+ * the (u, v) grid) at float offset pair.flow_offset / 2.  The 3-D form runs in
+ * particle index order (the workspace is not used).
  * workspace: optional device scratch, 256-byte aligned, of at least
  * synthpix_advect_workspace_size bytes (any workspace sized by
  * synthpix_workspace_size also fits).  With it, particles are first ordered by
@@ -245,7 +280,18 @@ synthpix_status synthpix_seed(const synthpix_pair* pairs_host, const synthpix_pa
 synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
                                 int32_t n_pairs, const float* flow, const synthpix_advect_params* ap,
                                 const float* x1, const float* y1, float* x2, float* y2,
+                                const float* wflow, const float* z1, float* z2,
                                 void* workspace, size_t ws_bytes, void* stream);
+
+/* Second diameter and correlation of every candidate particle for anisotropic
+ * particle images (Eq. 1; the sentence after it draws every shape parameter
+ * per particle): d_y from the seed's diameter distribution, rho ~ U[rho_lo,
+ * rho_hi] with -0.99 <= rho_lo <= rho_hi <= 0.99.  Draws: Philox stream 6 at
+ * the particle index (word 0 uniform d_y; words 1, 2 Box-Muller of a normal
+ * d_y; word 3 rho).  dy, rho: device float arrays like synthpix_seed's. */
+synthpix_status synthpix_seed_shape(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                    int32_t n_pairs, const synthpix_seed_params* sp, float rho_lo,
+                                    float rho_hi, uint64_t seed, float* dy, float* rho, void* stream);
 
 /* Bytes of the optional synthpix_advect workspace for this batch. */
 synthpix_status synthpix_advect_workspace_size(const synthpix_pair* pairs_host, int32_t n_pairs,
@@ -255,6 +301,10 @@ synthpix_status synthpix_advect_workspace_size(const synthpix_pair* pairs_host, 
  * (Eq. 1; Section 2, "Considerations on the aggregation", "Efficient
  * rasterization").  Frame 1 uses (x1, y1), frame 2 (x2, y2); z, d, I0 are
  * shared.  Particles with I0 <= 0, d <= 0 or non-finite position add nothing.
+ * extras: NULL, or the full model's per-particle d_y, rho and frame-2 z (each
+ * optional); with rp's frame-2 variation, hiding and sheet law they select the
+ * full model (an anisotropic particle adds I0 S(z) times Eq. 1 with
+ * sigma_x = d / 4, sigma_y = d_y / 4 on |dx| <= 1.5 d, |dy| <= 1.5 d_y).
  * tiling may be NULL (default); the output does not depend on it.
  * images: device buffer, float or uint16 per rp->bits; only the pairs' image
  * ranges are written.
@@ -264,10 +314,12 @@ synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synt
                                      const float* x1, const float* y1,
                                      const float* x2, const float* y2,
                                      const float* z, const float* d, const float* I0,
+                                     const synthpix_particle_extras* extras,
                                      const synthpix_render_params* rp, void* images,
                                      void* workspace, size_t ws_bytes, void* stream);
 
-/* Gradient of a loss L of the float images J (bits must be 0) with respect to
+/* Gradient of a loss L of the float images J (bits must be 0; the isotropic
+ * model: no frame-2 variation, no hiding, the Gaussian sheet) with respect to
  * the frame-1 positions, z, d, I0, each pair's sheet width and each pair's flow
  * grid (differentiating Eq. 1 with the Gaussian sheet peak, the patch cutoff
  * held fixed, and the blur; noise is additive and has no gradient).
@@ -316,8 +368,33 @@ synthpix_status synthpix_render_pair_noalloc(const synthpix_pair* pairs_host, co
                                              const float* x1, const float* y1,
                                              const float* x2, const float* y2,
                                              const float* z, const float* d, const float* I0,
+                                             const synthpix_particle_extras* extras,
                                              const synthpix_render_params* rp, void* images,
                                              uint32_t* status_out, void* stream);
+
+/* Ground-truth flow of every pair (the flow_fields a sampler returns next to
+ * the images, Section 2 "Usage"): the pair's (u, v) grid, pixels per frame,
+ * sampled bilinearly at each pixel centre (c + 1/2, r + 1/2) exactly as the
+ * advection samples it.  out: device floats, each pair's [H][W][2] field at
+ * float offset pair.image_offset (8-byte aligned; the same extent as the
+ * pair's two float frames).  n_pairs <= 65535. */
+synthpix_status synthpix_flow_field(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                    int32_t n_pairs, const float* flow, float* out, void* stream);
+
+/* Histogram adjustment of the stored images (Section 2, after Remark 2: the
+ * images are optionally adjusted to a user-specified intensity histogram).
+ * Every image (each frame of each pair, uint16 codes of `bits` bits, 1..14) is
+ * mapped in place onto the target histogram `target` (device uint32 counts
+ * [2^bits], total in [1, 2^32)): code k becomes the smallest m with
+ * T(m) / T_tot >= S(k) / N, where S and T are the cumulative counts of the
+ * image (N pixels) and of the target (T_tot); the comparison is exact integer
+ * arithmetic.  workspace: device, 256-byte aligned, at least
+ * synthpix_histogram_workspace_size bytes; its first word is the call's
+ * device status (SP_STATUS_HIST_*; synthpix_read_status reads it). */
+synthpix_status synthpix_histogram_workspace_size(int32_t n_pairs, int32_t bits, size_t* bytes_out);
+synthpix_status synthpix_histogram_match(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                         int32_t n_pairs, int32_t bits, const uint32_t* target, void* images,
+                                         void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------- batched, captured form */
 

@@ -24,6 +24,8 @@ SP_EULER = 0
 SP_RK4 = 1
 SP_DIST_UNIFORM = 0
 SP_DIST_NORMAL_CLIPPED = 1
+SP_SHEET_GAUSS = 0
+SP_SHEET_REMARK1 = 1
 
 SP_STATUS_D_ABOVE_MAX = 0x1
 SP_STATUS_FIXED_RANGE = 0x2
@@ -56,7 +58,14 @@ class AdvectParams(ctypes.Structure):
 class RenderParams(ctypes.Structure):
     _fields_ = [("sheet_sigma", ctypes.c_float), ("d_max", ctypes.c_float), ("blur_radius", ctypes.c_int32),
                 ("blur_sigma", ctypes.c_float), ("noise_sigma", ctypes.c_float), ("bits", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("advect", AdvectParams)]
+                ("seed", ctypes.c_uint64), ("advect", AdvectParams),
+                ("hide_p", ctypes.c_float), ("jitter_d", ctypes.c_float), ("jitter_rho", ctypes.c_float),
+                ("jitter_I0", ctypes.c_float), ("sheet_law", ctypes.c_int32), ("sheet_dz0", ctypes.c_float),
+                ("sheet_shape", ctypes.c_float)]
+
+
+class ParticleExtras(ctypes.Structure):
+    _fields_ = [("dy", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("z2", ctypes.c_void_p)]
 
 
 class Tiling(ctypes.Structure):
@@ -78,6 +87,7 @@ class BatchIO(ctypes.Structure):
 
 
 assert ctypes.sizeof(Pair) == 56
+assert ctypes.sizeof(RenderParams) == 72
 
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(Pair)
@@ -99,13 +109,19 @@ SIGNATURES = {
                               ctypes.POINTER(BinViews)],
     "synthpix_seed": [_PP, _P, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.c_uint64,
                       _P, _P, _P, _P, _P, _P, _P, _P],
-    "synthpix_advect": [_PP, _P, ctypes.c_int32, _P, ctypes.POINTER(AdvectParams), _P, _P, _P, _P, _P,
+    "synthpix_advect": [_PP, _P, ctypes.c_int32, _P, ctypes.POINTER(AdvectParams), _P, _P, _P, _P, _P, _P, _P, _P,
                         ctypes.c_size_t, _P],
+    "synthpix_flow_field": [_PP, _P, ctypes.c_int32, _P, _P, _P],
+    "synthpix_histogram_workspace_size": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "synthpix_histogram_match": [_PP, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P],
+    "synthpix_seed_shape": [_PP, _P, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.c_float, ctypes.c_float,
+                            ctypes.c_uint64, _P, _P, _P],
     "synthpix_advect_workspace_size": [_PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "synthpix_render_pair": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
-                             ctypes.POINTER(RenderParams), _P, _P, ctypes.c_size_t, _P],
+                             ctypes.POINTER(ParticleExtras), ctypes.POINTER(RenderParams), _P, _P, ctypes.c_size_t,
+                             _P],
     "synthpix_render_pair_noalloc": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
-                                     ctypes.POINTER(RenderParams), _P, _P, _P],
+                                     ctypes.POINTER(ParticleExtras), ctypes.POINTER(RenderParams), _P, _P, _P],
     "synthpix_render_pair_backward": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
                                       _P, ctypes.POINTER(RenderParams), _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P],

@@ -57,9 +57,13 @@ class PairBatch:
     @staticmethod
     def build(sizes: Sequence[Tuple[int, int]], grids: Sequence[Tuple[int, int]], n_max: Sequence[int],
               pair_ids: Optional[Sequence[int]] = None, device="cuda",
-              gaps: Tuple[int, int, int] = (0, 0, 0)) -> "PairBatch":
+              gaps: Tuple[int, int, int] = (0, 0, 0), flow_index: Optional[Sequence[int]] = None,
+              non_blocking: bool = False) -> "PairBatch":
         """Pairs packed in table order; ``gaps`` leaves that many unused particles,
-        image elements and flow floats (even) before every pair's range."""
+        image elements and flow floats (even) before every pair's range.
+        ``flow_index``: pairs that share a flow grid (pair p uses grid
+        flow_index[p]; grids packed in index order, all of pair p's shape).
+        ``non_blocking``: upload the table from pinned memory without waiting."""
         if gaps[2] % 2:
             raise ValueError("flow gaps must be even (one (u, v) node is two floats)")
         n = len(sizes)
@@ -79,8 +83,14 @@ class PairBatch:
             po += int(n_max[p])
             io += 2 * int(H) * int(W)
             fo += 2 * int(Gh) * int(Gw)
+        if flow_index is not None:
+            fo = 0
+            for p in range(n):
+                arr[p].flow_offset = 2 * int(grids[p][0]) * int(grids[p][1]) * int(flow_index[p])
+                fo = max(fo, int(arr[p].flow_offset) + 2 * int(grids[p][0]) * int(grids[p][1]))
         raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
-        dev = torch.from_numpy(raw).to(device)
+        t = torch.from_numpy(raw)
+        dev = t.pin_memory().to(device, non_blocking=True) if non_blocking else t.to(device)
         return PairBatch(arr, dev, n, po, io, fo, tuple(map(tuple, sizes)), tuple(map(tuple, grids)),
                          tuple(int(v) for v in n_max))
 
@@ -119,8 +129,16 @@ def advect_params(dt=1.0, substeps=1, integrator="euler"):
 
 
 def render_params(sheet_sigma=0.5, d_max=5.0, blur_radius=0, blur_sigma=0.7, noise_sigma=0.0, bits=0, seed=0,
-                  dt=1.0, substeps=1, integrator="euler"):
+                  dt=1.0, substeps=1, integrator="euler", hide_p=0.0, jitter=(0.0, 0.0, 0.0), sheet_law="gauss",
+                  sheet_dz0=0.0, sheet_shape=0.0):
+    """Rendering parameters; ``jitter`` = standard deviations of the frame-2
+    change of (diameters, rho, I0); ``sheet_law`` "gauss" or "remark1"."""
     rp = L.RenderParams()
+    rp.hide_p = float(hide_p)
+    rp.jitter_d, rp.jitter_rho, rp.jitter_I0 = (float(v) for v in jitter)
+    rp.sheet_law = {"gauss": L.SP_SHEET_GAUSS, "remark1": L.SP_SHEET_REMARK1}[sheet_law]
+    rp.sheet_dz0 = float(sheet_dz0)
+    rp.sheet_shape = float(sheet_shape)
     rp.sheet_sigma = float(sheet_sigma)
     rp.d_max = float(d_max)
     rp.blur_radius = int(blur_radius)
@@ -175,19 +193,75 @@ def advect_workspace_size(batch: PairBatch) -> int:
 
 
 def advect(batch: PairBatch, flow: torch.Tensor, ap, x1: torch.Tensor, y1: torch.Tensor, x2=None, y2=None,
-           workspace: Optional[torch.Tensor] = None, ordered: bool = True):
+           workspace: Optional[torch.Tensor] = None, ordered: bool = True, wflow=None, z1=None, z2=None):
     """Run ``synthpix_advect``.  ``ordered`` processes particles in home-block
     order (same results, faster); its scratch is ``workspace`` if given (e.g. a
-    render workspace), else a temporary."""
-    _need_cuda(flow, x1, y1)
+    render workspace), else a temporary.  With ``wflow`` (each pair's w grid)
+    and ``z1``, z is moved too and (x2, y2, z2) is returned."""
+    _need_cuda(flow, x1, y1, wflow, z1, z2)
+    if wflow is not None:
+        x2 = torch.empty_like(x1) if x2 is None else x2
+        y2 = torch.empty_like(y1) if y2 is None else y2
+        z2 = torch.empty_like(z1) if z2 is None else z2
+        L.check(L.load().synthpix_advect(batch.host_ptr, batch.dev_ptr, batch.n_pairs, _ptr(flow), ctypes.byref(ap),
+                                         _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(wflow), _ptr(z1), _ptr(z2),
+                                         None, 0, _stream()))
+        return x2, y2, z2
     x2 = torch.empty_like(x1) if x2 is None else x2
     y2 = torch.empty_like(y1) if y2 is None else y2
     if ordered and workspace is None:
         workspace = torch.empty(max(advect_workspace_size(batch), 256), dtype=torch.uint8, device=x1.device)
     ws, nb = (_ptr(workspace), workspace.numel()) if ordered else (None, 0)
     L.check(L.load().synthpix_advect(batch.host_ptr, batch.dev_ptr, batch.n_pairs, _ptr(flow), ctypes.byref(ap),
-                                     _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), ws, nb, _stream()))
+                                     _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), None, None, None, ws, nb, _stream()))
     return x2, y2
+
+
+def seed_shape(batch: PairBatch, sp, rho, seed_value: int, out=None):
+    """Run ``synthpix_seed_shape``: (dy, rho) float32 [n_particles]."""
+    dev = batch.dev.device
+    n = max(batch.n_particles, 1)
+    dy, r = out if out is not None else (torch.empty(n, dtype=torch.float32, device=dev),
+                                         torch.empty(n, dtype=torch.float32, device=dev))
+    L.check(L.load().synthpix_seed_shape(batch.host_ptr, batch.dev_ptr, batch.n_pairs, ctypes.byref(sp),
+                                         float(rho[0]), float(rho[1]), int(seed_value), _ptr(dy), _ptr(r), _stream()))
+    return dy, r
+
+
+def flow_field(batch: PairBatch, flow: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Run ``synthpix_flow_field``: each pair's (u, v) at its pixel centres,
+    [H][W][2] at the pair's image offset of a float buffer of the images' size."""
+    _need_cuda(flow, out)
+    if out is None:
+        out = torch.empty(batch.n_pixels, dtype=torch.float32, device=flow.device)
+    L.check(L.load().synthpix_flow_field(batch.host_ptr, batch.dev_ptr, batch.n_pairs, _ptr(flow), _ptr(out),
+                                         _stream()))
+    return out
+
+
+def histogram_match(batch: PairBatch, images: torch.Tensor, target: torch.Tensor, bits: int, workspace=None):
+    """Run ``synthpix_histogram_match``: every frame's codes mapped in place onto
+    the target histogram (uint32/int32 device counts [2^bits]).  Returns the
+    workspace (its status word: ``read_status``)."""
+    _need_cuda(images, target)
+    n = ctypes.c_size_t(0)
+    L.check(L.load().synthpix_histogram_workspace_size(batch.n_pairs, int(bits), ctypes.byref(n)))
+    if workspace is None:
+        workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=images.device)
+    L.check(L.load().synthpix_histogram_match(batch.host_ptr, batch.dev_ptr, batch.n_pairs, int(bits), _ptr(target),
+                                              _ptr(images), _ptr(workspace), workspace.numel(), _stream()))
+    return workspace
+
+
+def _extras(dy, rho, z2):
+    if dy is None and rho is None and z2 is None:
+        return None
+    _need_cuda(dy, rho, z2)
+    ex = L.ParticleExtras()
+    ex.dy = dy.data_ptr() if dy is not None else None
+    ex.rho = rho.data_ptr() if rho is not None else None
+    ex.z2 = z2.data_ptr() if z2 is not None else None
+    return ctypes.byref(ex)
 
 
 def workspace_size(batch: PairBatch, rp, tile=None, backward=False) -> int:
@@ -250,8 +324,10 @@ def read_status(workspace: torch.Tensor) -> int:
     return flags.value
 
 
-def render_pair(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, tile=None, images=None, workspace=None):
-    """Run ``synthpix_render_pair``; returns images [n_pixels] (float32 or uint16)."""
+def render_pair(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, tile=None, images=None, workspace=None, dy=None,
+                rho=None, z2=None):
+    """Run ``synthpix_render_pair``; returns images [n_pixels] (float32 or uint16).
+    dy, rho, z2: the full model's optional per-particle inputs."""
     _need_cuda(x1, y1, x2, y2, z, d, I0)
     dev = x1.device
     if images is None:
@@ -262,12 +338,13 @@ def render_pair(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, tile=None, image
     L.check(L.load().synthpix_render_pair(batch.host_ptr, batch.dev_ptr, batch.n_pairs,
                                           ctypes.byref(tile) if tile is not None else None,
                                           _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(z), _ptr(d), _ptr(I0),
-                                          ctypes.byref(rp), _ptr(images), _ptr(workspace),
+                                          _extras(dy, rho, z2), ctypes.byref(rp), _ptr(images), _ptr(workspace),
                                           workspace.numel(), _stream()))
     return images
 
 
-def render_pair_noalloc(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, images, tile=None, status=None):
+def render_pair_noalloc(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, images, tile=None, status=None, dy=None,
+                        rho=None, z2=None):
     """Run ``synthpix_render_pair_noalloc`` into the caller's ``images`` (the
     library's static scratch is the workspace; nothing is allocated).
     ``status``: optional int32/uint32 device tensor of one element that receives
@@ -276,8 +353,8 @@ def render_pair_noalloc(batch: PairBatch, x1, y1, x2, y2, z, d, I0, rp, images, 
     L.check(L.load().synthpix_render_pair_noalloc(batch.host_ptr, batch.dev_ptr, batch.n_pairs,
                                                   ctypes.byref(tile) if tile is not None else None,
                                                   _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(z), _ptr(d),
-                                                  _ptr(I0), ctypes.byref(rp), _ptr(images), _ptr(status),
-                                                  _stream()))
+                                                  _ptr(I0), _extras(dy, rho, z2), ctypes.byref(rp), _ptr(images),
+                                                  _ptr(status), _stream()))
     return images
 
 

@@ -87,6 +87,37 @@ synthpix_status check_render_params(const synthpix_render_params* rp)
     if (!(rp->noise_sigma >= 0.0f) || !std::isfinite(rp->noise_sigma))
         return fail(SP_ERR_INVALID_ARG, "noise_sigma must be >= 0 and finite");
     if (rp->bits < 0 || rp->bits > 16) return fail(SP_ERR_INVALID_ARG, "bits must be in [0, 16]");
+    if (!(rp->hide_p >= 0.0f && rp->hide_p <= 1.0f)) return fail(SP_ERR_INVALID_ARG, "hide_p must be in [0, 1]");
+    if (!(rp->jitter_d >= 0.0f) || !std::isfinite(rp->jitter_d) || !(rp->jitter_rho >= 0.0f) ||
+        !std::isfinite(rp->jitter_rho) || !(rp->jitter_I0 >= 0.0f) || !std::isfinite(rp->jitter_I0))
+        return fail(SP_ERR_INVALID_ARG, "frame-2 variation standard deviations must be >= 0 and finite");
+    if (rp->sheet_law != SP_SHEET_GAUSS && rp->sheet_law != SP_SHEET_REMARK1)
+        return fail(SP_ERR_INVALID_ARG, "unknown sheet law %d", rp->sheet_law);
+    if (rp->sheet_law == SP_SHEET_REMARK1 &&
+        !(rp->sheet_dz0 > 0.0f && std::isfinite(rp->sheet_dz0) && rp->sheet_shape > 0.0f &&
+          std::isfinite(rp->sheet_shape)))
+        return fail(SP_ERR_INVALID_ARG, "the Remark 1 sheet law needs sheet_dz0 > 0 and sheet_shape > 0");
+    return SP_OK;
+}
+
+// The full particle model is in use (the model's prep kernel runs) ...
+bool model_in_use(const synthpix_render_params& rp, const synthpix_particle_extras* ex)
+{
+    return rp.hide_p > 0.0f || rp.jitter_d > 0.0f || rp.jitter_rho > 0.0f || rp.jitter_I0 > 0.0f ||
+           rp.sheet_law != SP_SHEET_GAUSS || (ex && (ex->dy || ex->rho || ex->z2));
+}
+
+// ... and its particles may be anisotropic (shape records, anisotropic kernels).
+bool aniso_in_use(const synthpix_render_params& rp, const synthpix_particle_extras* ex)
+{
+    return rp.jitter_d > 0.0f || rp.jitter_rho > 0.0f || (ex && (ex->dy || ex->rho));
+}
+
+synthpix_status check_extras(const synthpix_particle_extras* ex)
+{
+    if (!ex) return SP_OK;
+    if ((ex->dy && !dev_ptr_ok(ex->dy)) || (ex->rho && !dev_ptr_ok(ex->rho)) || (ex->z2 && !dev_ptr_ok(ex->z2)))
+        return fail(SP_ERR_INVALID_ARG, "extras dy, rho, z2 must be NULL or 4-byte aligned device pointers");
     return SP_OK;
 }
 
@@ -173,6 +204,7 @@ sp::WorkspaceLayout workspace_layout(int32_t n_pairs, const sp::BatchTotals& T, 
     w.hist = o; o = align256(o + sizeof(uint32_t) * (size_t)T.hist);
     w.entries = o; o = align256(o + sizeof(int32_t) * (size_t)T.entries);
     w.records = o; o = align256(o + 2 * 16 * (size_t)T.n_span);
+    w.shapes = o; o = align256(o + 2 * 8 * (size_t)T.n_span);
     (void)backward;
     (void)ph;
     w.total = o;
@@ -274,9 +306,23 @@ hipError_t enqueue_render(const synthpix_pair* pairs_dev, int32_t n_pairs, const
                           const sp::BatchTotals& T, const sp::WorkspaceLayout& wl, const float* x1, const float* y1,
                           const float* x2, const float* y2, const float* z, const float* d, const float* I0,
                           const synthpix_render_params& rp, void* images, void* workspace, hipStream_t stream,
-                          const synthpix_batch_io* iod = nullptr)
+                          const synthpix_batch_io* iod = nullptr, const synthpix_particle_extras* ex = nullptr)
 {
     sp::RenderArgs a{};
+    if (ex) {
+        a.dy = ex->dy;
+        a.rho = ex->rho;
+        a.z2 = ex->z2;
+    }
+    a.hide_p = rp.hide_p;
+    a.jit_d = rp.jitter_d;
+    a.jit_rho = rp.jitter_rho;
+    a.jit_I0 = rp.jitter_I0;
+    a.sheet_law = rp.sheet_law;
+    a.sheet_dz0 = rp.sheet_dz0;
+    a.sheet_shape = rp.sheet_shape;
+    a.model = model_in_use(rp, ex);
+    a.aniso = aniso_in_use(rp, ex);
     a.iod = iod;
     a.pairs = pairs_dev;
     a.n_pairs = n_pairs;
@@ -496,6 +542,74 @@ synthpix_status synthpix_seed(const synthpix_pair* pairs_host, const synthpix_pa
     return SP_OK;
 }
 
+synthpix_status synthpix_seed_shape(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev, int32_t n_pairs,
+                                    const synthpix_seed_params* sp_, float rho_lo, float rho_hi, uint64_t seed,
+                                    float* dy, float* rho, void* stream)
+{
+    int64_t span;
+    synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
+    if (st) return st;
+    if ((st = check_seed_params(sp_, pairs_host, n_pairs))) return st;
+    if (!(rho_lo >= -0.99f && rho_lo <= rho_hi && rho_hi <= 0.99f))
+        return fail(SP_ERR_INVALID_ARG, "rho range must satisfy -0.99 <= rho_lo <= rho_hi <= 0.99");
+    if (!dev_ptr_ok(dy) || !dev_ptr_ok(rho))
+        return fail(SP_ERR_INVALID_ARG, "dy, rho must be non-NULL, 4-byte aligned device pointers");
+    const hipError_t e = sp::launch_seed_shape(pairs_dev, n_pairs, span, *sp_, rho_lo, rho_hi, seed, dy, rho,
+                                               as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "seed_shape launch");
+    return SP_OK;
+}
+
+synthpix_status synthpix_flow_field(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev, int32_t n_pairs,
+                                    const float* flow, float* out, void* stream)
+{
+    int64_t span;
+    synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
+    if (st) return st;
+    if (n_pairs > 65535) return fail(SP_ERR_UNSUPPORTED, "at most 65535 pairs per call");
+    if (!flow || !aligned(flow, 8)) return fail(SP_ERR_INVALID_ARG, "flow must be a non-NULL 8-byte aligned pointer");
+    if (!out || !aligned(out, 8)) return fail(SP_ERR_INVALID_ARG, "out must be a non-NULL 8-byte aligned pointer");
+    int64_t max_px = 0;
+    for (int32_t p = 0; p < n_pairs; ++p) {
+        if (pairs_host[p].image_offset & 1) return fail(SP_ERR_INVALID_ARG, "pair %d: image_offset must be even", p);
+        max_px = std::max<int64_t>(max_px, (int64_t)pairs_host[p].H * pairs_host[p].W);
+    }
+    const hipError_t e = sp::launch_flow_field(pairs_dev, n_pairs, max_px, flow, out, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "flow field launch");
+    return SP_OK;
+}
+
+synthpix_status synthpix_histogram_workspace_size(int32_t n_pairs, int32_t bits, size_t* bytes_out)
+{
+    if (!bytes_out) return fail(SP_ERR_INVALID_ARG, "bytes_out must be non-NULL");
+    if (n_pairs <= 0 || n_pairs > 32767) return fail(SP_ERR_INVALID_ARG, "n_pairs must be in [1, 32767]");
+    if (bits < 1 || bits > 14) return fail(SP_ERR_UNSUPPORTED, "histogram adjustment needs bits in [1, 14]");
+    *bytes_out = sp::hist_workspace_bytes(n_pairs, bits);
+    return SP_OK;
+}
+
+synthpix_status synthpix_histogram_match(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                         int32_t n_pairs, int32_t bits, const uint32_t* target, void* images,
+                                         void* workspace, size_t ws_bytes, void* stream)
+{
+    int64_t span;
+    synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
+    if (st) return st;
+    size_t need = 0;
+    if ((st = synthpix_histogram_workspace_size(n_pairs, bits, &need))) return st;
+    if (!target || !aligned(target, 4)) return fail(SP_ERR_INVALID_ARG, "target must be a 4-byte aligned device pointer");
+    if (!images || !aligned(images, 2)) return fail(SP_ERR_INVALID_ARG, "images must be a 2-byte aligned device pointer");
+    if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    int64_t max_px = 0;
+    for (int32_t p = 0; p < n_pairs; ++p) max_px = std::max<int64_t>(max_px, (int64_t)pairs_host[p].H * pairs_host[p].W);
+    const hipError_t e = sp::launch_histogram_match(pairs_dev, n_pairs, max_px, bits, target,
+                                                    static_cast<uint16_t*>(images), static_cast<char*>(workspace),
+                                                    as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "histogram launch");
+    return SP_OK;
+}
+
 synthpix_status synthpix_advect_workspace_size(const synthpix_pair* pairs_host, int32_t n_pairs, size_t* bytes_out)
 {
     if (!bytes_out) return fail(SP_ERR_INVALID_ARG, "bytes_out must be non-NULL");
@@ -510,8 +624,8 @@ synthpix_status synthpix_advect_workspace_size(const synthpix_pair* pairs_host, 
 
 synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev, int32_t n_pairs,
                                 const float* flow, const synthpix_advect_params* ap, const float* x1,
-                                const float* y1, float* x2, float* y2, void* workspace, size_t ws_bytes,
-                                void* stream)
+                                const float* y1, float* x2, float* y2, const float* wflow, const float* z1,
+                                float* z2, void* workspace, size_t ws_bytes, void* stream)
 {
     int64_t span;
     synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
@@ -521,6 +635,17 @@ synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_
     if (!dev_ptr_ok(x1) || !dev_ptr_ok(y1) || !dev_ptr_ok(x2) || !dev_ptr_ok(y2))
         return fail(SP_ERR_INVALID_ARG, "x1, y1, x2, y2 must be non-NULL, 4-byte aligned device pointers");
     if (x1 == x2 || y1 == y2) return fail(SP_ERR_INVALID_ARG, "x2/y2 must not alias x1/y1");
+    if ((wflow == nullptr) != (z1 == nullptr) || (wflow == nullptr) != (z2 == nullptr))
+        return fail(SP_ERR_INVALID_ARG, "wflow, z1 and z2 must be all NULL or all set");
+    if (wflow) {
+        if (!dev_ptr_ok(wflow) || !dev_ptr_ok(z1) || !dev_ptr_ok(z2))
+            return fail(SP_ERR_INVALID_ARG, "wflow, z1, z2 must be 4-byte aligned device pointers");
+        if (z1 == z2) return fail(SP_ERR_INVALID_ARG, "z2 must not alias z1");
+        const hipError_t e = sp::launch_advect3(pairs_dev, n_pairs, span, flow, wflow, *ap, x1, y1, z1, x2, y2, z2,
+                                                as_stream(stream));
+        if (e != hipSuccess) return hip_fail(e, "advect launch");
+        return SP_OK;
+    }
     sp::AdvectOrder order{nullptr, nullptr};
     if (workspace) {
         if (!aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -540,8 +665,9 @@ synthpix_status synthpix_advect(const synthpix_pair* pairs_host, const synthpix_
 synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
                                      int32_t n_pairs, const synthpix_tiling* tiling, const float* x1,
                                      const float* y1, const float* x2, const float* y2, const float* z,
-                                     const float* d, const float* I0, const synthpix_render_params* rp,
-                                     void* images, void* workspace, size_t ws_bytes, void* stream)
+                                     const float* d, const float* I0, const synthpix_particle_extras* extras,
+                                     const synthpix_render_params* rp, void* images, void* workspace,
+                                     size_t ws_bytes, void* stream)
 {
     int64_t span;
     synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
@@ -561,11 +687,13 @@ synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synt
     if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < wl.total)
         return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, wl.total);
-    if (sp::render_lds_bytes(cfg) > 160 * 1024)
+    if ((st = check_extras(extras))) return st;
+    const bool aniso = aniso_in_use(*rp, extras);
+    if (sp::render_lds_bytes(cfg, aniso) > 160 * 1024)
         return fail(SP_ERR_UNSUPPORTED, "tiling needs %zu bytes of LDS per workgroup (max 163840)",
-                    sp::render_lds_bytes(cfg));
+                    sp::render_lds_bytes(cfg, aniso));
     const hipError_t e = enqueue_render(pairs_dev, n_pairs, cfg, T, wl, x1, y1, x2, y2, z, d, I0, *rp, images,
-                                        workspace, as_stream(stream));
+                                        workspace, as_stream(stream), nullptr, extras);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return SP_OK;
 }
@@ -585,6 +713,9 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     if ((st = check_render_params(rp))) return st;
     if (tiling && (st = check_tiling(*tiling))) return st;
     if (rp->bits != 0) return fail(SP_ERR_UNSUPPORTED, "the backward differentiates float images (bits must be 0)");
+    if (model_in_use(*rp, nullptr))
+        return fail(SP_ERR_UNSUPPORTED, "the backward differentiates the isotropic model (no frame-2 variation, no "
+                    "hiding, the Gaussian sheet)");
     if ((st = check_advect_params(&rp->advect))) return st;
     if (!flow || !aligned(flow, 8)) return fail(SP_ERR_INVALID_ARG, "flow must be a non-NULL 8-byte aligned pointer");
     if (!dev_ptr_ok(x1) || !dev_ptr_ok(y1) || !dev_ptr_ok(z) || !dev_ptr_ok(d) || !dev_ptr_ok(I0) ||
@@ -701,6 +832,7 @@ extern "C" synthpix_status synthpix_render_pair_noalloc(const synthpix_pair* pai
                                                         const synthpix_tiling* tiling, const float* x1,
                                                         const float* y1, const float* x2, const float* y2,
                                                         const float* z, const float* d, const float* I0,
+                                                        const synthpix_particle_extras* extras,
                                                         const synthpix_render_params* rp, void* images,
                                                         uint32_t* status_out, void* stream)
 {
@@ -726,16 +858,18 @@ extern "C" synthpix_status synthpix_render_pair_noalloc(const synthpix_pair* pai
                     "batch needs %zu bytes of workspace; the static scratch holds %zu (split the batch or use "
                     "synthpix_render_pair with a caller workspace)",
                     wl.total, (size_t)SYNTHPIX_STATIC_SCRATCH_BYTES);
-    if (sp::render_lds_bytes(cfg) > 160 * 1024)
+    if ((st = check_extras(extras))) return st;
+    const bool aniso = aniso_in_use(*rp, extras);
+    if (sp::render_lds_bytes(cfg, aniso) > 160 * 1024)
         return fail(SP_ERR_UNSUPPORTED, "tiling needs %zu bytes of LDS per workgroup (max 163840)",
-                    sp::render_lds_bytes(cfg));
+                    sp::render_lds_bytes(cfg, aniso));
     void* ws = nullptr;
     if ((st = scratch_of_current_device(&ws))) return st;
     // every part of the workspace the kernels read is written earlier in the same
     // call (the status words are cleared by the layout kernel), so the previous
     // call's contents need no clearing
     hipError_t e = enqueue_render(pairs_dev, n_pairs, cfg, T, wl, x1, y1, x2, y2, z, d, I0, *rp, images, ws,
-                                  as_stream(stream));
+                                  as_stream(stream), nullptr, extras);
     if (e == hipSuccess && status_out)
         e = hipMemcpyAsync(status_out, static_cast<char*>(ws) + wl.status, sizeof(uint32_t),
                            hipMemcpyDeviceToDevice, as_stream(stream));
@@ -872,6 +1006,9 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
     if ((st = check_advect_params(ap))) return st;
     if ((st = check_render_params(rp))) return st;
     if ((st = check_io(io, rp->bits))) return st;
+    if (model_in_use(*rp, nullptr))
+        return fail(SP_ERR_UNSUPPORTED, "plans run the isotropic model (no frame-2 variation, no hiding, the Gaussian "
+                    "sheet); use the eager calls for the full model");
     if (order_bytes(pairs_host, n_pairs) == 0) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     const synthpix_tiling t0 = default_tiling();
     {

@@ -130,16 +130,101 @@ prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_spa
     rec1[g] = make_float4(x2, y2, d2, Af);
 }
 
+// The full particle model's records (Eq. 1 with sigma_y and rho; frame-2
+// parameter variation, the sentence after Eq. 1; per-frame hiding, Section 2
+// "Considerations on the aggregation"; the Remark 1 sheet law; frame-2 z from
+// the out-of-plane motion).  Per particle and frame: the record (x, y, d or -1,
+// 2^24 A) and, in the anisotropic layout, (d_y, rho).  Frame-2 parameters are
+// frame 1's plus zero-mean Gaussians (Philox stream 2: Box-Muller of words 0, 1
+// and 2, 3, cosine then sine, for d, d_y, rho, I0), clipped to [0, d_max],
+// [-0.99, 0.99] and [0, inf) (masked particles stay dark); a particle is hidden
+// in frame f when word f of stream 7 is below hide_p.
+__device__ __forceinline__ float model_peak(float I0, float z, const RenderArgs& a)
+{
+    if (a.sheet_law == 0) return I0 * expneg((z * z) * (0.5f / (a.sheet_sigma * a.sheet_sigma)));
+    // Remark 1: exp(-(1/sqrt(2 pi)) v^s), v = z^2 (2 / DZ0^2); v^s = exp(s ln v)
+    const float v = (z * z) * (2.0f / (a.sheet_dz0 * a.sheet_dz0));
+    float pw = 0.0f;
+    if (v >= 0x1p-126f) {
+        const float e = a.sheet_shape * log_ra(v);
+        if (!(e < 80.0f)) return 0.0f;
+        pw = expneg(-e);
+    }
+    return I0 * expneg((float)0.39894228040143267794 * pw);
+}
+
+__global__ void __launch_bounds__(256)
+prep_records_model(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span, RenderArgs a, float d_max,
+                   float4* __restrict__ rec0, float4* __restrict__ rec1, float2* __restrict__ shp0,
+                   float2* __restrict__ shp1, uint32_t* __restrict__ status)
+{
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t g = g0 + threadIdx.x;
+    if (g >= n_span) return;
+    const int p = find_pair_from(pairs, n_pairs, g0, g);
+    const int64_t i = g - pairs[p].particle_offset;
+    if (i < 0 || i >= pairs[p].n_max) return;
+    const uint64_t pid = pairs[p].pair_id;
+    const float x1 = a.x[0][g], y1 = a.y[0][g], x2 = a.x[1][g], y2 = a.y[1][g];
+    const float z1 = a.z[g];
+    const float z2 = a.z2 ? a.z2[g] : z1;
+    const float d = a.d[g];
+    const float dy = a.dy ? a.dy[g] : d;
+    const float r = a.rho ? a.rho[g] : 0.0f;
+    const float I = a.I0[g];
+    float d2 = d, dy2 = dy, r2 = r, I2 = I;
+    if (a.jit_d > 0.0f || a.jit_rho > 0.0f || a.jit_I0 > 0.0f) {
+        const u32x4 w = draw((uint32_t)i, STREAM_JITTER, pid, a.seed);
+        const float R0 = __builtin_sqrtf(-2.0f * log_ra(u24_open0(w.a)));
+        const float R1 = __builtin_sqrtf(-2.0f * log_ra(u24_open0(w.c)));
+        const float2 t0 = cossin2pi_ra(u24(w.b));
+        const float2 t1 = cossin2pi_ra(u24(w.d));
+        if (a.jit_d > 0.0f) {
+            d2 = __builtin_fminf(__builtin_fmaxf(__builtin_fmaf(a.jit_d, R0 * t0.x, d), 0.0f), d_max);
+            dy2 = __builtin_fminf(__builtin_fmaxf(__builtin_fmaf(a.jit_d, R0 * t0.y, dy), 0.0f), d_max);
+        }
+        if (a.jit_rho > 0.0f) r2 = __builtin_fminf(__builtin_fmaxf(__builtin_fmaf(a.jit_rho, R1 * t1.x, r), -0.99f), 0.99f);
+        if (a.jit_I0 > 0.0f) I2 = I > 0.0f ? __builtin_fmaxf(__builtin_fmaf(a.jit_I0, R1 * t1.y, I), 0.0f) : 0.0f;
+    }
+    float I1 = I;
+    if (a.hide_p > 0.0f) {
+        const u32x4 w = draw((uint32_t)i, STREAM_HIDE, pid, a.seed);
+        if (u24(w.a) < a.hide_p) I1 = 0.0f;
+        if (u24(w.b) < a.hide_p) I2 = 0.0f;
+    }
+    const float dd[2] = {d, d2}, ddy[2] = {dy, dy2}, rr[2] = {r, r2}, II[2] = {I1, I2};
+    const float xx[2] = {x1, x2}, yy[2] = {y1, y2}, zz[2] = {z1, z2};
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        float de = dd[f];
+        if (!(II[f] > 0.0f) || !(dd[f] > 0.0f) || !(ddy[f] > 0.0f) || !__builtin_isfinite(xx[f]) ||
+            !__builtin_isfinite(yy[f]))
+            de = -1.0f;
+        if (de > 0.0f && !(dd[f] <= d_max && ddy[f] <= d_max)) {
+            atomicOr(status, SP_STATUS_D_ABOVE_MAX);
+            de = -1.0f;
+        }
+        if (de > 0.0f && !(__builtin_fabsf(rr[f]) <= 0.99f)) {
+            atomicOr(status, SP_STATUS_BAD_SHAPE);
+            de = -1.0f;
+        }
+        const float4 rc = make_float4(xx[f], yy[f], de, fixed_peak(model_peak(II[f], zz[f], a)));
+        (f ? rec1 : rec0)[g] = rc;
+        if (a.aniso) (f ? shp1 : shp0)[g] = make_float2(ddy[f], rr[f]);
+    }
+}
+
 // ------------------------------------------------------------------ membership
 
 // ------------------------------------------------------------------ count / scatter
 
-template <bool SCATTER>
+template <bool SCATTER, bool ANISO>
 __global__ void __launch_bounds__(256)
 bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
-         const float4* __restrict__ rec0, const float4* __restrict__ rec1, RenderConfig cfg,
-         uint32_t* __restrict__ hist, const int64_t* __restrict__ tile_offset, int64_t tiles_total,
-         int32_t* __restrict__ entries, unsigned n_chunks_total)
+         const float4* __restrict__ rec0, const float4* __restrict__ rec1, const float2* __restrict__ shp0,
+         const float2* __restrict__ shp1, RenderConfig cfg, uint32_t* __restrict__ hist,
+         const int64_t* __restrict__ tile_offset, int64_t tiles_total, int32_t* __restrict__ entries,
+         unsigned n_chunks_total)
 {
     extern __shared__ uint32_t lh[];
     const int f = blockIdx.y;
@@ -158,21 +243,25 @@ bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__
     __syncthreads();
     const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
     const float4* __restrict__ rec = f ? rec1 : rec0;
+    const float2* __restrict__ shp = f ? shp1 : shp0;
     // BIN_ILP particles per thread and step: their record loads and LDS atomic
     // round trips overlap
     constexpr int BIN_ILP = 4;
     for (int i0 = chunk * cfg.chunk + threadIdx.x; i0 < i_end; i0 += BIN_ILP * blockDim.x) {
         float4 r[BIN_ILP];
+        float ry[BIN_ILP];
 #pragma unroll
         for (int q = 0; q < BIN_ILP; ++q) {
             const int i = i0 + q * blockDim.x;
             r[q] = i < i_end ? rec[P.particle_offset + i] : make_float4(0.0f, 0.0f, -1.0f, 0.0f);
+            ry[q] = r[q].z;
+            if (ANISO && i < i_end) ry[q] = shp[P.particle_offset + i].x;
         }
 #pragma unroll
         for (int q = 0; q < BIN_ILP; ++q) {
             const int i = i0 + q * blockDim.x;
             int tx0, tx1, ty0, ty1;
-            if (!tile_rect(r[q], P.H, P.W, cfg, PL.ntx, PL.nty, tx0, tx1, ty0, ty1)) continue;
+            if (!tile_rect(r[q], ry[q], P.H, P.W, cfg, PL.ntx, PL.nty, tx0, tx1, ty0, ty1)) continue;
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     const uint32_t slot = atomicAdd(&lh[ty * PL.ntx + tx], 1u);
@@ -321,14 +410,15 @@ struct RenderLds {
     size_t bytes;
 };
 
-__host__ __device__ inline RenderLds render_lds_shape(int tw, int th, int apron, int cap, int wm4)
+__host__ __device__ inline RenderLds render_lds_shape(int tw, int th, int apron, int cap, int wm4, bool aniso)
 {
     RenderLds L;
     const int RW = tw + 2 * apron, RH = th + 2 * apron;
     L.acc_words = (RH * RW + 8 + 3) & ~3;
     L.tables = cap * wm4;
-    size_t work = (size_t)cap * 16                                  // staged (x, y, kappa, Af)
+    size_t work = (size_t)cap * 16                                  // staged (x, y, kappa_x, Af)
                 + (size_t)cap * 4                                   // staged patch box
+                + (aniso ? (size_t)cap * 8 : 0)                     // staged (kappa_y, kappa_xy)
                 + (size_t)L.tables * sizeof(float)                  // column factors gx
                 + (size_t)L.tables * sizeof(uint16_t)               // work items
                 + 64;                                                // scan scratch
@@ -337,9 +427,9 @@ __host__ __device__ inline RenderLds render_lds_shape(int tw, int th, int apron,
     return L;
 }
 
-__host__ __device__ inline RenderLds render_lds(const RenderConfig& c)
+__host__ __device__ inline RenderLds render_lds(const RenderConfig& c, bool aniso)
 {
-    return render_lds_shape(c.tile_w, c.tile_h, c.apron, c.cap, c.wm4);
+    return render_lds_shape(c.tile_w, c.tile_h, c.apron, c.cap, c.wm4, aniso);
 }
 
 // Exclusive scan of one counter over a workgroup of 256 threads (4 waves of
@@ -384,11 +474,17 @@ __device__ __forceinline__ uint32_t pack_box(int c0, int w, int r0, int h)
 }
 
 // Tile renderer, templated on the tile shape and the blur radius (tile-local
-// index arithmetic becomes shifts, blur loops unroll).
-template <int TW, int TH, int B>
+// index arithmetic becomes shifts, blur loops unroll).  ANISO: the full model's
+// particle images (Eq. 1 with sigma_y = d_y / 4 and rho, from the shape
+// records): kappa_x = 8 / (om d^2), kappa_y = 8 / (om d_y^2), om = 1 - rho^2;
+// rho = 0 keeps the separable factors (with kappa_y for the rows), rho != 0
+// evaluates exp(-q) per pixel, q = dx (kappa_x dx + kappa_xy dy) + kappa_y dy^2,
+// kappa_xy = -16 rho / (om d d_y); the patch is |dx| <= 1.5 d, |dy| <= 1.5 d_y.
+template <int TW, int TH, int B, bool ANISO>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
-            const float4* __restrict__ rec0, const float4* __restrict__ rec1, EpilogueArgs a, int cap, int wm4,
+            const float4* __restrict__ rec0, const float4* __restrict__ rec1, const float2* __restrict__ shp0,
+            const float2* __restrict__ shp1, EpilogueArgs a, int cap, int wm4,
             const uint32_t* __restrict__ tile_count, const int64_t* __restrict__ tile_offset,
             const int32_t* __restrict__ entries, int64_t tiles_total, uint32_t* __restrict__ status)
 {
@@ -400,7 +496,7 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
 #pragma unroll
     for (int q = 0; q <= 2 * B; ++q) wb[q] = a.blur_w[q];
     extern __shared__ __align__(16) unsigned char smem[];
-    const RenderLds lay = render_lds_shape(TW, TH, B, cap, wm4);
+    const RenderLds lay = render_lds_shape(TW, TH, B, cap, wm4, ANISO);
     constexpr int b = B;
     constexpr int RW = TW + 2 * B;
     constexpr int RH = TH + 2 * B;
@@ -408,7 +504,8 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
     float4* stg = reinterpret_cast<float4*>(acc + lay.acc_words);       // (x, y, kappa, Af)
     uint32_t* box = reinterpret_cast<uint32_t*>(stg + cap);              // c0 | w | r0 | h bytes
-    float* gx = reinterpret_cast<float*>(box + cap);
+    float2* stg2 = reinterpret_cast<float2*>(box + cap);                // (kappa_y, kappa_xy), ANISO only
+    float* gx = reinterpret_cast<float*>(ANISO ? reinterpret_cast<uint32_t*>(stg2 + cap) : box + cap);
     uint16_t* items = reinterpret_cast<uint16_t*>(gx + lay.tables);     // tables entries
     int* s_wave = reinterpret_cast<int*>(items + lay.tables);
     float* tmp = reinterpret_cast<float*>(stg);   // blur scratch, reuses the particle tables
@@ -442,6 +539,7 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     const int cnt = (int)tile_count[item];
     const int64_t off = tile_offset[item];
     const float4* __restrict__ rec = f ? rec1 : rec0;
+    const float2* __restrict__ shp = f ? shp1 : shp0;
 
     for (int k = threadIdx.x; k < (lay.acc_words >> 2); k += 256)
         reinterpret_cast<uint4*>(acc)[k] = make_uint4(0u, 0u, 0u, 0u);
@@ -450,19 +548,29 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     // the record of a thread's particle in the next pass is loaded one pass ahead,
     // so its two dependent loads overlap the current pass's factor and splat work
     float4 next = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
-    if ((int)threadIdx.x < min(cap, cnt)) next = rec[p_off + entries[off + threadIdx.x]];
+    float2 next_sh = make_float2(0.0f, 0.0f);
+    if ((int)threadIdx.x < min(cap, cnt)) {
+        const int e = entries[off + threadIdx.x];
+        next = rec[p_off + e];
+        if (ANISO) next_sh = shp[p_off + e];
+    }
     for (int base = 0; base < cnt; base += cap) {
         const int n = min(cap, cnt - base);
         const float4 r = next;
-        if ((int)threadIdx.x < cap && base + cap + (int)threadIdx.x < cnt)
-            next = rec[p_off + entries[off + base + cap + threadIdx.x]];
+        const float2 rs = next_sh;
+        if ((int)threadIdx.x < cap && base + cap + (int)threadIdx.x < cnt) {
+            const int e = entries[off + base + cap + threadIdx.x];
+            next = rec[p_off + e];
+            if (ANISO) next_sh = shp[p_off + e];
+        }
         __syncthreads();
         // stage: one particle per thread
         int w = 0, h = 0, c0 = 0, r0 = 0;
         if ((int)threadIdx.x < n) {
             const float R = 1.5f * r.z;
+            const float Ry = ANISO ? 1.5f * rs.x : R;
             int a0, a1, b0, b1;
-            if (support_range(r.x, R, pW, a0, a1) && support_range(r.y, R, pH, b0, b1)) {
+            if (support_range(r.x, R, pW, a0, a1) && support_range(r.y, Ry, pH, b0, b1)) {
                 a0 = max(a0, rx0);
                 a1 = min(a1, rx0 + RW - 1);
                 b0 = max(b0, ry0);
@@ -479,7 +587,14 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
                     r0 = b0 - ry0;
                 }
             }
-            stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (r.z * r.z), r.w);
+            if (ANISO) {
+                const float om = __builtin_fmaf(-rs.y, rs.y, 1.0f);
+                stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (om * (r.z * r.z)), r.w);
+                stg2[threadIdx.x] = make_float2(8.0f / (om * (rs.x * rs.x)),
+                                                rs.y == 0.0f ? 0.0f : (-16.0f * rs.y) / (om * (r.z * rs.x)));
+            } else {
+                stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (r.z * r.z), r.w);
+            }
             box[threadIdx.x] = pack_box(c0, w, r0, h);
             if (w > 0) {
                 const unsigned long long pk = (unsigned long long)r.w;
@@ -507,7 +622,7 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             const int it = items[i];
             const int k = it >> 8, j = it & 255;
             const uint32_t bx = box[k];
-            if (j < (int)((bx >> 8) & 255u)) {
+            if (j < (int)((bx >> 8) & 255u) && (!ANISO || stg2[k].y == 0.0f)) {
                 const float4 sf = stg[k];
                 const float dx = ((float)(rx0 + (int)(bx & 255u) + j) + 0.5f) - sf.x;
                 gx[k * WM + j] = expneg_lt80(sf.z * (dx * dx));
@@ -524,9 +639,22 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             const int pc0 = (int)(bx & 255u), pw = (int)((bx >> 8) & 255u), pr0 = (int)((bx >> 16) & 255u);
             const float4 sf = stg[k];
             const float dy = ((float)(ry0 + pr0 + j) + 0.5f) - sf.y;
-            const float rv = sf.w * expneg_lt80(sf.z * (dy * dy));
-            const float* gk = gx + k * WM;
             uint32_t* dst = acc + (pr0 + j) * RW + pc0;
+            if (ANISO) {
+                const float2 s2 = stg2[k];
+                if (s2.y != 0.0f) {
+                    // rho != 0: one exponential per pixel of the row
+                    const float ra = s2.y * dy, rb = s2.x * (dy * dy);
+                    for (int c = 0; c < pw; ++c) {
+                        const float dx = ((float)(rx0 + pc0 + c) + 0.5f) - sf.x;
+                        const float q = __builtin_fmaxf(__builtin_fmaf(dx, __builtin_fmaf(sf.z, dx, ra), rb), 0.0f);
+                        atomicAdd(dst + c, (uint32_t)(sf.w * expneg(q)));
+                    }
+                    continue;
+                }
+            }
+            const float rv = sf.w * expneg_lt80((ANISO ? stg2[k].x : sf.z) * (dy * dy));
+            const float* gk = gx + k * WM;
             for (int cs0 = 0; cs0 < pw; cs0 += 8) {
                 const float4 g0 = *reinterpret_cast<const float4*>(gk + cs0);
                 atomicAdd(dst + cs0 + 0, (uint32_t)(rv * g0.x));
@@ -664,7 +792,7 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     }
 }
 
-size_t render_lds_bytes(const RenderConfig& cfg) { return render_lds(cfg).bytes; }
+size_t render_lds_bytes(const RenderConfig& cfg, bool aniso) { return render_lds(cfg, aniso).bytes; }
 
 // Tile shapes with a compiled renderer (width x height).
 bool render_shape_supported(int tw, int th)
@@ -690,9 +818,9 @@ static void launch_scans(const PairLayout* L, int n_pairs, uint32_t* hist, uint3
 
 template <int TW, int TH>
 static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const RenderArgs& a, const RenderConfig& cfg,
-                                const PairLayout* L, const float4* r0, const float4* r1, const uint32_t* tile_count,
-                                const int64_t* tile_offset, const int32_t* entries, int64_t tiles,
-                                uint32_t* status)
+                                const PairLayout* L, const float4* r0, const float4* r1, const float2* h0,
+                                const float2* h1, const uint32_t* tile_count, const int64_t* tile_offset,
+                                const int32_t* entries, int64_t tiles, uint32_t* status)
 {
     EpilogueArgs ea;
     ea.images = a.images;
@@ -703,8 +831,14 @@ static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const Rend
     for (int q = 0; q < 7; ++q) ea.blur_w[q] = a.blur_w[q];
 #define SP_B(B_)                                                                                                 \
     case B_:                                                                                                     \
-        hipLaunchKernelGGL((render_tile<TW, TH, B_>), grid, dim3(256), lds, s, a.pairs, L, a.n_pairs, r0, r1,    \
-                           ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles, status);              \
+        if (a.aniso)                                                                                             \
+            hipLaunchKernelGGL((render_tile<TW, TH, B_, true>), grid, dim3(256), lds, s, a.pairs, L, a.n_pairs,  \
+                               r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles,    \
+                               status);                                                                          \
+        else                                                                                                     \
+            hipLaunchKernelGGL((render_tile<TW, TH, B_, false>), grid, dim3(256), lds, s, a.pairs, L, a.n_pairs, \
+                               r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles,    \
+                               status);                                                                          \
         break;
     switch (cfg.apron) { SP_B(0) SP_B(1) SP_B(2) SP_B(3) default: break; }
 #undef SP_B
@@ -721,6 +855,8 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
     int32_t* entries = reinterpret_cast<int32_t*>(ws + wl.entries);
     float4* rec0 = reinterpret_cast<float4*>(ws + wl.records);
     float4* rec1 = rec0 + tot.n_span;
+    float2* shp0 = reinterpret_cast<float2*>(ws + wl.shapes);
+    float2* shp1 = shp0 + tot.n_span;
 
     {
         TimedScope ts("bin_layout", s);
@@ -728,14 +864,23 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
     }
     if (tot.n_span > 0) {
         TimedScope ts("prep", s);
-        hipLaunchKernelGGL(prep_records, dim3((unsigned)((tot.n_span + 255) / 256)), dim3(256), 0, s, a.pairs,
-                           a.n_pairs, tot.n_span, a, cfg.d_max, rec0, rec1, status);
+        if (a.model)
+            hipLaunchKernelGGL(prep_records_model, dim3((unsigned)((tot.n_span + 255) / 256)), dim3(256), 0, s,
+                               a.pairs, a.n_pairs, tot.n_span, a, cfg.d_max, rec0, rec1, shp0, shp1, status);
+        else
+            hipLaunchKernelGGL(prep_records, dim3((unsigned)((tot.n_span + 255) / 256)), dim3(256), 0, s, a.pairs,
+                               a.n_pairs, tot.n_span, a, cfg.d_max, rec0, rec1, status);
     }
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
+    const dim3 bgrid((unsigned)tot.chunks, 2);
     if (tot.chunks > 0) {
         TimedScope ts("bin_count", s);
-        hipLaunchKernelGGL(bin_pass<false>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s, a.pairs, L,
-                           a.n_pairs, rec0, rec1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
+        if (a.aniso)
+            hipLaunchKernelGGL((bin_pass<false, true>), bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, rec0,
+                               rec1, shp0, shp1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
+        else
+            hipLaunchKernelGGL((bin_pass<false, false>), bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, rec0,
+                               rec1, shp0, shp1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
     }
     if (tot.tiles > 0) {
         TimedScope ts("bin_scan", s);
@@ -743,8 +888,12 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
     }
     if (tot.chunks > 0) {
         TimedScope ts("bin_scatter", s);
-        hipLaunchKernelGGL(bin_pass<true>, dim3((unsigned)tot.chunks, 2), dim3(256), hist_lds, s, a.pairs, L,
-                           a.n_pairs, rec0, rec1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
+        if (a.aniso)
+            hipLaunchKernelGGL((bin_pass<true, true>), bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, rec0,
+                               rec1, shp0, shp1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
+        else
+            hipLaunchKernelGGL((bin_pass<true, false>), bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, rec0,
+                               rec1, shp0, shp1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
     }
     return hipGetLastError();
 }
@@ -759,16 +908,18 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
     int32_t* entries = reinterpret_cast<int32_t*>(ws + wl.entries);
     float4* rec0 = reinterpret_cast<float4*>(ws + wl.records);
     float4* rec1 = rec0 + tot.n_span;
+    float2* shp0 = reinterpret_cast<float2*>(ws + wl.shapes);
+    float2* shp1 = shp0 + tot.n_span;
     const hipError_t e = launch_bins(a, cfg, tot, ws, wl, s);
     if (e != hipSuccess) return e;
     if (tot.tiles > 0) {
         TimedScope ts("render_tile", s);
-        const size_t lds = render_lds_bytes(cfg);
+        const size_t lds = render_lds_bytes(cfg, a.aniso);
         const dim3 grid((unsigned)(2 * tot.tiles));
 #define SP_SHAPE(W_, H_)                                                                                        \
     if (cfg.tile_w == W_ && cfg.tile_h == H_)                                                                   \
-        launch_render_shape<W_, H_>(grid, lds, s, a, cfg, L, rec0, rec1, tile_count, tile_offset, entries,      \
-                                    tot.tiles, status);                                                         \
+        launch_render_shape<W_, H_>(grid, lds, s, a, cfg, L, rec0, rec1, shp0, shp1, tile_count, tile_offset,   \
+                                    entries, tot.tiles, status);                                                \
     else
         SP_SHAPE(8, 8) SP_SHAPE(16, 16) SP_SHAPE(32, 16) SP_SHAPE(32, 32) SP_SHAPE(64, 16) SP_SHAPE(64, 32)
         SP_SHAPE(64, 64) SP_SHAPE(128, 32)

@@ -56,7 +56,10 @@ __device__ __forceinline__ u32x4 draw(uint32_t index, uint32_t stream, uint64_t 
                   (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
-enum : uint32_t { STREAM_GEOM = 0, STREAM_PHOTO = 1, STREAM_NOISE0 = 3, STREAM_PAIR = 5 };
+enum : uint32_t {
+    STREAM_GEOM = 0, STREAM_PHOTO = 1, STREAM_JITTER = 2, STREAM_NOISE0 = 3, STREAM_PAIR = 5, STREAM_SHAPE = 6,
+    STREAM_HIDE = 7
+};
 
 __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
 __device__ __forceinline__ float u24_open0(uint32_t w) { return (float)((w >> 8) + 1u) * 0x1p-24f; }
@@ -134,6 +137,32 @@ __device__ __forceinline__ float cos2pi_ra(float u)
     case 1: return -s;
     case 2: return -c;
     default: return s;
+    }
+}
+
+// cos(2 pi u) and sin(2 pi u) of one reduction (the same polynomials as cos2pi_ra;
+// sin(k pi/2 + x) picks sin x, cos x, -sin x, -cos x by quadrant).
+__device__ __forceinline__ float2 cossin2pi_ra(float u)
+{
+    const float t = u * 4.0f;
+    const float kf = __builtin_rintf(t);
+    const float f = t - kf;
+    const float x = f * (float)1.57079632679489661923;
+    const float x2 = x * x;
+    float c = __builtin_fmaf(x2, (float)(1.0 / 40320.0), (float)(-1.0 / 720.0));
+    c = __builtin_fmaf(x2, c, (float)(1.0 / 24.0));
+    c = __builtin_fmaf(x2, c, -0.5f);
+    c = __builtin_fmaf(x2, c, 1.0f);
+    float s = __builtin_fmaf(x2, (float)(1.0 / 362880.0), (float)(-1.0 / 5040.0));
+    s = __builtin_fmaf(x2, s, (float)(1.0 / 120.0));
+    s = __builtin_fmaf(x2, s, (float)(-1.0 / 6.0));
+    s = __builtin_fmaf(x2, s, 1.0f);
+    s = x * s;
+    switch (((int)kf) & 3) {
+    case 0: return make_float2(c, s);
+    case 1: return make_float2(-s, c);
+    case 2: return make_float2(-c, -s);
+    default: return make_float2(s, -c);
     }
 }
 

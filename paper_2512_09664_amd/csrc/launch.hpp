@@ -63,14 +63,15 @@ struct RenderConfig {
 // Totals of a batch (host side).
 // Tile rectangle touched by one particle record: its support, clipped to the
 // image, grown by the blur apron.  False when the particle adds nothing.
-__device__ __forceinline__ bool tile_rect(const float4 r, int H, int W, const RenderConfig& cfg, int ntx, int nty,
-                                          int& tx0, int& tx1, int& ty0, int& ty1)
+// dy: the particle's second diameter (its patch half-height is 1.5 dy); the
+// isotropic path passes the record's own diameter.
+__device__ __forceinline__ bool tile_rect(const float4 r, float dy, int H, int W, const RenderConfig& cfg, int ntx,
+                                          int nty, int& tx0, int& tx1, int& ty0, int& ty1)
 {
     if (!(r.z > 0.0f)) return false;
-    const float R = 1.5f * r.z;
     int c0, c1, r0, r1;
-    if (!support_range(r.x, R, W, c0, c1)) return false;
-    if (!support_range(r.y, R, H, r0, r1)) return false;
+    if (!support_range(r.x, 1.5f * r.z, W, c0, c1)) return false;
+    if (!support_range(r.y, 1.5f * dy, H, r0, r1)) return false;
     const int b = cfg.apron;
     tx0 = c0 - b < 0 ? 0 : (c0 - b) >> cfg.log_tw;
     ty0 = r0 - b < 0 ? 0 : (r0 - b) >> cfg.log_th;
@@ -99,6 +100,7 @@ struct WorkspaceLayout {
     size_t hist;            // uint32 [hist]
     size_t entries;         // int32  [entries]
     size_t records;         // float4 [2 * n_span] per-frame particle records
+    size_t shapes;          // float2 [2 * n_span] per-frame (d_y, rho) of the anisotropic model
     size_t total;
 };
 
@@ -140,6 +142,16 @@ hipError_t launch_advect(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_
                          float* y2, hipStream_t s, AdvectOrder order = AdvectOrder{nullptr, nullptr},
                          const synthpix_batch_io* iod = nullptr);
 
+// Second diameter and correlation per candidate particle (Philox stream 6).
+hipError_t launch_seed_shape(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
+                             const synthpix_seed_params& prm, float rho_lo, float rho_hi, uint64_t seed, float* dy,
+                             float* rho, hipStream_t s);
+
+// Three-dimensional motion: (x2, y2, z2) under the (u, v) grid and the w grid.
+hipError_t launch_advect3(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
+                          const float* wflow, const synthpix_advect_params& ap, const float* x1, const float* y1,
+                          const float* z1, float* x2, float* y2, float* z2, hipStream_t s);
+
 struct RenderArgs {
     const synthpix_pair* pairs;
     int n_pairs;
@@ -155,6 +167,16 @@ struct RenderArgs {
     uint64_t seed;
     float blur_w[7];
     const synthpix_batch_io* iod;   // captured plans: buffers, key and pair-id offset (else null)
+    // the full particle model (all zero / null: the isotropic Gaussian-sheet path)
+    const float* dy;                // second diameter per particle (null: d)
+    const float* rho;               // correlation per particle (null: 0)
+    const float* z2;                // frame-2 out-of-plane position (null: z)
+    float hide_p;                   // per-frame hiding probability
+    float jit_d, jit_rho, jit_I0;   // std of the frame-2 parameter changes
+    int sheet_law;                  // 0 Gaussian sheet, 1 Remark 1
+    float sheet_dz0, sheet_shape;   // Remark 1: thickness and shape factor
+    bool model;                     // any of the above in use (the model's prep kernel runs)
+    bool aniso;                     // shape records in use (d_y != d or rho != 0 possible)
 };
 
 // What the tile renderer's epilogue needs (kept small: kernel arguments live in SGPRs).
@@ -172,7 +194,7 @@ struct EpilogueArgs {
 hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot, char* ws,
                        const WorkspaceLayout& wl, hipStream_t s);
 
-size_t render_lds_bytes(const RenderConfig& cfg);
+size_t render_lds_bytes(const RenderConfig& cfg, bool aniso = false);
 bool render_shape_supported(int tile_w, int tile_h);
 
 hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const BatchTotals& tot,
@@ -227,6 +249,15 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
 // Peak-rate probes (store, copy, fma, trans, mul64, store_nt = kinds 0..5); *work gets
 // the launch's bytes or wave64 instructions.
 hipError_t launch_probe(int kind, void* buf, size_t bytes, int iters, hipStream_t s, double* work);
+
+// Ground-truth flow fields: each pair's grid sampled at its pixel centres.
+hipError_t launch_flow_field(const synthpix_pair* pairs_dev, int n_pairs, int64_t max_px, const float* flow, float* out,
+                             hipStream_t s);
+
+// Histogram adjustment of uint16 images (bits 1..14): workspace bytes and launch.
+size_t hist_workspace_bytes(int n_pairs, int bits);
+hipError_t launch_histogram_match(const synthpix_pair* pairs_dev, int n_pairs, int64_t max_pixels, int bits,
+                                  const uint32_t* target, uint16_t* images, char* ws, hipStream_t s);
 
 // Compute units of the current device (cached per device).
 int device_cu_count();

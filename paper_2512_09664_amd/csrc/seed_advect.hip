@@ -291,6 +291,159 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
     }
 }
 
+// Second diameter d_y and correlation rho of Eq. 1 per candidate particle
+// (anisotropic particle images; the sentence after Eq. 1 draws every shape
+// parameter per particle): d_y from the seed's diameter distribution, rho
+// uniform in [rho_lo, rho_hi]; Philox stream 6 (word 0: uniform d_y; words 1, 2:
+// Box-Muller of a normal d_y; word 3: rho).
+__global__ void __launch_bounds__(256)
+seed_shape_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span, synthpix_seed_params prm,
+                  float rho_lo, float rho_hi, uint64_t seed, float* __restrict__ dy, float* __restrict__ rho)
+{
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t g = g0 + threadIdx.x;
+    if (g >= n_span) return;
+    const int p = find_pair_from(pairs, n_pairs, g0, g);
+    const synthpix_pair P = pairs[p];
+    const int64_t i64 = g - P.particle_offset;
+    if (i64 < 0 || i64 >= P.n_max) return;
+    const u32x4 w = draw((uint32_t)i64, STREAM_SHAPE, P.pair_id, seed);
+    float v;
+    if (prm.d_dist == SP_DIST_UNIFORM) {
+        v = __builtin_fmaf(prm.d_b - prm.d_a, u24(w.a), prm.d_a);
+    } else {
+        const float R = __builtin_sqrtf(-2.0f * log_ra(u24_open0(w.b)));
+        v = __builtin_fmaf(prm.d_b, R * cos2pi_ra(u24(w.c)), prm.d_a);
+        v = __builtin_fminf(__builtin_fmaxf(v, prm.d_lo), prm.d_hi);
+    }
+    dy[g] = v;
+    rho[g] = __builtin_fmaf(rho_hi - rho_lo, u24(w.d), rho_lo);
+}
+
+// Bilinear, clamped sample of a pair's scalar grid (the out-of-plane velocity w,
+// one float per node, registered like the (u, v) grid).
+__device__ __forceinline__ float sample_scalar(const float* __restrict__ G, const FlowView& fv, float px, float py)
+{
+    float gx = px * fv.sx - 0.5f;
+    float gy = py * fv.sy - 0.5f;
+    gx = __builtin_fminf(__builtin_fmaxf(gx, 0.0f), (float)(fv.Gw - 1));
+    gy = __builtin_fminf(__builtin_fmaxf(gy, 0.0f), (float)(fv.Gh - 1));
+    int j0 = (int)__builtin_floorf(gx);
+    int i0 = (int)__builtin_floorf(gy);
+    j0 = j0 > fv.Gw - 2 ? fv.Gw - 2 : j0;
+    i0 = i0 > fv.Gh - 2 ? fv.Gh - 2 : i0;
+    const float fx = gx - (float)j0;
+    const float fy = gy - (float)i0;
+    const float* a = G + (size_t)i0 * fv.Gw + j0;
+    const float* c = a + fv.Gw;
+    const float top = __builtin_fmaf(fx, a[1] - a[0], a[0]);
+    const float bot = __builtin_fmaf(fx, c[1] - c[0], c[0]);
+    return __builtin_fmaf(fy, bot - top, top);
+}
+
+// Three-dimensional motion (Remark 1's particles in 3-D space under a 3-D
+// flow): the in-plane trajectory of advect_kernel, and z integrating the
+// out-of-plane velocity w(x, y) with the same stages (Euler z = fma(h, w, z);
+// RK4 z = fma(h, (((w1 + 2 w2) + 2 w3) + w4) / 6, z), w_k at the k-th stage
+// position).  One particle per thread in index order.
+__global__ void __launch_bounds__(256)
+advect3_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span, const float* __restrict__ flow,
+               const float* __restrict__ wflow, synthpix_advect_params ap, const float* __restrict__ x1,
+               const float* __restrict__ y1, const float* __restrict__ z1, float* __restrict__ x2,
+               float* __restrict__ y2, float* __restrict__ z2)
+{
+    const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256;
+    const int64_t g = g0 + threadIdx.x;
+    if (g >= n_span) return;
+    const int p = find_pair_from(pairs, n_pairs, g0, g);
+    const synthpix_pair P = pairs[p];
+    const int64_t i = g - P.particle_offset;
+    if (i < 0 || i >= P.n_max) return;
+    const FlowView fv = flow_view(P, flow);
+    const float* W = wflow + P.flow_offset / 2;
+    float px = x1[g], py = y1[g], pz = z1[g];
+    const float h = ap.dt / (float)ap.substeps;
+    const float hh = h * 0.5f;
+    for (int s = 0; s < ap.substeps; ++s) {
+        if (ap.integrator == SP_EULER) {
+            const float2 u = sample_flow(fv, px, py);
+            const float w = sample_scalar(W, fv, px, py);
+            px = __builtin_fmaf(h, u.x, px);
+            py = __builtin_fmaf(h, u.y, py);
+            pz = __builtin_fmaf(h, w, pz);
+        } else {
+            const float2 k1 = sample_flow(fv, px, py);
+            const float w1 = sample_scalar(W, fv, px, py);
+            const float ax = __builtin_fmaf(hh, k1.x, px), ay = __builtin_fmaf(hh, k1.y, py);
+            const float2 k2 = sample_flow(fv, ax, ay);
+            const float w2 = sample_scalar(W, fv, ax, ay);
+            const float bx = __builtin_fmaf(hh, k2.x, px), by = __builtin_fmaf(hh, k2.y, py);
+            const float2 k3 = sample_flow(fv, bx, by);
+            const float w3 = sample_scalar(W, fv, bx, by);
+            const float cx = __builtin_fmaf(h, k3.x, px), cy = __builtin_fmaf(h, k3.y, py);
+            const float2 k4 = sample_flow(fv, cx, cy);
+            const float w4 = sample_scalar(W, fv, cx, cy);
+            const float su = ((k1.x + 2.0f * k2.x) + 2.0f * k3.x) + k4.x;
+            const float sv = ((k1.y + 2.0f * k2.y) + 2.0f * k3.y) + k4.y;
+            const float sw = ((w1 + 2.0f * w2) + 2.0f * w3) + w4;
+            px = __builtin_fmaf(h, su / 6.0f, px);
+            py = __builtin_fmaf(h, sv / 6.0f, py);
+            pz = __builtin_fmaf(h, sw / 6.0f, pz);
+        }
+    }
+    x2[g] = px;
+    y2[g] = py;
+    z2[g] = pz;
+}
+
+// Ground-truth flow of each pair (the sampler's flow_fields): the pair's (u, v)
+// grid sampled bilinearly at every pixel centre, (c + 1/2, r + 1/2), exactly
+// as the advection samples it; written as [H][W][2] floats at the pair's image
+// offset (2 H W floats, the extent of its two float frames).  One thread per
+// pixel; grid y = pair.
+__global__ void __launch_bounds__(256)
+flow_field_kernel(const synthpix_pair* __restrict__ pairs, const float* __restrict__ flow, float* __restrict__ out)
+{
+    const synthpix_pair P = pairs[blockIdx.y];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)P.H * P.W) return;
+    const int r = (int)(k / P.W), c = (int)(k - (int64_t)r * P.W);
+    const float2 u = sample_flow(flow_view(P, flow), (float)c + 0.5f, (float)r + 0.5f);
+    *reinterpret_cast<float2*>(out + P.image_offset + 2 * k) = u;
+}
+
+hipError_t launch_flow_field(const synthpix_pair* pairs_dev, int n_pairs, int64_t max_px, const float* flow, float* out,
+                             hipStream_t s)
+{
+    if (max_px <= 0) return hipSuccess;
+    TimedScope ts("flow_field", s);
+    hipLaunchKernelGGL(flow_field_kernel, dim3((unsigned)((max_px + 255) / 256), (unsigned)n_pairs), dim3(256), 0, s,
+                       pairs_dev, flow, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_shape(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
+                             const synthpix_seed_params& prm, float rho_lo, float rho_hi, uint64_t seed, float* dy,
+                             float* rho, hipStream_t s)
+{
+    if (n_span <= 0) return hipSuccess;
+    TimedScope ts("seed_shape", s);
+    hipLaunchKernelGGL(seed_shape_kernel, dim3((unsigned)((n_span + 255) / 256)), dim3(256), 0, s, pairs_dev, n_pairs,
+                       n_span, prm, rho_lo, rho_hi, seed, dy, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect3(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span, const float* flow,
+                          const float* wflow, const synthpix_advect_params& ap, const float* x1, const float* y1,
+                          const float* z1, float* x2, float* y2, float* z2, hipStream_t s)
+{
+    if (n_span <= 0) return hipSuccess;
+    TimedScope ts("advect", s);
+    hipLaunchKernelGGL(advect3_kernel, dim3((unsigned)((n_span + 255) / 256)), dim3(256), 0, s, pairs_dev, n_pairs,
+                       n_span, flow, wflow, ap, x1, y1, z1, x2, y2, z2);
+    return hipGetLastError();
+}
+
 // Moves a captured plan's descriptor on to the next batch of the same shape:
 // the pair-id offset grows by `step` (the batch size), so replays draw fresh
 // particles.

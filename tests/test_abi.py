@@ -129,36 +129,36 @@ def test_advect_and_render_validation(L):
     fake = ctypes.c_void_p(0x1000)
     ap = L.AdvectParams(1.0, 0, 1)
     assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
-                               ctypes.c_void_p(0x3000), None, 0, None) == L.SP_ERR_INVALID_ARG
+                               ctypes.c_void_p(0x3000), None, None, None, None, 0, None) == L.SP_ERR_INVALID_ARG
     ap = L.AdvectParams(1.0, 4, 7)
     assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
-                               ctypes.c_void_p(0x3000), None, 0, None) == L.SP_ERR_INVALID_ARG
+                               ctypes.c_void_p(0x3000), None, None, None, None, 0, None) == L.SP_ERR_INVALID_ARG
     ap = L.AdvectParams(1.0, 4, 1)
     assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, fake, ctypes.c_void_p(0x3000),
-                               None, 0, None) == L.SP_ERR_INVALID_ARG   # aliasing
+                               None, None, None, None, 0, None) == L.SP_ERR_INVALID_ARG   # aliasing
     n = ctypes.c_size_t()
     assert lib.synthpix_advect_workspace_size(pairs, 1, ctypes.byref(n)) == 0 and n.value >= 4 * 100
     assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
-                               ctypes.c_void_p(0x3000), ctypes.c_void_p(0x10000), n.value - 1,
+                               ctypes.c_void_p(0x3000), None, None, None, ctypes.c_void_p(0x10000), n.value - 1,
                                None) == L.SP_ERR_WORKSPACE
     assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, ctypes.c_void_p(0x2000),
-                               ctypes.c_void_p(0x3000), ctypes.c_void_p(0x10010), n.value,
+                               ctypes.c_void_p(0x3000), None, None, None, ctypes.c_void_p(0x10010), n.value,
                                None) == L.SP_ERR_WORKSPACE
     wsz = ctypes.c_size_t()
     assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(_rp(L)), None, 0, ctypes.byref(wsz)) == 0
     assert wsz.value >= n.value
     # workspace too small / misaligned
     rp = _rp(L)
-    st = lib.synthpix_render_pair(pairs, fake, 1, None, fake, fake, fake, fake, fake, fake, fake, ctypes.byref(rp),
+    st = lib.synthpix_render_pair(pairs, fake, 1, None, fake, fake, fake, fake, fake, fake, fake, None, ctypes.byref(rp),
                                   fake, ctypes.c_void_p(0x10000), 256, None)
     assert st == L.SP_ERR_WORKSPACE
-    st = lib.synthpix_render_pair(pairs, fake, 1, None, fake, fake, fake, fake, fake, fake, fake, ctypes.byref(rp),
+    st = lib.synthpix_render_pair(pairs, fake, 1, None, fake, fake, fake, fake, fake, fake, fake, None, ctypes.byref(rp),
                                   fake, ctypes.c_void_p(0x10010), 1 << 30, None)
     assert st == L.SP_ERR_WORKSPACE
     # overlapping particle ranges
     two = _pairs(L, [(64, 64, 16, 16, 100), (64, 64, 16, 16, 100)])
     two[1].particle_offset = 50
-    assert lib.synthpix_render_pair(two, fake, 2, None, fake, fake, fake, fake, fake, fake, fake,
+    assert lib.synthpix_render_pair(two, fake, 2, None, fake, fake, fake, fake, fake, fake, fake, None,
                                     ctypes.byref(rp), fake, ctypes.c_void_p(0x10000), 1 << 30,
                                     None) == L.SP_ERR_INVALID_ARG
 
@@ -265,3 +265,51 @@ def test_backward_validation(L):
     assert lib.synthpix_render_pair_backward(*half, ctypes.byref(rp), fake, fake, fake, fake, fake, fake, fake,
                                              None, fake, ctypes.c_void_p(0x100000), 1 << 30,
                                              None) == L.SP_ERR_INVALID_ARG
+
+
+def test_model_validation(L):
+    """The full model's parameters and inputs are checked on the host before
+    anything is enqueued."""
+    lib = L.load()
+    pairs = _pairs(L, [(64, 64, 16, 16, 100)])
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000)
+
+    def render(rp, ex=None):
+        return lib.synthpix_render_pair(pairs, fake, 1, None, fake, fake, fake, fake, fake, fake, fake,
+                                        ctypes.byref(ex) if ex is not None else None, ctypes.byref(rp), fake, ws,
+                                        1 << 30, None)
+
+    for field, value in (("hide_p", 1.5), ("hide_p", -0.1), ("jitter_d", -1.0), ("jitter_rho", float("nan")),
+                         ("jitter_I0", float("inf")), ("sheet_law", 7)):
+        rp = _rp(L)
+        setattr(rp, field, value)
+        assert render(rp) == L.SP_ERR_INVALID_ARG, field
+    rp = _rp(L)
+    rp.sheet_law = L.SP_SHEET_REMARK1
+    rp.sheet_dz0, rp.sheet_shape = 0.0, 2.0
+    assert render(rp) == L.SP_ERR_INVALID_ARG
+    rp.sheet_dz0, rp.sheet_shape = 1.0, 0.0
+    assert render(rp) == L.SP_ERR_INVALID_ARG
+    ex = L.ParticleExtras(0x1002, None, None)           # misaligned d_y
+    assert render(_rp(L), ex) == L.SP_ERR_INVALID_ARG
+    # 3-D motion needs wflow, z1 and z2 together, z2 not aliasing z1
+    ap = L.AdvectParams(1.0, 1, 0)
+    a2, a3 = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, a2, a3, fake, None, None, None,
+                               0, None) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_advect(pairs, fake, 1, fake, ctypes.byref(ap), fake, fake, a2, a3, fake,
+                               ctypes.c_void_p(0x4000), ctypes.c_void_p(0x4000), None, 0,
+                               None) == L.SP_ERR_INVALID_ARG
+    # the shape draws' correlation range
+    sp = L.SeedParams(0.02, 0.02, 0, 1.0, 2.0, 0, 0, 0.8, 1.0, -1, 1)
+    pairs82 = _pairs(L, [(64, 64, 16, 16, 82)])
+    for lo, hi in ((-1.0, 0.5), (0.2, 0.1), (0.0, 0.995)):
+        assert lib.synthpix_seed_shape(pairs82, fake, 1, ctypes.byref(sp), lo, hi, 0, fake, a2,
+                                       None) == L.SP_ERR_INVALID_ARG
+    # the backward differentiates the isotropic model only
+    rp = _rp(L)
+    rp.hide_p = 0.1
+    assert lib.synthpix_render_pair_backward(pairs, fake, 1, None, fake, fake, fake, None, None, fake, fake, fake,
+                                             ctypes.byref(rp), fake, fake, fake, fake, fake, fake, fake, None, fake,
+                                             ws, 1 << 30, None) == L.SP_ERR_UNSUPPORTED

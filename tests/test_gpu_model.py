@@ -1,0 +1,216 @@
+"""The full particle model on the GPU against the oracle: anisotropic particle
+images (Eq. 1 with sigma_y and rho), frame-2 parameter variation, per-frame
+hiding, the Remark 1 sheet law and out-of-plane motion.  Integer results (the
+shape draws, z2, the 12-bit codes with noise off, the binary32 images) are
+compared bit for bit with the binary32 mirror; float images within 1e-5 of the
+peak with the float64 definition evaluated on the GPU's binary32 particles."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import epilogue as oep
+from oracle import model as om
+from oracle import ra32
+from workloads import make_flows
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2512_09664_amd as sp
+    from gpu_util import DEV, batch_for, to_dev, to_np
+
+SIZES = ((160, 224), (97, 131), (256, 256))
+
+
+def _model(**kw):
+    m = dict(ppp=(0.03, 0.06), d_dist="uniform", d_params=(1.5, 4.5), I0=(0.8, 1.0), z=(-1.0, 1.0),
+             rho=(-0.6, 0.6), anisotropic=True, jitter=(0.0, 0.0, 0.0), hide_p=0.0, d_max=4.5, law="gauss",
+             sheet_sigma=0.5, dz0=1.0, shape=1.0, dt=1.0, substeps=2, integrator="rk4")
+    m.update(kw)
+    return m
+
+
+def _wgrids(flows, seed=3):
+    rng = np.random.default_rng(seed)
+    return [rng.normal(0.0, 0.08, size=f.shape[:2]).astype(np.float32) for f in flows]
+
+
+def _run(m, sizes=SIZES, seed=5, blur=1, bits=12, w3=False, tile=None):
+    """GPU seed -> shape -> advect (3-D if w3) -> render; returns everything the
+    checks need.  The device status word must come back clear."""
+    flows = make_flows("lamb_oseen", seed, sizes, 4, 6.0, 1.0)
+    n_max = [sp.particle_count(H, W, m["ppp"][1]) for (H, W) in sizes]
+    batch = batch_for(sizes, [f.shape[:2] for f in flows], n_max)
+    flow_dev = to_dev(np.concatenate([f.reshape(-1) for f in flows]))
+    sprm = sp.seed_params(m["ppp"], m["d_dist"], m["d_params"], m["I0"], m["z"])
+    aprm = sp.advect_params(m["dt"], m["substeps"], m["integrator"])
+    rprm = sp.render_params(m["sheet_sigma"], m["d_max"], blur, 0.7, 0.0, bits, seed, m["dt"], m["substeps"],
+                            m["integrator"], hide_p=m["hide_p"], jitter=m["jitter"], sheet_law=m["law"],
+                            sheet_dz0=m["dz0"], sheet_shape=m["shape"])
+    P = sp.seed(batch, sprm, seed)
+    dy = rho = None
+    if m["anisotropic"]:
+        dy, rho = sp.seed_shape(batch, sprm, m["rho"], seed)
+    wg = None
+    z2 = None
+    if w3:
+        wg = _wgrids(flows)
+        wflow = to_dev(np.concatenate([w.reshape(-1) for w in wg]))
+        x2, y2, z2 = sp.advect(batch, flow_dev, aprm, P["x"], P["y"], wflow=wflow, z1=P["z"])
+    else:
+        x2, y2 = sp.advect(batch, flow_dev, aprm, P["x"], P["y"])
+    ws = sp.alloc_workspace(batch, rprm, tile)
+    img = sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, tile, None, ws, dy=dy,
+                         rho=rho, z2=z2)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    return dict(batch=batch, flows=flows, wg=wg, P=P, dy=dy, rho=rho, x2=x2, y2=y2, z2=z2, img=img, seed=seed,
+                blur=blur, bits=bits)
+
+
+def _mirror_pairs(m, R):
+    batch = R["batch"]
+    img = to_np(R["img"])
+    w = oep.blur_weights(R["blur"], 0.7) if R["blur"] > 0 else None
+    for p in range(batch.n_pairs):
+        H, W = batch.host[p].H, batch.host[p].W
+        ref = ra32.generate_pair_model(m, H, W, p, R["seed"], R["flows"][p], R["wg"][p] if R["wg"] else None,
+                                       w, R["bits"])
+        o = batch.host[p].image_offset
+        got = img[o:o + 2 * H * W].reshape(2, H, W)
+        yield p, H, W, got, ref
+
+
+def test_seed_shape_matches_mirror():
+    for d_dist, d_params in (("uniform", (1.5, 4.5)), ("normal", (2.5, 0.5, 1.0, 5.0))):
+        m = _model(d_dist=d_dist, d_params=d_params, d_max=5.0)
+        sizes = ((64, 80), (33, 47))
+        n_max = [sp.particle_count(H, W, m["ppp"][1]) for (H, W) in sizes]
+        batch = batch_for(sizes, [(16, 20), (8, 11)], n_max, [7, 2 ** 33 + 5])
+        sprm = sp.seed_params(m["ppp"], d_dist, d_params, m["I0"], m["z"])
+        dy, rho = sp.seed_shape(batch, sprm, (-0.7, 0.4), 9)
+        torch.cuda.synchronize()
+        for p, pid in enumerate((7, 2 ** 33 + 5)):
+            s = slice(batch.host[p].particle_offset, batch.host[p].particle_offset + n_max[p])
+            rdy, rrho = ra32.seed_shape(n_max[p], pid, 9, d_dist, d_params, (-0.7, 0.4))
+            assert np.array_equal(to_np(dy)[s], rdy)
+            assert np.array_equal(to_np(rho)[s], rrho)
+
+
+@pytest.mark.parametrize("integrator,substeps", [("euler", 1), ("rk4", 3)])
+def test_out_of_plane_motion_matches_mirror(integrator, substeps):
+    m = _model(integrator=integrator, substeps=substeps, anisotropic=False)
+    R = _run(m, w3=True, bits=0, blur=0)
+    batch = R["batch"]
+    for p in range(batch.n_pairs):
+        H, W = batch.host[p].H, batch.host[p].W
+        s = slice(batch.host[p].particle_offset, batch.host[p].particle_offset + batch.host[p].n_max)
+        x1, y1, z1 = (to_np(R["P"][k])[s] for k in ("x", "y", "z"))
+        rx2, ry2 = ra32.advect(R["flows"][p], H, W, x1, y1, m["dt"], substeps, integrator)
+        rz2 = ra32.advect_z(R["flows"][p], R["wg"][p], H, W, x1, y1, z1, m["dt"], substeps, integrator)
+        assert np.array_equal(to_np(R["x2"])[s], rx2)
+        assert np.array_equal(to_np(R["y2"])[s], ry2)
+        assert np.array_equal(to_np(R["z2"])[s], rz2)
+
+
+CASES = {
+    "aniso": dict(),
+    "aniso_jitter_hide": dict(jitter=(0.15, 0.1, 0.05), hide_p=0.2),
+    "remark1_3d": dict(anisotropic=False, law="remark1", dz0=1.2, shape=2.0),
+    "hide_only": dict(anisotropic=False, hide_p=0.35),
+    "remark1_aniso_jitter": dict(law="remark1", dz0=0.9, shape=0.7, jitter=(0.1, 0.2, 0.0), rho=(-0.9, 0.9)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("blur", [0, 1, 2])
+def test_model_codes_match_mirror(case, blur):
+    m = _model(**CASES[case])
+    R = _run(m, blur=blur, bits=12, w3=case.startswith("remark1"))
+    for p, H, W, got, ref in _mirror_pairs(m, R):
+        assert np.array_equal(got, ref["codes"]), f"{case} pair {p}: {(got != ref['codes']).sum()} codes differ"
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_model_float_images_match_mirror_and_float64(case):
+    m = _model(**CASES[case])
+    R = _run(m, blur=1, bits=0, w3=case.startswith("remark1"))
+    batch = R["batch"]
+    w = oep.blur_weights(1, 0.7)
+    for p, H, W, got, ref in _mirror_pairs(m, R):
+        assert np.array_equal(got, ref["J"]), f"{case} pair {p}: binary32 images differ from the mirror"
+        # float64 definition on the GPU's binary32 particles
+        s = slice(batch.host[p].particle_offset, batch.host[p].particle_offset + batch.host[p].n_max)
+        g = {k: to_np(R["P"][k])[s].astype(np.float64) for k in ("x", "y", "z", "d", "I0")}
+        dyv = to_np(R["dy"])[s].astype(np.float64) if R["dy"] is not None else g["d"]
+        rhov = to_np(R["rho"])[s].astype(np.float64) if R["rho"] is not None else np.zeros_like(g["d"])
+        z2 = to_np(R["z2"])[s].astype(np.float64) if R["z2"] is not None else g["z"]
+        f1, f2 = om.frame_params(g["d"], dyv, rhov, g["I0"], p, R["seed"], m["jitter"], m["hide_p"], m["d_max"])
+        frames = []
+        for (xf, yf, zf, f) in ((g["x"], g["y"], g["z"], f1),
+                                (to_np(R["x2"])[s], to_np(R["y2"])[s], z2, f2)):
+            A = om.peaks(f[3], zf, m["law"], m["sheet_sigma"], m["dz0"], m["shape"])
+            frames.append(oep.blur(om.render_frame(xf, yf, A, f[0], f[1], f[2], H, W), w))
+        J64 = np.stack(frames)
+        peak = J64.max()
+        err = np.max(np.abs(got.astype(np.float64) - J64))
+        assert err <= 1e-5 * peak, f"{case} pair {p}: {err:.3e} > 1e-5 * {peak:.3f}"
+
+
+def test_isotropic_extras_give_the_isotropic_bits():
+    # d_y = d and rho = 0 passed explicitly through the anisotropic kernels: the
+    # isotropic path's images, bit for bit
+    m = _model(anisotropic=False)
+    R = _run(m, bits=12, blur=1)
+    b = R["batch"]
+    P = R["P"]
+    rprm = sp.render_params(0.5, 4.5, 1, 0.7, 0.0, 12, R["seed"])
+    img = sp.render_pair(b, P["x"], P["y"], R["x2"], R["y2"], P["z"], P["d"], P["I0"], rprm, None, None, None,
+                         dy=P["d"], rho=torch.zeros_like(P["d"]))
+    torch.cuda.synchronize()
+    base = sp.render_pair(b, P["x"], P["y"], R["x2"], R["y2"], P["z"], P["d"], P["I0"], rprm)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(img), to_np(base))
+
+
+@pytest.mark.parametrize("tile", [(16, 16, 1024, 64), (64, 64, 2048, 128), (128, 32, 4096, 32)])
+def test_model_tiling_does_not_change_bits(tile):
+    m = _model(**CASES["aniso_jitter_hide"])
+    base = _run(m, bits=12, blur=1)
+    R = _run(m, bits=12, blur=1, tile=sp.tiling(*tile))
+    assert np.array_equal(to_np(base["img"]), to_np(R["img"]))
+
+
+def test_bad_rho_is_flagged():
+    sizes = ((40, 48),)
+    n = 6
+    batch = batch_for(sizes, [(10, 12)], [n])
+    x = to_dev(np.array([10.5, 20.0, 30.0, 5.0, 40.0, 24.0], np.float32))
+    y = to_dev(np.array([10.5, 20.0, 8.0, 30.0, 35.0, 24.0], np.float32))
+    z = torch.zeros(n, device=DEV)
+    d = torch.full((n,), 3.0, device=DEV)
+    I0 = torch.full((n,), 0.9, device=DEV)
+    rho = to_dev(np.array([0.0, 0.5, -0.99, 0.995, 0.3, -0.2], np.float32))
+    rprm = sp.render_params(0.5, 4.0, 0, 0.7, 0.0, 0, 0)
+    ws = sp.alloc_workspace(batch, rprm)
+    img = sp.render_pair(batch, x, y, x, y, z, d, I0, rprm, None, None, ws, dy=d, rho=rho)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 4
+    # the flagged particle is left out; every other one is rendered
+    keep = np.array([True, True, True, False, True, True])
+    A = om.peaks(np.full(n, 0.9), np.zeros(n), "gauss", 0.5)
+    ref = om.render_frame(to_np(x)[keep], to_np(y)[keep], A[keep], np.full(n, 3.0)[keep], np.full(n, 3.0)[keep],
+                          to_np(rho)[keep], 40, 48)
+    got = to_np(img)[:40 * 48].reshape(40, 48)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * ref.max()
+
+
+def test_full_size_model_pair_1024():
+    # one 1024x1024 pair of the scale workload's density under the full model:
+    # every 12-bit code equal to the mirror's
+    m = _model(ppp=(0.05, 0.05), d_dist="normal", d_params=(2.5, 0.5, 1.0, 5.0), d_max=5.0,
+               jitter=(0.1, 0.05, 0.02), hide_p=0.1, rho=(-0.8, 0.8), substeps=4)
+    R = _run(m, sizes=((1024, 1024),), blur=1, bits=12)
+    for p, H, W, got, ref in _mirror_pairs(m, R):
+        assert np.array_equal(got, ref["codes"])

@@ -87,7 +87,7 @@ def plan_throughput(sp, torch, np, dev, wl, flows, flow, batch, sprm, aprm, rprm
     dt = _time_plan(torch, plan, steps)
     plan.close()
     return {"pairs_per_s": round(wl.n_pairs / dt, 1), "ms_per_step": round(1000 * dt, 4),
-            "tiling": [t.tile_w, t.tile_h, t.chunk, t.cap]}
+            "tiling": [t.tile_w, t.tile_h, t.chunk, t.cap, t.persistent]}
 
 
 def dense_throughput(sp, torch, np, dev, steps=10):
@@ -104,7 +104,7 @@ def dense_throughput(sp, torch, np, dev, steps=10):
     del io
     torch.cuda.empty_cache()
     return {"pairs_per_s": round(wl.n_pairs / dt, 1), "gpx_per_s": round(wl.pixels() / dt / 1e9, 2),
-            "ms_per_step": round(1000 * dt, 4), "tiling": [t.tile_w, t.tile_h, t.chunk, t.cap]}
+            "ms_per_step": round(1000 * dt, 4), "tiling": [t.tile_w, t.tile_h, t.chunk, t.cap, t.persistent]}
 
 
 def uneven_batched_vs_per_pair(sp, torch, np, dev, steps=5):
@@ -257,6 +257,103 @@ def fp64_error(sp, torch, np, dev):
             cnt += e.size
         out[name] = {"pairs": wl.n_pairs, "max_rel_peak": float(f"{mx:.3e}"), "mean_rel_peak": float(f"{sm / cnt:.3e}")}
     return out
+
+
+def model_throughput(sp, torch, np, dev, steps=10):
+    """scale_1024 under the full particle model (anisotropic particles with
+    rho ~ U[-0.5, 0.5], frame-2 variation (0.1 px, 0.05, 0.02), hiding 0.1, the
+    Remark 1 sheet law with DZ0 = 1, shape 2, out-of-plane motion), eager calls,
+    against the isotropic path on the same batch."""
+    from workloads import get_workload
+    wl = get_workload("scale_1024")
+    flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
+    rpm = sp.render_params(wl.sheet_sigma, wl.d_max, wl.blur_radius, wl.blur_sigma, wl.noise_sigma, wl.bits,
+                           wl.seed, wl.dt, wl.substeps, wl.integrator, hide_p=0.1, jitter=(0.1, 0.05, 0.02),
+                           sheet_law="remark1", sheet_dz0=1.0, sheet_shape=2.0)
+    wflow = 0.02 * torch.randn(flow.numel() // 2, device=dev, generator=torch.Generator(device=dev).manual_seed(2))
+    P = sp.seed(batch, sprm, wl.seed)
+    dy, rho = sp.seed_shape(batch, sprm, (-0.5, 0.5), wl.seed)
+    x2 = torch.empty_like(P["x"])
+    y2 = torch.empty_like(P["x"])
+    z2 = torch.empty_like(P["x"])
+    img = torch.empty(batch.n_pixels, dtype=sp.api.U16, device=dev)
+    ws = sp.alloc_workspace(batch, rpm)
+
+    def step(k):
+        sp.seed(batch, sprm, wl.seed + k, out=P)
+        sp.seed_shape(batch, sprm, (-0.5, 0.5), wl.seed + k, out=(dy, rho))
+        sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2, wflow=wflow, z1=P["z"], z2=z2)
+        sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rpm, None, img, ws, dy=dy, rho=rho,
+                       z2=z2)
+
+    step(0)
+    torch.cuda.synchronize()
+    sp.timing_read(None)
+    sp.timing_enable(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k + 1)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    sp.timing_enable(False)
+    ms, n = sp.timing_read("render_tile")
+    sp.timing_read(None)
+    flags = sp.read_status(ws)
+    del ws, img, P, dy, rho, x2, y2, z2, wflow
+    torch.cuda.empty_cache()
+    return {"pairs_per_s": round(wl.n_pairs / dt, 1), "ms_per_step": round(1000 * dt, 4),
+            "render_tile_us": round(1000 * ms / max(n, 1), 2), "status": flags}
+
+
+def sampler_throughput(sp, torch, np, dev, batches=30):
+    """The sampler front end (make / next) on the paper's ablation setting:
+    512x512, ppp 0.06, d ~ U[0.8, 1.2], B = 64, F = 1, one flow field kept for
+    all batches, Euler dt = 1, float images; batches consumed back to back with
+    pre-fetching.  Also the same with the full model and 12-bit codes adjusted
+    to a flat histogram."""
+    from paper_2512_09664_amd import sampler as smp
+    out = {}
+    base = dict(image_shape=(512, 512), batch_size=64, flows_per_batch=1, batches_per_flow=1 << 20,
+                seeding_density=(0.06, 0.06), diameter={"dist": "uniform", "range": [0.8, 1.2]},
+                flow={"kind": "lamb_oseen", "grid_div": 4, "max_disp": 8.0}, seed=0)
+    full = dict(base, rho=(-0.5, 0.5), jitter=(0.05, 0.05, 0.02), hide_p=0.05, bits=12, noise_sigma=0.01,
+                blur={"radius": 1, "sigma": 0.7}, histogram=[1] * 4096,
+                sheet={"law": "remark1", "dz0": 1.0, "shape": 2.0})
+    for name, cfg in (("ablation_512", base), ("full_model_512", full)):
+        s = smp.make(cfg)
+        for _ in range(3):
+            next(s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(batches):
+            b = next(s)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / batches
+        s.close()
+        out[name] = {"pairs_per_s": round(64 / dt, 1), "ms_per_batch": round(1000 * dt, 4),
+                     "graph": bool(s._graph)}
+        del s, b
+        torch.cuda.empty_cache()
+    return out
+
+
+def histogram_cost(sp, torch, np, dev, batch, images, reps=10):
+    """Histogram adjustment of scale_1024's 12-bit images to a flat target:
+    microseconds per batch and the rate over its algorithmic bytes (the codes
+    read twice and written once)."""
+    target = torch.ones(4096, dtype=torch.int32, device=dev)
+    ws = sp.histogram_match(batch, images, target, 12)
+    torch.cuda.synchronize()
+    sp.timing_read(None)
+    sp.timing_enable(True)
+    for _ in range(reps):
+        sp.histogram_match(batch, images, target, 12, ws)
+    torch.cuda.synchronize()
+    sp.timing_enable(False)
+    ms, n = sp.timing_read("histogram_match")
+    sp.timing_read(None)
+    us = 1000.0 * ms / n
+    return {"us_per_batch": round(us, 2), "gb_per_s": round(3 * images.numel() * 2 / (us * 1e-6) / 1e9, 1)}
 
 
 def _one_thread():
@@ -471,6 +568,8 @@ def main():
 
     extras = {}
     if not args.no_extras:
+        extras["histogram_match"] = histogram_cost(sp, torch, np, dev, batch, images)
+        log(f"[bench] histogram_match: {extras['histogram_match']}")
         extras["graph_plan"] = plan_throughput(sp, torch, np, dev, wl, flows, flow, batch, sprm, aprm, rprm)
         log(f"[bench] graph plan on {wl.name}: {extras['graph_plan']}")
         del images, ws, P, x2, y2
@@ -483,6 +582,10 @@ def main():
         log(f"[bench] dense_2048: {extras['dense_2048']}")
         extras["dense_2048_grad"] = gradient_cost(sp, torch, np, dev, "dense_2048", steps=5)
         log(f"[bench] dense_2048_grad: {extras['dense_2048_grad']}")
+        extras["full_model"] = model_throughput(sp, torch, np, dev)
+        log(f"[bench] full_model: {extras['full_model']}")
+        extras["sampler"] = sampler_throughput(sp, torch, np, dev)
+        log(f"[bench] sampler: {extras['sampler']}")
         extras["plain_256_latency"] = latency_plain_256(sp, torch, np, dev)
         log(f"[bench] plain_256 latency: {extras['plain_256_latency']}")
         extras["fp64_err"] = fp64_error(sp, torch, np, dev)

@@ -160,6 +160,9 @@ typedef struct {
     int32_t tile_w, tile_h;
     int32_t chunk;              /* particles per binning block (256 .. 16384, multiple of 256) */
     int32_t cap;                /* particles staged in LDS per render pass (32 .. 256)        */
+    int32_t persistent;         /* 1: one persistent render launch whose workgroups (as many as
+                                   the device holds) pop (frame, tile) items from per-XCD work
+                                   queues; 0: one workgroup per item.  Same images either way. */
 } synthpix_tiling;
 
 /* ---------------------------------------------------------------- helpers */
@@ -177,7 +180,7 @@ synthpix_status synthpix_default_tiling(const synthpix_pair* pairs_host, int32_t
 /* The tilings a plan's autotuner may choose for these parameters (the default
  * first): every compiled tile shape x LDS particle capacity whose LDS fits,
  * with 2048-particle binning blocks, then the binning block sizes it tries for
- * the fastest of those.  Writes at most max_out entries, the total count to
+ * the fastest of those, then the persistent form of the fastest.  Writes at most max_out entries, the total count to
  * *n_out. */
 synthpix_status synthpix_tiling_candidates(const synthpix_render_params* rp, synthpix_tiling* out,
                                            int32_t max_out, int32_t* n_out);
@@ -382,7 +385,8 @@ synthpix_status synthpix_flow_field(const synthpix_pair* pairs_host, const synth
                                     int32_t n_pairs, const float* flow, float* out, void* stream);
 
 /* Histogram adjustment of the stored images (Section 2, after Remark 2: the
- * images are optionally adjusted to a user-specified intensity histogram).
+ * output may be remapped so that its intensities follow a histogram the user
+ * chooses).
  * Every image (each frame of each pair, uint16 codes of `bits` bits, 1..14) is
  * mapped in place onto the target histogram `target` (device uint32 counts
  * [2^bits], total in [1, 2^32)): code k becomes the smallest m with

@@ -1,7 +1,7 @@
 """Histogram adjustment of the stored images, definition (oracle, test infrastructure).
 
-Section 2 (after Remark 2): the generated images are optionally adjusted to a
-user-specified intensity histogram.  Reading: classical histogram
+Section 2 (after Remark 2): the output may be remapped so that its
+intensities follow a histogram the user chooses.  Reading: classical histogram
 specification of each stored image (each frame of each pair, its integer
 codes 0 .. 2^bits - 1) to one target histogram t[0 .. 2^bits - 1] of
 non-negative counts.  With the image's cumulative counts S(k) (pixels with a

@@ -70,7 +70,7 @@ class ParticleExtras(ctypes.Structure):
 
 class Tiling(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("cap", ctypes.c_int32)]
+                ("cap", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class BinViews(ctypes.Structure):

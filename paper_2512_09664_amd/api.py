@@ -150,9 +150,10 @@ def render_params(sheet_sigma=0.5, d_max=5.0, blur_radius=0, blur_sigma=0.7, noi
     return rp
 
 
-def tiling(tile_w=32, tile_h=32, chunk=4096, cap=128):
+def tiling(tile_w=32, tile_h=32, chunk=4096, cap=128, persistent=0):
     t = L.Tiling()
     t.tile_w, t.tile_h, t.chunk, t.cap = int(tile_w), int(tile_h), int(chunk), int(cap)
+    t.persistent = int(persistent)
     return t
 
 

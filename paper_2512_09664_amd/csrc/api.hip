@@ -129,6 +129,7 @@ synthpix_status check_tiling(const synthpix_tiling& t)
     if (t.chunk < 256 || t.chunk > 16384 || (t.chunk & 255))
         return fail(SP_ERR_INVALID_ARG, "chunk must be a multiple of 256 in [256, 16384]");
     if (t.cap < 32 || t.cap > 256) return fail(SP_ERR_INVALID_ARG, "cap must be in [32, 256]");
+    if (t.persistent != 0 && t.persistent != 1) return fail(SP_ERR_INVALID_ARG, "persistent must be 0 or 1");
     return SP_OK;
 }
 
@@ -150,6 +151,7 @@ sp::RenderConfig make_config(const synthpix_render_params& rp, const synthpix_ti
     c.tile_h = t.tile_h;
     c.chunk = t.chunk;
     c.cap = t.cap;
+    c.persistent = t.persistent;
     c.apron = rp.blur_radius;
     c.d_max = rp.d_max;
     c.log_tw = 0;
@@ -197,7 +199,7 @@ sp::WorkspaceLayout workspace_layout(int32_t n_pairs, const sp::BatchTotals& T, 
 {
     sp::WorkspaceLayout w{};
     size_t o = 0;
-    w.status = o; o = align256(o + 16);
+    w.status = o; o = align256(o + 64);     // status words 0..3, render work queues 8..15
     w.layout = o; o = align256(o + sizeof(sp::PairLayout) * (size_t)n_pairs);
     w.tile_count = o; o = align256(o + sizeof(uint32_t) * 2 * (size_t)T.tiles);
     w.tile_offset = o; o = align256(o + sizeof(int64_t) * 2 * (size_t)T.tiles);
@@ -344,6 +346,7 @@ synthpix_tiling default_tiling()
     t.tile_h = 32;
     t.chunk = 2048;    // smaller binning blocks keep more of each tile list's writes in L2
     t.cap = 64;
+    t.persistent = 0;
     return t;
 }
 
@@ -955,7 +958,7 @@ std::vector<synthpix_tiling> shape_candidates(const synthpix_render_params& rp)
     const int caps[] = {32, 64, 128};
     for (const auto& sh : shapes)
         for (int cap : caps) {
-            synthpix_tiling t{sh[0], sh[1], 2048, cap};
+            synthpix_tiling t{sh[0], sh[1], 2048, cap, 0};
             if (t.tile_w == out[0].tile_w && t.tile_h == out[0].tile_h && t.cap == out[0].cap) continue;
             if (sp::render_lds_bytes(make_config(rp, t)) > 160 * 1024) continue;
             out.push_back(t);
@@ -986,7 +989,8 @@ synthpix_status synthpix_tiling_candidates(const synthpix_render_params* rp, syn
     synthpix_status st = check_render_params(rp);
     if (st) return st;
     std::vector<synthpix_tiling> c = shape_candidates(*rp);
-    for (int ch : CHUNK_CANDIDATES) c.push_back(synthpix_tiling{c[0].tile_w, c[0].tile_h, ch, c[0].cap});
+    for (int ch : CHUNK_CANDIDATES) c.push_back(synthpix_tiling{c[0].tile_w, c[0].tile_h, ch, c[0].cap, 0});
+    c.push_back(synthpix_tiling{c[0].tile_w, c[0].tile_h, c[0].chunk, c[0].cap, 1});
     for (int32_t i = 0; i < max_out && i < (int32_t)c.size(); ++i) out[i] = c[i];
     *n_out = (int32_t)c.size();
     return SP_OK;
@@ -1100,6 +1104,12 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
             synthpix_tiling tc = shape_best;
             tc.chunk = ch;
             time_one(tc);
+        }
+        // then the persistent form of the fastest
+        if (e == hipSuccess) {
+            synthpix_tiling tp = P->tiling;
+            tp.persistent = 1;
+            time_one(tp);
         }
         if (a) hipEventDestroy(a);
         if (b) hipEventDestroy(b);

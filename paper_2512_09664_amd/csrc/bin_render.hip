@@ -18,6 +18,10 @@
 //                 blur, noise, quantise and store.
 // No global atomics: counts, cursors and pixel sums all live in LDS.  Pixel sums
 // are exact 32-bit fixed point, so the LDS atomics' order does not matter.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "device_math.hpp"
 #include "launch.hpp"
 
@@ -43,7 +47,8 @@ bin_layout(const synthpix_pair* __restrict__ pairs, int n_pairs, RenderConfig cf
     __shared__ int64_t s_carry[4];
     const int t = threadIdx.x;
     if (t < 4) s_carry[t] = 0;
-    if (t == 0) { status[0] = 0u; status[1] = 0u; status[2] = 0u; status[3] = 0u; }
+    // status words, and the renderer's per-XCD work queues (words 8 .. 15)
+    if (t < 16) status[t] = 0u;
     __syncthreads();
     for (int base = 0; base < n_pairs; base += 256) {
         const int p = base + t;
@@ -480,13 +485,14 @@ __device__ __forceinline__ uint32_t pack_box(int c0, int w, int r0, int h)
 // rho = 0 keeps the separable factors (with kappa_y for the rows), rho != 0
 // evaluates exp(-q) per pixel, q = dx (kappa_x dx + kappa_xy dy) + kappa_y dy^2,
 // kappa_xy = -16 rho / (om d d_y); the patch is |dx| <= 1.5 d, |dy| <= 1.5 d_y.
-template <int TW, int TH, int B, bool ANISO>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+template <int TW, int TH, int B, bool ANISO, bool PERSIST>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PERSIST ? 6 : 8)))
 render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
             const float4* __restrict__ rec0, const float4* __restrict__ rec1, const float2* __restrict__ shp0,
             const float2* __restrict__ shp1, EpilogueArgs a, int cap, int wm4,
             const uint32_t* __restrict__ tile_count, const int64_t* __restrict__ tile_offset,
-            const int32_t* __restrict__ entries, int64_t tiles_total, uint32_t* __restrict__ status)
+            const int32_t* __restrict__ entries, int64_t tiles_total, uint32_t* __restrict__ status,
+            uint32_t* __restrict__ queue)
 {
     static_assert(TW % 4 == 0 && (TW & (TW - 1)) == 0 && (TH & (TH - 1)) == 0, "power-of-two tiles");
     static_assert(TW + 6 < 256 && TH + 6 < 256, "patch boxes are packed in bytes");
@@ -515,20 +521,42 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     // peak, so a row's prefix sum bounds every pixel sum of that row.
     __shared__ unsigned long long s_rows[RH + 1];
 
-    // one (frame, tile) item per workgroup; XCD-contiguous numbering keeps
-    // neighbouring tiles (which share particles) on one L2
-    const int64_t item = xcd_contiguous(blockIdx.x, gridDim.x);
+    // PERSIST: a persistent work list.  Each workgroup pops (frame, tile) items
+    // from the queue of its XCD until the queue is empty; the items of one XCD
+    // form a contiguous range (workgroups are dispatched to the 8 XCDs
+    // round-robin), so the neighbouring tiles in flight on an XCD share particle
+    // records in its L2, and the grid is at most what the chip holds at once.
+    // Otherwise one item per workgroup, numbered XCD-contiguously.
+    __shared__ unsigned s_pop;
+    uint64_t pid_base = 0;
+    if (a.iod) {
+        a.images = a.iod->images;
+        a.seed = a.iod->seed;
+        pid_base = a.iod->pair_id_base;
+    }
+    const unsigned n_items = (unsigned)(2 * tiles_total);
+    const bool split = gridDim.x >= 8;
+    const unsigned xq = split ? (blockIdx.x & 7u) : 0u;
+    const unsigned q8 = n_items >> 3, r8 = n_items & 7u;
+    const unsigned lo = split ? (xq < r8 ? xq * (q8 + 1) : r8 * (q8 + 1) + (xq - r8) * q8) : 0u;
+    const unsigned len = split ? (xq < r8 ? q8 + 1 : q8) : n_items;
+    for (;;) {
+    int64_t item;
+    if (PERSIST) {
+        if (threadIdx.x == 0) s_pop = atomicAdd(&queue[xq], 1u);
+        __syncthreads();
+        const unsigned kq = (unsigned)__builtin_amdgcn_readfirstlane((int)s_pop);   // uniform: one scalar value
+        if (kq >= len) break;             // the same value in every thread of the workgroup
+        item = (int64_t)lo + kq;
+    } else {
+        item = xcd_contiguous(blockIdx.x, gridDim.x);
+    }
     const int f = item >= tiles_total ? 1 : 0;
     const int64_t tile = item - (int64_t)f * tiles_total;
     const int p = find_pair_by_tile(L, n_pairs, tile);
     const int pW = pairs[p].W, pH = pairs[p].H;
     const int64_t p_off = pairs[p].particle_offset, p_img = pairs[p].image_offset;
-    uint64_t pid = pairs[p].pair_id;
-    if (a.iod) {
-        a.images = a.iod->images;
-        a.seed = a.iod->seed;
-        pid += a.iod->pair_id_base;
-    }
+    const uint64_t pid = pairs[p].pair_id + pid_base;
     const int64_t tile_base = L[p].tile_base;
     const int ntx = L[p].ntx;
     const int tl = (int)(tile - tile_base);
@@ -790,6 +818,10 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             }
         }
     }
+    if (!PERSIST) break;
+    // the next item's accumulator reset and queue pop wait for this epilogue
+    __syncthreads();
+    }
 }
 
 size_t render_lds_bytes(const RenderConfig& cfg, bool aniso) { return render_lds(cfg, aniso).bytes; }
@@ -816,6 +848,38 @@ static void launch_scans(const PairLayout* L, int n_pairs, uint32_t* hist, uint3
                        tiles);
 }
 
+// Launches one renderer instantiation: one workgroup per item, or (persistent
+// kernels) as many workgroups as the device holds at once, from the kernel's
+// occupancy at this LDS size (cached per kernel and size).  The persistent
+// form is compiled for the isotropic renderer; anisotropic batches run one
+// workgroup per item.
+template <typename K, typename... Args>
+static void launch_tile_kernel(K kernel, dim3 grid, size_t lds, hipStream_t s, bool persistent, Args... args)
+{
+    if (persistent) {
+        static std::mutex mu;
+        static std::map<std::pair<const void*, size_t>, int> cache;
+        int per_cu = 0;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), lds);
+            auto it = cache.find(key);
+            if (it == cache.end()) {
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds) != hipSuccess)
+                    per_cu = 0;
+                cache[key] = per_cu;
+            } else {
+                per_cu = it->second;
+            }
+        }
+        if (per_cu > 0) {
+            const unsigned cap = (unsigned)per_cu * (unsigned)device_cu_count();
+            if (grid.x > cap) grid.x = cap;
+        }
+    }
+    hipLaunchKernelGGL(kernel, grid, dim3(256), lds, s, args...);
+}
+
 template <int TW, int TH>
 static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const RenderArgs& a, const RenderConfig& cfg,
                                 const PairLayout* L, const float4* r0, const float4* r1, const float2* h0,
@@ -832,13 +896,17 @@ static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const Rend
 #define SP_B(B_)                                                                                                 \
     case B_:                                                                                                     \
         if (a.aniso)                                                                                             \
-            hipLaunchKernelGGL((render_tile<TW, TH, B_, true>), grid, dim3(256), lds, s, a.pairs, L, a.n_pairs,  \
+            launch_tile_kernel(render_tile<TW, TH, B_, true, false>, grid, lds, s, false, a.pairs, L, a.n_pairs, \
                                r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles,    \
-                               status);                                                                          \
+                               status, status + 8);                                                              \
+        else if (cfg.persistent)                                                                                 \
+            launch_tile_kernel(render_tile<TW, TH, B_, false, true>, grid, lds, s, true, a.pairs, L, a.n_pairs,  \
+                               r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles,    \
+                               status, status + 8);                                                              \
         else                                                                                                     \
-            hipLaunchKernelGGL((render_tile<TW, TH, B_, false>), grid, dim3(256), lds, s, a.pairs, L, a.n_pairs, \
-                               r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles,    \
-                               status);                                                                          \
+            launch_tile_kernel(render_tile<TW, TH, B_, false, false>, grid, lds, s, false, a.pairs, L,           \
+                               a.n_pairs, r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset,         \
+                               entries, tiles, status, status + 8);                                              \
         break;
     switch (cfg.apron) { SP_B(0) SP_B(1) SP_B(2) SP_B(3) default: break; }
 #undef SP_B

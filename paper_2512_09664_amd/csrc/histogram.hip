@@ -1,6 +1,6 @@
 // Histogram adjustment of the stored images (Section 2, after Remark 2: the
-// generated images are optionally adjusted to a user-specified intensity
-// histogram), gfx950.
+// output may be remapped so that its intensities follow a histogram the user
+// chooses), gfx950.
 //
 // Histogram specification of every stored image (each frame of each pair, its
 // integer codes) to one target histogram t[0 .. B - 1], B = 2^bits: with the

@@ -58,6 +58,7 @@ struct RenderConfig {
     int wm4;                // wmax rounded up to a multiple of 4 (row stride of the tables)
     int kx, ky;             // bound on tiles touched per particle per axis
     float d_max;
+    int persistent;         // renderer grid capped at the device's resident workgroups
 };
 
 // Totals of a batch (host side).

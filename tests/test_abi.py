@@ -232,6 +232,7 @@ def test_tiling_candidates(L):
         assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(rp), ctypes.byref(t), 0, ctypes.byref(size)) == 0
         chunks.add(t.chunk)
     assert chunks >= {1024, 2048, 4096, 8192}
+    assert [t.persistent for t in arr].count(1) == 1 and arr[n.value - 1].persistent == 1
     bad = _rp(L, sheet_sigma=-1.0)
     assert lib.synthpix_tiling_candidates(ctypes.byref(bad), arr, n.value, ctypes.byref(n)) == L.SP_ERR_INVALID_ARG
 

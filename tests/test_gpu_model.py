@@ -174,7 +174,8 @@ def test_isotropic_extras_give_the_isotropic_bits():
     assert np.array_equal(to_np(img), to_np(base))
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 1024, 64), (64, 64, 2048, 128), (128, 32, 4096, 32)])
+@pytest.mark.parametrize("tile", [(16, 16, 1024, 64), (64, 64, 2048, 128), (128, 32, 4096, 32),
+                                  (64, 32, 2048, 64, 1)])
 def test_model_tiling_does_not_change_bits(tile):
     m = _model(**CASES["aniso_jitter_hide"])
     base = _run(m, bits=12, blur=1)

@@ -181,7 +181,8 @@ def _render_gpu(b, arrs, rp, tile=None, workspace=None):
     return gu.to_np(img)
 
 
-TILINGS = [None, (8, 8, 256, 32), (64, 32, 256, 64), (128, 32, 16384, 128), (32, 16, 512, 96)]
+TILINGS = [None, (8, 8, 256, 32), (64, 32, 256, 64), (128, 32, 16384, 128), (32, 16, 512, 96),
+           (64, 32, 2048, 64, 1), (8, 8, 256, 32, 1)]
 
 
 @pytest.mark.parametrize("tile", TILINGS)
@@ -232,7 +233,7 @@ def test_tiling_and_batching_do_not_change_bits():
         o += 2 * H * W
 
 
-@pytest.mark.parametrize("tile", [None, (8, 8, 256, 32), (128, 32, 16384, 128)])
+@pytest.mark.parametrize("tile", [None, (8, 8, 256, 32), (128, 32, 16384, 128), (64, 64, 2048, 128, 1)])
 def test_large_diameters_match_oracle(ra, tile):
     """Diameters up to 15 px under d_max = 16 (the largest accepted) with the
     widest blur: patches far wider than small tiles, the widest factor tables."""

@@ -56,7 +56,7 @@ def _plan_run(wl, autotune=True):
     t = plan.tiling
     status = plan.read_status()
     plan.close()
-    return flows, batch, io, (t.tile_w, t.tile_h, t.chunk, t.cap), status
+    return flows, batch, io, (t.tile_w, t.tile_h, t.chunk, t.cap, t.persistent), status
 
 
 @pytest.fixture(scope="module")
@@ -124,7 +124,7 @@ def test_every_tiling_candidate_matches_mirror(mirrors):
         for p, (H, W) in enumerate(SIZES):
             got = im[o:o + 2 * H * W].reshape(2, H, W)
             o += 2 * H * W
-            assert np.array_equal(got, mirrors[p]["codes"]), (p, t.tile_w, t.tile_h, t.chunk, t.cap)
+            assert np.array_equal(got, mirrors[p]["codes"]), (p, t.tile_w, t.tile_h, t.chunk, t.cap, t.persistent)
         del ws, img
 
 

@@ -373,10 +373,14 @@ def _oracle_pair(args):
 
 
 def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
-    """Advect + render forward vs the backward from dL/dJ, on float images:
-    grad_512 (64 pairs of 512^2, RK4 x4, 3x3 blur) or dense_2048 (32 pairs of
-    2048^2, 0.1 ppp, d ~ U[2, 6], RK4 x8, 5x5 blur; the differentiable form
-    renders float images, so noise and codes are off)."""
+    """Advect + render forward vs the backward of an image loss, on float
+    images: grad_512 (64 pairs of 512^2, RK4 x4, 3x3 blur) or dense_2048 (32
+    pairs of 2048^2, 0.1 ppp, d ~ U[2, 6], RK4 x8, 5x5 blur; the differentiable
+    form renders float images, so noise and codes are off).  The loss is the
+    mean squared difference to a target pair rendered from the same particles
+    moved by a perturbed flow (the grid plus Gaussian noise of 5% of its rms,
+    seed 1): every step renders J, forms dL/dJ = 2 (J - T) / M and runs the
+    backward."""
     from workloads import get_workload
     wl = get_workload(name).with_(bits=0, noise_sigma=0.0)
     flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
@@ -384,15 +388,21 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
     x2 = torch.empty_like(P["x"])
     y2 = torch.empty_like(P["y"])
     img = torch.empty(batch.n_pixels, dtype=torch.float32, device=dev)
-    gJ = torch.randn(batch.n_pixels, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
     wsf = sp.alloc_workspace(batch, rprm)
     wsb = sp.alloc_workspace(batch, rprm, backward=True)
+    g = torch.Generator(device=dev).manual_seed(1)
+    flow_t = flow + 0.05 * flow.pow(2).mean().sqrt() * torch.randn(flow.shape, device=dev, generator=g)
+    sp.advect(batch, flow_t, aprm, P["x"], P["y"], x2, y2, wsf)
+    target = sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, None, wsf)
+    gJ = torch.empty_like(img)
+    scale = 2.0 / img.numel()
 
     def fwd():
         sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2, wsf)
         sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, img, wsf)
 
     def bwd():   # as the autograd wrapper calls it: the forward's frame-2 positions are reused
+        torch.sub(img, target, out=gJ).mul_(scale)                # the loss's own gradient (the caller's)
         sp.render_pair_backward(batch, flow, P["x"], P["y"], P["z"], P["d"], P["I0"], rprm, gJ, None, wsb, x2=x2, y2=y2)
 
     fwd()
@@ -405,9 +415,11 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
             fn()
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) / steps
-    del wsb, wsf, gJ, img
+    loss = float(((img - target) ** 2).mean())
+    del wsb, wsf, gJ, img, target, flow_t
     torch.cuda.empty_cache()
-    return {"fwd_ms": round(1000 * res["fwd"], 4), "bwd_ms": round(1000 * res["bwd"], 4),
+    return {"loss": "mse_vs_perturbed_flow_target", "loss_value": float(f"{loss:.6e}"),
+            "fwd_ms": round(1000 * res["fwd"], 4), "bwd_ms": round(1000 * res["bwd"], 4),
             "fwd_bwd_over_fwd": round((res["fwd"] + res["bwd"]) / res["fwd"], 3)}
 
 

@@ -206,6 +206,7 @@ sp::WorkspaceLayout workspace_layout(int32_t n_pairs, const sp::BatchTotals& T, 
     w.hist = o; o = align256(o + sizeof(uint32_t) * (size_t)T.hist);
     w.entries = o; o = align256(o + sizeof(int32_t) * (size_t)T.entries);
     w.records = o; o = align256(o + 2 * 16 * (size_t)T.n_span);
+    w.boxes = o; o = align256(o + 2 * 8 * (size_t)T.n_span);
     w.shapes = o; o = align256(o + 2 * 8 * (size_t)T.n_span);
     (void)backward;
     (void)ph;

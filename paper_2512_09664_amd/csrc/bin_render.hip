@@ -97,12 +97,16 @@ bin_layout(const synthpix_pair* __restrict__ pairs, int n_pairs, RenderConfig cf
 
 // ------------------------------------------------------------------ particle records
 
-// Per particle and frame: (x, y, d, Af) with Af = min(2^24 I0 exp(-z^2 / (2 s^2)),
-// 2^32 - 256).  d is replaced by -1 for particles that add nothing (I0 <= 0,
-// d <= 0 or not a number, non-finite position) or whose d exceeds d_max (flagged).
+// Per particle and frame: the record (x, y, kappa, Af) with kappa = 8 / (d d)
+// and Af = min(2^24 I0 exp(-z^2 / (2 s^2)), 2^32 - 256), and the patch box
+// |dx|, |dy| <= 1.5 d clipped to the image (computed once here for every tile
+// list and tile that uses the particle).  Particles that add nothing (I0 <= 0,
+// d <= 0 or not a number, non-finite position) or whose d exceeds d_max
+// (flagged) get an empty box.
 __global__ void __launch_bounds__(256)
 prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span, RenderArgs a,
-             float d_max, float4* __restrict__ rec0, float4* __restrict__ rec1, uint32_t* __restrict__ status)
+             float d_max, float4* __restrict__ rec0, float4* __restrict__ rec1, uint2* __restrict__ box0,
+             uint2* __restrict__ box1, uint32_t* __restrict__ status)
 {
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t g = g0 + threadIdx.x;
@@ -119,20 +123,23 @@ prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_spa
         a.d = a.iod->d;
         a.I0 = a.iod->I0;
     }
+    const int W = pairs[p].W, H = pairs[p].H;
     const float cs = 0.5f / (a.sheet_sigma * a.sheet_sigma);
     const float z = a.z[g], d = a.d[g], I0 = a.I0[g];
     const float x1 = a.x[0][g], y1 = a.y[0][g], x2 = a.x[1][g], y2 = a.y[1][g];
     const float Af = fixed_peak(I0 * expneg((z * z) * cs));
-    float dd = d;
-    if (!(I0 > 0.0f) || !(d > 0.0f)) dd = -1.0f;
-    if (dd > 0.0f && !(d <= d_max)) {
+    bool live = (I0 > 0.0f) && (d > 0.0f);
+    if (live && !(d <= d_max)) {
         atomicOr(status, SP_STATUS_D_ABOVE_MAX);
-        dd = -1.0f;
+        live = false;
     }
-    const float d1 = (__builtin_isfinite(x1) && __builtin_isfinite(y1)) ? dd : -1.0f;
-    const float d2 = (__builtin_isfinite(x2) && __builtin_isfinite(y2)) ? dd : -1.0f;
-    rec0[g] = make_float4(x1, y1, d1, Af);
-    rec1[g] = make_float4(x2, y2, d2, Af);
+    const float R = 1.5f * d;
+    const uint2 empty = make_uint2(EMPTY_BOX, EMPTY_BOX);
+    const float kap = live ? 8.0f / (d * d) : 0.0f;
+    rec0[g] = make_float4(x1, y1, kap, Af);
+    rec1[g] = make_float4(x2, y2, kap, Af);
+    box0[g] = live ? patch_box(x1, y1, R, R, W, H) : empty;
+    box1[g] = live ? patch_box(x2, y2, R, R, W, H) : empty;
 }
 
 // The full particle model's records (Eq. 1 with sigma_y and rho; frame-2
@@ -160,8 +167,9 @@ __device__ __forceinline__ float model_peak(float I0, float z, const RenderArgs&
 
 __global__ void __launch_bounds__(256)
 prep_records_model(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span, RenderArgs a, float d_max,
-                   float4* __restrict__ rec0, float4* __restrict__ rec1, float2* __restrict__ shp0,
-                   float2* __restrict__ shp1, uint32_t* __restrict__ status)
+                   float4* __restrict__ rec0, float4* __restrict__ rec1, uint2* __restrict__ box0,
+                   uint2* __restrict__ box1, float2* __restrict__ shp0, float2* __restrict__ shp1,
+                   uint32_t* __restrict__ status)
 {
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t g = g0 + threadIdx.x;
@@ -199,23 +207,28 @@ prep_records_model(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t
     }
     const float dd[2] = {d, d2}, ddy[2] = {dy, dy2}, rr[2] = {r, r2}, II[2] = {I1, I2};
     const float xx[2] = {x1, x2}, yy[2] = {y1, y2}, zz[2] = {z1, z2};
+    const int W = pairs[p].W, H = pairs[p].H;
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-        float de = dd[f];
-        if (!(II[f] > 0.0f) || !(dd[f] > 0.0f) || !(ddy[f] > 0.0f) || !__builtin_isfinite(xx[f]) ||
-            !__builtin_isfinite(yy[f]))
-            de = -1.0f;
-        if (de > 0.0f && !(dd[f] <= d_max && ddy[f] <= d_max)) {
+        bool live = (II[f] > 0.0f) && (dd[f] > 0.0f) && (ddy[f] > 0.0f);
+        if (live && !(dd[f] <= d_max && ddy[f] <= d_max)) {
             atomicOr(status, SP_STATUS_D_ABOVE_MAX);
-            de = -1.0f;
+            live = false;
         }
-        if (de > 0.0f && !(__builtin_fabsf(rr[f]) <= 0.99f)) {
+        if (live && !(__builtin_fabsf(rr[f]) <= 0.99f)) {
             atomicOr(status, SP_STATUS_BAD_SHAPE);
-            de = -1.0f;
+            live = false;
         }
-        const float4 rc = make_float4(xx[f], yy[f], de, fixed_peak(model_peak(II[f], zz[f], a)));
-        (f ? rec1 : rec0)[g] = rc;
-        if (a.aniso) (f ? shp1 : shp0)[g] = make_float2(ddy[f], rr[f]);
+        // om = 1 - rho^2; kappa_x = 8 / (om d^2), kappa_y = 8 / (om d_y^2),
+        // kappa_xy = -16 rho / (om d d_y) (0 for rho = 0: the separable form)
+        const float om = __builtin_fmaf(-rr[f], rr[f], 1.0f);
+        const float kx = live ? 8.0f / (om * (dd[f] * dd[f])) : 0.0f;
+        const float ky = live ? 8.0f / (om * (ddy[f] * ddy[f])) : 0.0f;
+        const float kxy = (live && rr[f] != 0.0f) ? (-16.0f * rr[f]) / (om * (dd[f] * ddy[f])) : 0.0f;
+        (f ? rec1 : rec0)[g] = make_float4(xx[f], yy[f], kx, fixed_peak(model_peak(II[f], zz[f], a)));
+        (f ? box1 : box0)[g] = live ? patch_box(xx[f], yy[f], 1.5f * dd[f], 1.5f * ddy[f], W, H)
+                                    : make_uint2(EMPTY_BOX, EMPTY_BOX);
+        if (a.aniso) (f ? shp1 : shp0)[g] = make_float2(ky, kxy);
     }
 }
 
@@ -223,11 +236,10 @@ prep_records_model(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t
 
 // ------------------------------------------------------------------ count / scatter
 
-template <bool SCATTER, bool ANISO>
+template <bool SCATTER>
 __global__ void __launch_bounds__(256)
 bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
-         const float4* __restrict__ rec0, const float4* __restrict__ rec1, const float2* __restrict__ shp0,
-         const float2* __restrict__ shp1, RenderConfig cfg, uint32_t* __restrict__ hist,
+         const uint2* __restrict__ box0, const uint2* __restrict__ box1, RenderConfig cfg, uint32_t* __restrict__ hist,
          const int64_t* __restrict__ tile_offset, int64_t tiles_total, int32_t* __restrict__ entries,
          unsigned n_chunks_total)
 {
@@ -247,26 +259,22 @@ bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__
     for (int t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = SCATTER ? gh[t] + (uint32_t)(toff[t] - seg0) : 0u;
     __syncthreads();
     const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
-    const float4* __restrict__ rec = f ? rec1 : rec0;
-    const float2* __restrict__ shp = f ? shp1 : shp0;
-    // BIN_ILP particles per thread and step: their record loads and LDS atomic
+    const uint2* __restrict__ bxs = f ? box1 : box0;
+    // BIN_ILP particles per thread and step: their box loads and LDS atomic
     // round trips overlap
     constexpr int BIN_ILP = 4;
     for (int i0 = chunk * cfg.chunk + threadIdx.x; i0 < i_end; i0 += BIN_ILP * blockDim.x) {
-        float4 r[BIN_ILP];
-        float ry[BIN_ILP];
+        uint2 r[BIN_ILP];
 #pragma unroll
         for (int q = 0; q < BIN_ILP; ++q) {
             const int i = i0 + q * blockDim.x;
-            r[q] = i < i_end ? rec[P.particle_offset + i] : make_float4(0.0f, 0.0f, -1.0f, 0.0f);
-            ry[q] = r[q].z;
-            if (ANISO && i < i_end) ry[q] = shp[P.particle_offset + i].x;
+            r[q] = i < i_end ? bxs[P.particle_offset + i] : make_uint2(EMPTY_BOX, EMPTY_BOX);
         }
 #pragma unroll
         for (int q = 0; q < BIN_ILP; ++q) {
             const int i = i0 + q * blockDim.x;
             int tx0, tx1, ty0, ty1;
-            if (!tile_rect(r[q], ry[q], P.H, P.W, cfg, PL.ntx, PL.nty, tx0, tx1, ty0, ty1)) continue;
+            if (!tile_rect(r[q], cfg, PL.ntx, PL.nty, tx0, tx1, ty0, ty1)) continue;
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     const uint32_t slot = atomicAdd(&lh[ty * PL.ntx + tx], 1u);
@@ -488,7 +496,8 @@ __device__ __forceinline__ uint32_t pack_box(int c0, int w, int r0, int h)
 template <int TW, int TH, int B, bool ANISO, bool PERSIST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PERSIST ? 6 : 8)))
 render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
-            const float4* __restrict__ rec0, const float4* __restrict__ rec1, const float2* __restrict__ shp0,
+            const float4* __restrict__ rec0, const float4* __restrict__ rec1, const uint2* __restrict__ box0,
+            const uint2* __restrict__ box1, const float2* __restrict__ shp0,
             const float2* __restrict__ shp1, EpilogueArgs a, int cap, int wm4,
             const uint32_t* __restrict__ tile_count, const int64_t* __restrict__ tile_offset,
             const int32_t* __restrict__ entries, int64_t tiles_total, uint32_t* __restrict__ status,
@@ -567,6 +576,7 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     const int cnt = (int)tile_count[item];
     const int64_t off = tile_offset[item];
     const float4* __restrict__ rec = f ? rec1 : rec0;
+    const uint2* __restrict__ bxs = f ? box1 : box0;
     const float2* __restrict__ shp = f ? shp1 : shp0;
 
     for (int k = threadIdx.x; k < (lay.acc_words >> 2); k += 256)
@@ -575,30 +585,33 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
 
     // the record of a thread's particle in the next pass is loaded one pass ahead,
     // so its two dependent loads overlap the current pass's factor and splat work
-    float4 next = make_float4(0.0f, 0.0f, -1.0f, 0.0f);
+    float4 next = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint2 next_bx = make_uint2(EMPTY_BOX, EMPTY_BOX);
     float2 next_sh = make_float2(0.0f, 0.0f);
     if ((int)threadIdx.x < min(cap, cnt)) {
         const int e = entries[off + threadIdx.x];
         next = rec[p_off + e];
+        next_bx = bxs[p_off + e];
         if (ANISO) next_sh = shp[p_off + e];
     }
     for (int base = 0; base < cnt; base += cap) {
         const int n = min(cap, cnt - base);
         const float4 r = next;
+        const uint2 pb = next_bx;
         const float2 rs = next_sh;
         if ((int)threadIdx.x < cap && base + cap + (int)threadIdx.x < cnt) {
             const int e = entries[off + base + cap + threadIdx.x];
             next = rec[p_off + e];
+            next_bx = bxs[p_off + e];
             if (ANISO) next_sh = shp[p_off + e];
         }
         __syncthreads();
-        // stage: one particle per thread
+        // stage: one particle per thread; its patch box (image pixels) clipped to the region
         int w = 0, h = 0, c0 = 0, r0 = 0;
         if ((int)threadIdx.x < n) {
-            const float R = 1.5f * r.z;
-            const float Ry = ANISO ? 1.5f * rs.x : R;
-            int a0, a1, b0, b1;
-            if (support_range(r.x, R, pW, a0, a1) && support_range(r.y, Ry, pH, b0, b1)) {
+            if (!box_empty(pb)) {
+                int a0 = (int)(pb.x & 0xffffu), a1 = (int)(pb.x >> 16);
+                int b0 = (int)(pb.y & 0xffffu), b1 = (int)(pb.y >> 16);
                 a0 = max(a0, rx0);
                 a1 = min(a1, rx0 + RW - 1);
                 b0 = max(b0, ry0);
@@ -615,14 +628,8 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
                     r0 = b0 - ry0;
                 }
             }
-            if (ANISO) {
-                const float om = __builtin_fmaf(-rs.y, rs.y, 1.0f);
-                stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (om * (r.z * r.z)), r.w);
-                stg2[threadIdx.x] = make_float2(8.0f / (om * (rs.x * rs.x)),
-                                                rs.y == 0.0f ? 0.0f : (-16.0f * rs.y) / (om * (r.z * rs.x)));
-            } else {
-                stg[threadIdx.x] = make_float4(r.x, r.y, 8.0f / (r.z * r.z), r.w);
-            }
+            stg[threadIdx.x] = r;                                   // (x, y, kappa_x, Af)
+            if (ANISO) stg2[threadIdx.x] = rs;                      // (kappa_y, kappa_xy)
             box[threadIdx.x] = pack_box(c0, w, r0, h);
             if (w > 0) {
                 const unsigned long long pk = (unsigned long long)r.w;
@@ -882,9 +889,9 @@ static void launch_tile_kernel(K kernel, dim3 grid, size_t lds, hipStream_t s, b
 
 template <int TW, int TH>
 static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const RenderArgs& a, const RenderConfig& cfg,
-                                const PairLayout* L, const float4* r0, const float4* r1, const float2* h0,
-                                const float2* h1, const uint32_t* tile_count, const int64_t* tile_offset,
-                                const int32_t* entries, int64_t tiles, uint32_t* status)
+                                const PairLayout* L, const float4* r0, const float4* r1, const uint2* b0,
+                                const uint2* b1, const float2* h0, const float2* h1, const uint32_t* tile_count,
+                                const int64_t* tile_offset, const int32_t* entries, int64_t tiles, uint32_t* status)
 {
     EpilogueArgs ea;
     ea.images = a.images;
@@ -897,16 +904,18 @@ static void launch_render_shape(dim3 grid, size_t lds, hipStream_t s, const Rend
     case B_:                                                                                                     \
         if (a.aniso)                                                                                             \
             launch_tile_kernel(render_tile<TW, TH, B_, true, false>, grid, lds, s, false, a.pairs, L, a.n_pairs, \
-                               r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles,    \
+                               r0, r1, b0, b1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries,   \
+                               tiles,                                                                            \
                                status, status + 8);                                                              \
         else if (cfg.persistent)                                                                                 \
             launch_tile_kernel(render_tile<TW, TH, B_, false, true>, grid, lds, s, true, a.pairs, L, a.n_pairs,  \
-                               r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries, tiles,    \
+                               r0, r1, b0, b1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset, entries,   \
+                               tiles,                                                                            \
                                status, status + 8);                                                              \
         else                                                                                                     \
             launch_tile_kernel(render_tile<TW, TH, B_, false, false>, grid, lds, s, false, a.pairs, L,           \
-                               a.n_pairs, r0, r1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count, tile_offset,         \
-                               entries, tiles, status, status + 8);                                              \
+                               a.n_pairs, r0, r1, b0, b1, h0, h1, ea, cfg.cap, cfg.wm4, tile_count,              \
+                               tile_offset, entries, tiles, status, status + 8);                                 \
         break;
     switch (cfg.apron) { SP_B(0) SP_B(1) SP_B(2) SP_B(3) default: break; }
 #undef SP_B
@@ -923,6 +932,8 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
     int32_t* entries = reinterpret_cast<int32_t*>(ws + wl.entries);
     float4* rec0 = reinterpret_cast<float4*>(ws + wl.records);
     float4* rec1 = rec0 + tot.n_span;
+    uint2* box0 = reinterpret_cast<uint2*>(ws + wl.boxes);
+    uint2* box1 = box0 + tot.n_span;
     float2* shp0 = reinterpret_cast<float2*>(ws + wl.shapes);
     float2* shp1 = shp0 + tot.n_span;
 
@@ -934,21 +945,18 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
         TimedScope ts("prep", s);
         if (a.model)
             hipLaunchKernelGGL(prep_records_model, dim3((unsigned)((tot.n_span + 255) / 256)), dim3(256), 0, s,
-                               a.pairs, a.n_pairs, tot.n_span, a, cfg.d_max, rec0, rec1, shp0, shp1, status);
+                               a.pairs, a.n_pairs, tot.n_span, a, cfg.d_max, rec0, rec1, box0, box1, shp0, shp1,
+                               status);
         else
             hipLaunchKernelGGL(prep_records, dim3((unsigned)((tot.n_span + 255) / 256)), dim3(256), 0, s, a.pairs,
-                               a.n_pairs, tot.n_span, a, cfg.d_max, rec0, rec1, status);
+                               a.n_pairs, tot.n_span, a, cfg.d_max, rec0, rec1, box0, box1, status);
     }
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
     const dim3 bgrid((unsigned)tot.chunks, 2);
     if (tot.chunks > 0) {
         TimedScope ts("bin_count", s);
-        if (a.aniso)
-            hipLaunchKernelGGL((bin_pass<false, true>), bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, rec0,
-                               rec1, shp0, shp1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
-        else
-            hipLaunchKernelGGL((bin_pass<false, false>), bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, rec0,
-                               rec1, shp0, shp1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
+        hipLaunchKernelGGL(bin_pass<false>, bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, box0, box1, cfg,
+                           hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
     }
     if (tot.tiles > 0) {
         TimedScope ts("bin_scan", s);
@@ -956,12 +964,8 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
     }
     if (tot.chunks > 0) {
         TimedScope ts("bin_scatter", s);
-        if (a.aniso)
-            hipLaunchKernelGGL((bin_pass<true, true>), bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, rec0,
-                               rec1, shp0, shp1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
-        else
-            hipLaunchKernelGGL((bin_pass<true, false>), bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, rec0,
-                               rec1, shp0, shp1, cfg, hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
+        hipLaunchKernelGGL(bin_pass<true>, bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, box0, box1, cfg,
+                           hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
     }
     return hipGetLastError();
 }
@@ -976,6 +980,8 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
     int32_t* entries = reinterpret_cast<int32_t*>(ws + wl.entries);
     float4* rec0 = reinterpret_cast<float4*>(ws + wl.records);
     float4* rec1 = rec0 + tot.n_span;
+    uint2* box0 = reinterpret_cast<uint2*>(ws + wl.boxes);
+    uint2* box1 = box0 + tot.n_span;
     float2* shp0 = reinterpret_cast<float2*>(ws + wl.shapes);
     float2* shp1 = shp0 + tot.n_span;
     const hipError_t e = launch_bins(a, cfg, tot, ws, wl, s);
@@ -986,8 +992,8 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
         const dim3 grid((unsigned)(2 * tot.tiles));
 #define SP_SHAPE(W_, H_)                                                                                        \
     if (cfg.tile_w == W_ && cfg.tile_h == H_)                                                                   \
-        launch_render_shape<W_, H_>(grid, lds, s, a, cfg, L, rec0, rec1, shp0, shp1, tile_count, tile_offset,   \
-                                    entries, tot.tiles, status);                                                \
+        launch_render_shape<W_, H_>(grid, lds, s, a, cfg, L, rec0, rec1, box0, box1, shp0, shp1, tile_count,   \
+                                    tile_offset, entries, tot.tiles, status);                                   \
     else
         SP_SHAPE(8, 8) SP_SHAPE(16, 16) SP_SHAPE(32, 16) SP_SHAPE(32, 32) SP_SHAPE(64, 16) SP_SHAPE(64, 32)
         SP_SHAPE(64, 64) SP_SHAPE(128, 32)

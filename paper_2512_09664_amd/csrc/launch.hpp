@@ -64,15 +64,28 @@ struct RenderConfig {
 // Totals of a batch (host side).
 // Tile rectangle touched by one particle record: its support, clipped to the
 // image, grown by the blur apron.  False when the particle adds nothing.
-// dy: the particle's second diameter (its patch half-height is 1.5 dy); the
-// isotropic path passes the record's own diameter.
-__device__ __forceinline__ bool tile_rect(const float4 r, float dy, int H, int W, const RenderConfig& cfg, int ntx,
-                                          int nty, int& tx0, int& tx1, int& ty0, int& ty1)
+// A particle's patch in image pixels, clipped to the image: columns c0 .. c1 in
+// the low and high halves of .x, rows r0 .. r1 in those of .y.  A particle that
+// adds nothing has c1 < c0 (EMPTY_BOX).
+constexpr uint32_t EMPTY_BOX = 1u;
+
+__device__ __forceinline__ uint2 patch_box(float x, float y, float Rx, float Ry, int W, int H)
 {
-    if (!(r.z > 0.0f)) return false;
     int c0, c1, r0, r1;
-    if (!support_range(r.x, 1.5f * r.z, W, c0, c1)) return false;
-    if (!support_range(r.y, 1.5f * dy, H, r0, r1)) return false;
+    if (!support_range(x, Rx, W, c0, c1) || !support_range(y, Ry, H, r0, r1)) return make_uint2(EMPTY_BOX, EMPTY_BOX);
+    return make_uint2((uint32_t)c0 | ((uint32_t)c1 << 16), (uint32_t)r0 | ((uint32_t)r1 << 16));
+}
+
+__device__ __forceinline__ bool box_empty(uint2 b) { return (b.x >> 16) < (b.x & 0xffffu); }
+
+// Tile rectangle touched by one particle's patch box, grown by the blur apron.
+// False when the particle adds nothing.
+__device__ __forceinline__ bool tile_rect(const uint2 bx, const RenderConfig& cfg, int ntx, int nty, int& tx0,
+                                          int& tx1, int& ty0, int& ty1)
+{
+    if (box_empty(bx)) return false;
+    const int c0 = (int)(bx.x & 0xffffu), c1 = (int)(bx.x >> 16);
+    const int r0 = (int)(bx.y & 0xffffu), r1 = (int)(bx.y >> 16);
     const int b = cfg.apron;
     tx0 = c0 - b < 0 ? 0 : (c0 - b) >> cfg.log_tw;
     ty0 = r0 - b < 0 ? 0 : (r0 - b) >> cfg.log_th;
@@ -100,8 +113,9 @@ struct WorkspaceLayout {
     size_t tile_offset;     // int64  [2 * tiles]
     size_t hist;            // uint32 [hist]
     size_t entries;         // int32  [entries]
-    size_t records;         // float4 [2 * n_span] per-frame particle records
-    size_t shapes;          // float2 [2 * n_span] per-frame (d_y, rho) of the anisotropic model
+    size_t records;         // float4 [2 * n_span] per-frame particle records (x, y, kappa_x, 2^24 A)
+    size_t boxes;           // uint2 [2 * n_span] per-frame patch boxes in image pixels
+    size_t shapes;          // float2 [2 * n_span] per-frame (kappa_y, kappa_xy) of the anisotropic model
     size_t total;
 };
 

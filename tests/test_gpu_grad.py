@@ -438,3 +438,44 @@ def test_backward_dense_2048_sampled(ra):
     # pairs with no lit particle get a zero flow gradient in the masked launch
     fo = batch.host[5].flow_offset
     assert not np.any(GS["flow"][fo:fo + flows[5].size])
+
+
+def test_mse_loss_against_perturbed_flow_target():
+    """The differentiable workload's loss: the mean squared difference between
+    the rendered pair and a target pair rendered from the same particles under a
+    perturbed flow (the grid plus Gaussian noise of 5% of its rms).  The
+    autograd gradient of every input equals the float64 oracle gradient of the
+    same loss (its dL/dJ formed from the oracle's own images)."""
+    sizes = [(40, 48), (24, 20)]
+    grids = [(10, 12), (8, 7)]
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, 24, 21)
+    rng = np.random.default_rng(1)
+    flows_t = [(f + 0.05 * np.sqrt(np.mean(f.astype(np.float64) ** 2)) * rng.standard_normal(f.shape))
+               .astype(np.float32) for f in flows]
+    flow_t_dev = gu.to_dev(np.concatenate([f.reshape(-1) for f in flows_t]))
+    rp = sp.render_params(0.5, 5.0, 1, 0.7, 0.0, 0, 0, 1.0, 2, "rk4")
+    inp = {k: v.clone().requires_grad_(True) for k, v in dev.items()}
+    fl = flow_dev.clone().requires_grad_(True)
+    img = sp.render_images(batch, fl, inp["x"], inp["y"], inp["z"], inp["d"], inp["I0"], 0.5, rp)
+    with torch.no_grad():
+        x2t, y2t = sp.advect(batch, flow_t_dev, rp.advect, dev["x"], dev["y"])
+        target = sp.render_pair(batch, dev["x"], dev["y"], x2t, y2t, dev["z"], dev["d"], dev["I0"], rp)
+    loss = ((img - target) ** 2).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    w = oep.blur_weights(1, rp.blur_sigma)
+    M = batch.n_pixels
+    fo = 0
+    for p, (H, W) in enumerate(sizes):
+        args = (P["x"][p], P["y"][p], P["z"][p], P["d"][p], P["I0"][p], 0.5)
+        J = ogr.forward_pair(*args, flows[p], H, W, 1.0, 2, "rk4", w, cutoff=True)
+        T = ogr.forward_pair(*args, flows_t[p], H, W, 1.0, 2, "rk4", w, cutoff=True)
+        gJ = 2.0 * (J - T) / M
+        ref = ogr.backward_pair(*args, flows[p], H, W, gJ, dt=1.0, substeps=2, integrator="rk4", w_blur=w,
+                                cutoff=True)
+        sl = slice(batch.host[p].particle_offset, batch.host[p].particle_offset + 24)
+        for name, key in (("x", "x1"), ("y", "y1"), ("z", "z"), ("d", "d"), ("I0", "I0")):
+            _close(gu.to_np(inp[name].grad)[sl], ref[key], f"pair {p} {key}", tol=1e-3)
+        n_f = flows[p].size
+        _close(gu.to_np(fl.grad)[fo:fo + n_f].reshape(flows[p].shape), ref["flow"], f"pair {p} flow", tol=1e-3)
+        fo += n_f

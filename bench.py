@@ -379,8 +379,8 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
     form renders float images, so noise and codes are off).  The loss is the
     mean squared difference to a target pair rendered from the same particles
     moved by a perturbed flow (the grid plus Gaussian noise of 5% of its rms,
-    seed 1): every step renders J, forms dL/dJ = 2 (J - T) / M and runs the
-    backward."""
+    seed 1): every step renders J, forms dL/dJ = 2 (J - T) / M in one pass
+    (synthpix_mse_grad) and runs the backward."""
     from workloads import get_workload
     wl = get_workload(name).with_(bits=0, noise_sigma=0.0)
     flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
@@ -402,7 +402,7 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
         sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, img, wsf)
 
     def bwd():   # as the autograd wrapper calls it: the forward's frame-2 positions are reused
-        torch.sub(img, target, out=gJ).mul_(scale)                # the loss's own gradient (the caller's)
+        sp.mse_grad(img, target, scale, out=gJ)                   # the loss's own gradient, one pass
         sp.render_pair_backward(batch, flow, P["x"], P["y"], P["z"], P["d"], P["I0"], rprm, gJ, None, wsb, x2=x2, y2=y2)
 
     fwd()
@@ -415,7 +415,7 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
             fn()
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) / steps
-    loss = float(((img - target) ** 2).mean())
+    loss = float(sp.mse_grad(img, target, scale, out=gJ, loss=True)[1])
     del wsb, wsf, gJ, img, target, flow_t
     torch.cuda.empty_cache()
     return {"loss": "mse_vs_perturbed_flow_target", "loss_value": float(f"{loss:.6e}"),

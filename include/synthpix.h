@@ -351,6 +351,20 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host,
                                               float* g_flow, void* workspace, size_t ws_bytes,
                                               void* stream);
 
+/* Image loss of a fitting loop through the generator (the acquisition and
+ * parameter co-design the Abstract and Introduction name): the mean squared
+ * difference L = sum_i (J_i - T_i)^2 / n of rendered float images J to a target
+ * T of the same layout, and its gradient dL/dJ_i = scale (J_i - T_i), with
+ * scale = 2 / n for L itself (the caller picks it, e.g. to weight several
+ * terms), in one pass.  J, T, grad: n device floats, 16-byte aligned (NULL
+ * allowed for n = 0); grad may be J or T itself.  loss: optional (NULL: skipped) device double receiving
+ * sum_i (J_i - T_i)^2 / n, summed in a fixed order (bit-reproducible); it
+ * needs the workspace: 256-byte aligned device memory of
+ * synthpix_mse_workspace_size(n) bytes (NULL when loss is NULL). */
+size_t synthpix_mse_workspace_size(int64_t n);
+synthpix_status synthpix_mse_grad(const float* J, const float* T, int64_t n, float scale, float* grad,
+                                  double* loss, void* workspace, size_t ws_bytes, void* stream);
+
 /* Allocation-free form of synthpix_render_pair, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same inputs, outputs and results as

@@ -114,6 +114,8 @@ SIGNATURES = {
     "synthpix_flow_field": [_PP, _P, ctypes.c_int32, _P, _P, _P],
     "synthpix_histogram_workspace_size": [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "synthpix_histogram_match": [_PP, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P],
+    "synthpix_mse_workspace_size": [ctypes.c_int64],
+    "synthpix_mse_grad": [_P, _P, ctypes.c_int64, ctypes.c_float, _P, _P, _P, ctypes.c_size_t, _P],
     "synthpix_seed_shape": [_PP, _P, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.c_float, ctypes.c_float,
                             ctypes.c_uint64, _P, _P, _P],
     "synthpix_advect_workspace_size": [_PP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
@@ -135,7 +137,8 @@ SIGNATURES = {
     "synthpix_plan_tiling": [_P, ctypes.POINTER(Tiling)],
     "synthpix_plan_destroy": [_P],
 }
-_RESTYPES = {"synthpix_version": ctypes.c_int32, "synthpix_last_error": ctypes.c_char_p}
+_RESTYPES = {"synthpix_version": ctypes.c_int32, "synthpix_last_error": ctypes.c_char_p,
+             "synthpix_mse_workspace_size": ctypes.c_size_t}
 
 _lib = None
 

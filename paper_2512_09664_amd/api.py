@@ -254,6 +254,31 @@ def histogram_match(batch: PairBatch, images: torch.Tensor, target: torch.Tensor
     return workspace
 
 
+def mse_grad(J: torch.Tensor, T: torch.Tensor, scale: Optional[float] = None, out=None, loss: bool = False,
+             workspace=None):
+    """Run ``synthpix_mse_grad``: dL/dJ = scale (J - T) (scale 2 / n by default,
+    the gradient of the mean squared difference) into ``out`` (new if None).
+    With ``loss``, also the mean of (J - T)^2 as a float64 device scalar;
+    returns (grad, loss or None)."""
+    _need_cuda(J, T)
+    n = J.numel()
+    if T.numel() != n or J.dtype != torch.float32 or T.dtype != torch.float32:
+        raise ValueError("J and T must be float32 tensors with the same number of elements")
+    out = torch.empty_like(J) if out is None else out
+    _need_cuda(out)
+    lv = None
+    ws_n = 0
+    if loss:
+        lv = torch.empty((), dtype=torch.float64, device=J.device)
+        if workspace is None:
+            workspace = torch.empty(max(L.load().synthpix_mse_workspace_size(n), 256), dtype=torch.uint8,
+                                    device=J.device)
+        ws_n = workspace.numel()
+    L.check(L.load().synthpix_mse_grad(_ptr(J), _ptr(T), n, float(2.0 / max(n, 1) if scale is None else scale),
+                                       _ptr(out), _ptr(lv), _ptr(workspace) if loss else None, ws_n, _stream()))
+    return out, lv
+
+
 def _extras(dy, rho, z2):
     if dy is None and rho is None and z2 is None:
         return None

@@ -225,10 +225,10 @@ int64_t flow_span(const synthpix_pair* ph, int32_t n_pairs)
 
 // Backward workspace: particle-major, no bins.
 struct BwdLayout {
-    size_t status, scale, x2, y2, gx2, gy2, sheet, sheet_part, bound_part, fixed, eblur, total;
+    size_t status, scale, x2, y2, gx2, gy2, sheet, sheet_part, bound_part, fixed, eblur, parts, total;
 };
 
-BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs, int64_t n_eblur)
+BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs, int64_t n_eblur, bool tile)
 {
     BwdLayout w{};
     size_t o = 0;
@@ -244,16 +244,18 @@ BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs, int64_t n_
     w.bound_part = o; o = align256(o + sizeof(float) * 2 * sp::BWD_SLICES * (size_t)n_pairs);
     w.fixed = o; o = align256(o + sizeof(uint64_t) * (size_t)n_flow);
     w.eblur = o; o = align256(o + sizeof(float) * (size_t)n_eblur);
+    w.parts = o; o = align256(o + (tile ? 2 * 16 * (size_t)n_span : 0));
     w.total = o;
     return w;
 }
 
 // Elements of the blurred-gradient images the backward keeps (B^T dL/dJ, the
-// images' layout) when the blur is wide enough (radius >= 2) for the gather to
-// pay for a per-pixel pass, else none.
-int64_t eblur_span(const synthpix_pair* ph, int32_t n_pairs, int blur_radius)
+// images' layout): for any blur under the tile-major gather, else when the blur
+// is wide enough (radius >= 2) for the particle-major gather to pay for a
+// per-pixel pass; otherwise none.
+int64_t eblur_span(const synthpix_pair* ph, int32_t n_pairs, int blur_radius, bool tile)
 {
-    if (blur_radius < 2) return 0;
+    if (blur_radius < (tile ? 1 : 2)) return 0;
     int64_t span = 0;
     for (int32_t p = 0; p < n_pairs; ++p)
         span = std::max<int64_t>(span, ph[p].image_offset + 2 * (int64_t)ph[p].H * ph[p].W);
@@ -399,6 +401,25 @@ size_t order_bytes(const synthpix_pair* ph, int32_t n_pairs)
     return order_layout(n_pairs, T, 0).total;
 }
 
+// Backward workspace: the gradient layout, then the frame-1 home-block order
+// and, for the tile-major gather, the frame-2 one.
+struct BwdPlan {
+    BwdLayout wl;
+    size_t ob;
+    bool tile;
+    size_t total;
+};
+
+BwdPlan bwd_plan(const synthpix_pair* ph, int32_t n_pairs, int64_t span, const synthpix_render_params& rp)
+{
+    BwdPlan b{};
+    b.ob = order_bytes(ph, n_pairs);
+    b.tile = sp::tile_gather_fits(rp.d_max, order_config(ph, n_pairs).log_tw, rp.blur_radius);
+    b.wl = bwd_layout(span, flow_span(ph, n_pairs), n_pairs, eblur_span(ph, n_pairs, rp.blur_radius, b.tile), b.tile);
+    b.total = b.wl.total + b.ob * (b.tile ? 2 : 1);
+    return b;
+}
+
 // Builds the home-block order of (x, y) in `ws` at byte offset `base` and
 // returns it for the advection launch.
 hipError_t enqueue_order(const synthpix_pair* ph, const synthpix_pair* pd, int32_t n_pairs, const float* x,
@@ -413,6 +434,8 @@ hipError_t enqueue_order(const synthpix_pair* ph, const synthpix_pair* pd, int32
     out->entries = reinterpret_cast<const int32_t*>(ws + ol.entries);
     out->log_block = cfg.log_tw;
     out->blocks = T.tiles;
+    out->count = reinterpret_cast<const uint32_t*>(ws + ol.tile_count);
+    out->offset = reinterpret_cast<const int64_t*>(ws + ol.tile_offset);
     return sp::launch_order(pd, n_pairs, x, y, cfg, T, ws, ol, s, iod);
 }
 
@@ -456,8 +479,7 @@ synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t
     const size_t ob = order_bytes(pairs_host, n_pairs);
     if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (backward) {
-        *bytes_out = bwd_layout(span, flow_span(pairs_host, n_pairs), n_pairs,
-                                eblur_span(pairs_host, n_pairs, rp->blur_radius)).total + ob;
+        *bytes_out = bwd_plan(pairs_host, n_pairs, span, *rp).total;
         return SP_OK;
     }
     const sp::RenderConfig cfg = make_config(*rp, t);
@@ -702,6 +724,33 @@ synthpix_status synthpix_render_pair(const synthpix_pair* pairs_host, const synt
     return SP_OK;
 }
 
+size_t synthpix_mse_workspace_size(int64_t n)
+{
+    (void)n;
+    return align256(sizeof(double) * sp::MSE_BLOCKS);
+}
+
+synthpix_status synthpix_mse_grad(const float* J, const float* T, int64_t n, float scale, float* grad,
+                                  double* loss, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (n < 0) return fail(SP_ERR_INVALID_ARG, "n must be >= 0");
+    if ((n > 0 && (!J || !T || !grad)) || !aligned(J, 16) || !aligned(T, 16) || !aligned(grad, 16))
+        return fail(SP_ERR_INVALID_ARG, "J, T and grad must be 16-byte aligned device pointers (non-NULL for n > 0)");
+    if (!std::isfinite(scale)) return fail(SP_ERR_INVALID_ARG, "scale must be finite");
+    if (loss) {
+        if (!aligned(loss, 8)) return fail(SP_ERR_INVALID_ARG, "loss must be an 8-byte aligned device pointer");
+        if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+        if (ws_bytes < synthpix_mse_workspace_size(n))
+            return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes,
+                        synthpix_mse_workspace_size(n));
+    }
+    if (n == 0 && !loss) return SP_OK;
+    const hipError_t e = sp::launch_mse_grad(J, T, n, scale, grad, loss, static_cast<double*>(workspace),
+                                             as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "loss gradient launch");
+    return SP_OK;
+}
+
 synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
                                               int32_t n_pairs, const synthpix_tiling* tiling, const float* flow,
                                               const float* x1, const float* y1, const float* x2,
@@ -733,22 +782,19 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     if (g_sheet_total && !dev_ptr_ok(g_sheet_total))
         return fail(SP_ERR_INVALID_ARG, "g_sheet_total must be NULL or a 4-byte aligned device pointer");
     const int64_t n_flow = flow_span(pairs_host, n_pairs);
-    const int64_t n_eblur = eblur_span(pairs_host, n_pairs, rp->blur_radius);
-    const BwdLayout wl = bwd_layout(span, n_flow, n_pairs, n_eblur);
-    const size_t ob = order_bytes(pairs_host, n_pairs);
-    if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
+    const BwdPlan bp = bwd_plan(pairs_host, n_pairs, span, *rp);
+    const BwdLayout& wl = bp.wl;
+    if (!bp.ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-    if (ws_bytes < wl.total + ob)
-        return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, wl.total + ob);
+    if (ws_bytes < bp.total)
+        return fail(SP_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, bp.total);
     char* ws = static_cast<char*>(workspace);
-    sp::AdvectOrder a_order_tmp{nullptr, nullptr};
+    hipStream_t hs = as_stream(stream);
+    sp::BwdArgs a{};
     {
-        const hipError_t e = enqueue_order(pairs_host, pairs_dev, n_pairs, x1, y1, ws, wl.total, as_stream(stream),
-                                           &a_order_tmp);
+        const hipError_t e = enqueue_order(pairs_host, pairs_dev, n_pairs, x1, y1, ws, wl.total, hs, &a.order);
         if (e != hipSuccess) return hip_fail(e, "backward order launch");
     }
-    sp::BwdArgs a{};
-    a.order = a_order_tmp;
     a.pairs = pairs_dev;
     a.n_pairs = n_pairs;
     a.flow = flow;
@@ -759,11 +805,25 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.x2 = x2 ? x2 : a.x2w;
     a.y2 = y2 ? y2 : a.y2w;
     a.recompute_x2 = x2 == nullptr;
+    if (bp.tile) {
+        // the tile gather groups frame 2 by its own positions: recompute them
+        // first when the caller did not pass them, then order them
+        if (a.recompute_x2) {
+            const hipError_t e = sp::launch_advect(pairs_dev, n_pairs, span, flow, rp->advect, x1, y1, a.x2w, a.y2w,
+                                                   hs, a.order);
+            if (e != hipSuccess) return hip_fail(e, "backward advect launch");
+            a.recompute_x2 = false;
+        }
+        const hipError_t e = enqueue_order(pairs_host, pairs_dev, n_pairs, a.x2, a.y2, ws, wl.total + bp.ob, hs,
+                                           &a.order2);
+        if (e != hipSuccess) return hip_fail(e, "backward order launch");
+        a.parts = reinterpret_cast<float4*>(ws + wl.parts);
+    }
     a.z = z;
     a.d = d;
     a.I0 = I0;
     a.grad = grad_images;
-    a.eblur = n_eblur ? reinterpret_cast<float*>(ws + wl.eblur) : nullptr;
+    a.eblur = wl.parts > wl.eblur ? reinterpret_cast<float*>(ws + wl.eblur) : nullptr;
     a.g_x1 = g_x1;
     a.g_y1 = g_y1;
     a.g_z = g_z;
@@ -788,7 +848,7 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
         a.max_w = std::max(a.max_w, (int)pairs_host[p].W);
     }
     const hipError_t e = sp::launch_backward(a, span, n_flow, rp->advect, rp->blur_radius,
-                                             sample_exponent(span, rp->advect), as_stream(stream));
+                                             sample_exponent(span, rp->advect), hs);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return SP_OK;
 }

@@ -31,11 +31,12 @@ constexpr int BG = 16;             // lanes per particle in the gather
 constexpr int BPW = 256 / BG;      // particles per workgroup
 constexpr int GROWS = 8;           // patch rows loaded per batch (independent loads in flight)
 
-// BT table slots cover the pixel range (<= 3 d_max + 3 pixels) plus 4 b of zero padding.
-template <int BT>
+// BT table slots cover the pixel range (<= 3 d_max + 3 pixels) plus 4 b of zero
+// padding; the raw row factors are kept only where a blur is folded in (RY).
+template <int BT, bool RY = true>
 struct GatherLds {
     float rx[BPW][3][BT];          // raw column factors gx dx^k, k = 0, 1, 2 (slot = c - c0 + 2b)
-    float ry[BPW][3][BT];
+    float ry[RY ? BPW : 1][3][RY ? BT : 1];
     float4 ty[BPW][BT];            // blurred row tables (Ty0, Ty1, Ty2, 0)
 };
 
@@ -91,6 +92,191 @@ __device__ __forceinline__ bool cover_range(float p, float R, int n, int& lo, in
     return lo <= hi;
 }
 
+// One lane group's sums for one frame of its particle: the raw factor tables,
+// the blurred row tables (B > 0) and the gather
+//     S0 = sum e G,  Sx = sum e G dx,  Sy = sum e G dy,  Sr = sum e G (dx^2 + dy^2)
+// over the blurred support inside the image, reading pixel (r, c) of the
+// frame's dL/dJ (B > 0) or B^T dL/dJ (B = 0) at src[(r - sr) * stride + (c - sc)]
+// (global memory, or a region staged in LDS).  Every lane returns the group's
+// sums.  on: the particle is valid and its support [c0, c1] x [r0, r1] is not
+// empty.
+template <int B, int BT, bool RY>
+__device__ __forceinline__ float4 frame_sums(GatherLds<BT, RY>& S, int grp, int lane, bool on, float x, float y,
+                                             float kap, float R, int c0, int c1, int r0, int r1, int W, int H,
+                                             const float* __restrict__ src, int64_t stride, int sr, int sc,
+                                             const float* blur_w)
+{
+    // raw factor tables over the slots the gather reads, 0 .. max(c1 - c0, r1 - r0)
+    // + 4b (zeros outside the support); a group stops after its last one
+    const int n_raw = on ? max(c1 - c0, r1 - r0) + 4 * B + 1 : 0;
+#pragma unroll
+    for (int m = 0; m < BT / BG; ++m) {
+        if (BG * m >= n_raw) break;
+        const int slot = lane + BG * m;
+        const int c = c0 - 2 * B + slot;
+        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+        const float dx = ((float)c + 0.5f) - x;
+        if (on && c >= c0 && c <= c1 && __builtin_fabsf(dx) <= R) {
+            v0 = expneg_hw(kap * (dx * dx));
+            v1 = v0 * dx;
+            v2 = v1 * dx;
+        }
+        S.rx[grp][0][slot] = v0;
+        S.rx[grp][1][slot] = v1;
+        S.rx[grp][2][slot] = v2;
+        const int r = r0 - 2 * B + slot;
+        float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+        const float dy = ((float)r + 0.5f) - y;
+        if (on && r >= r0 && r <= r1 && __builtin_fabsf(dy) <= R) {
+            u0 = expneg_hw(kap * (dy * dy));
+            u1 = u0 * dy;
+            u2 = u1 * dy;
+        }
+        if constexpr (B == 0) {
+            S.ty[grp][slot] = make_float4(u0, u1, u2, 0.0f);
+        } else {
+            static_assert(RY, "a folded blur needs the raw row factors");
+            S.ry[grp][0][slot] = u0;
+            S.ry[grp][1][slot] = u1;
+            S.ry[grp][2][slot] = u2;
+        }
+    }
+    group_sync();
+    if constexpr (B > 0) {
+        // blurred row tables (the column ones are formed per column in the gather);
+        // table slot t is pixel r0 - b + t; raw slot t + 2b - k' holds pixel q - (k' - b)
+        const int n_ty = on ? (r1 - r0 + 1) + 2 * B : 0;
+#pragma unroll
+        for (int m = 0; m < BT / BG; ++m) {
+            if (BG * m >= n_ty) break;
+            const int t = lane + BG * m;
+            if (t < BT - 2 * B) {
+                float Y[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int k = 0; k <= 2 * B; ++k) {
+                    const float w = blur_w[k];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Y[j] = __builtin_fmaf(w, S.ry[grp][j][t + 2 * B - k], Y[j]);
+                }
+                S.ty[grp][t] = make_float4(Y[0], Y[1], Y[2], 0.0f);
+            }
+        }
+        group_sync();
+    }
+
+    // gather: sum_q (dL/dJ)_q Ty(r) Tx(c) over the blurred support, inside the
+    // image.  The column factors are constant along a column, so each lane
+    // first forms P_j = sum_r (dL/dJ) Ty_j(r) down a column, or a slice of one
+    // (three FMAs per pixel), and applies Tx afterwards.  Columns go to lanes
+    // in blocks of 16; a block of m < 16 columns splits its rows into
+    // 16 / m' slices (m' = m rounded up to a power of two), so the lanes a
+    // narrow block would leave idle shorten its walk instead.
+    float s0 = 0.0f, s_x = 0.0f, s_y = 0.0f, s_r = 0.0f;
+    if (on) {
+        const int nt = (c1 - c0 + 1) + 2 * B, nu = (r1 - r0 + 1) + 2 * B;
+        const int tlo = B - c0 > 0 ? B - c0 : 0;
+        const int thi = nt < W - c0 + B ? nt : W - c0 + B;
+        const int ulo = B - r0 > 0 ? B - r0 : 0;
+        const int uhi = nu < H - r0 + B ? nu : H - r0 + B;
+        const float(*T)[BT] = S.rx[grp];
+        const int ncol = thi - tlo, nrow = uhi - ulo;
+        for (int cb = 0; cb < ncol; cb += BG) {
+            const int m = ncol - cb < BG ? ncol - cb : BG;
+            const int lm = m > 8 ? 4 : m > 4 ? 3 : m > 2 ? 2 : m > 1 ? 1 : 0;   // log2 m'
+            const int cl = lane & ((1 << lm) - 1);
+            const int per = (nrow + (BG >> lm) - 1) >> (4 - lm);                // rows per slice
+            const int ua = ulo + (lane >> lm) * per;
+            const int ub = ua + per < uhi ? ua + per : uhi;
+            if (cl >= m || ua >= ub) continue;
+            const int t = tlo + cb + cl;
+            // walk down the column slice with a row pointer: whole batches of GROWS
+            // rows (their loads issued together), then batches of 4, 2 and 1
+            const float* __restrict__ q = src + (int64_t)(r0 - B + ua - sr) * stride + (c0 - B + t - sc);
+            float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
+            int u = ua;
+#pragma unroll 1
+            for (; u + GROWS <= ub; u += GROWS) {
+                float e[GROWS];
+#pragma unroll
+                for (int k = 0; k < GROWS; ++k) {
+                    e[k] = *q;
+                    q += stride;
+                }
+#pragma unroll
+                for (int k = 0; k < GROWS; ++k) {
+                    const float4 ty = S.ty[grp][u + k];
+                    P0 = __builtin_fmaf(ty.x, e[k], P0);
+                    P1 = __builtin_fmaf(ty.y, e[k], P1);
+                    P2 = __builtin_fmaf(ty.z, e[k], P2);
+                }
+            }
+#pragma unroll
+            for (int nb = GROWS / 2; nb >= 1; nb >>= 1) {
+                if (ub - u >= nb) {
+                    float e[GROWS / 2];
+#pragma unroll
+                    for (int k = 0; k < nb; ++k) {
+                        e[k] = *q;
+                        q += stride;
+                    }
+#pragma unroll
+                    for (int k = 0; k < nb; ++k) {
+                        const float4 ty = S.ty[grp][u + k];
+                        P0 = __builtin_fmaf(ty.x, e[k], P0);
+                        P1 = __builtin_fmaf(ty.y, e[k], P1);
+                        P2 = __builtin_fmaf(ty.z, e[k], P2);
+                    }
+                    u += nb;
+                }
+            }
+            // blurred column factors of this column, from the raw ones
+            float X0 = 0.0f, X1 = 0.0f, X2 = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= 2 * B; ++k) {
+                const float w = B > 0 ? blur_w[k] : 1.0f;
+                X0 = __builtin_fmaf(w, T[0][t + 2 * B - k], X0);
+                X1 = __builtin_fmaf(w, T[1][t + 2 * B - k], X1);
+                X2 = __builtin_fmaf(w, T[2][t + 2 * B - k], X2);
+            }
+            s0 = __builtin_fmaf(P0, X0, s0);
+            s_x = __builtin_fmaf(P0, X1, s_x);
+            s_y = __builtin_fmaf(P1, X0, s_y);
+            s_r = __builtin_fmaf(P0, X2, __builtin_fmaf(P2, X0, s_r));
+        }
+    }
+    const float4 out = make_float4(group_sum(s0), group_sum(s_x), group_sum(s_y), group_sum(s_r));
+    group_sync();
+    return out;
+}
+
+// Gradients of one particle from its two frames' sums.
+struct ParticleGrads {
+    float gx1, gy1, gx2, gy2, gd, gz, gI0, sheet;
+};
+
+__device__ __forceinline__ ParticleGrads particle_grads(float z, float d, float I0, float sheet_sigma, float4 f0,
+                                                        float4 f1)
+{
+    const float kap = 8.0f / (d * d);
+    const float sum0 = f0.x + f1.x, sumr = f0.w + f1.w;
+    const float s = sheet_sigma;
+    const float Sz = expneg((z * z) * (0.5f / (s * s)));
+    const float A = I0 * Sz;
+    const float k2 = 2.0f * kap;                // d/dx of -kap dx^2 is 2 kap dx
+    ParticleGrads o;
+    o.gx1 = A * k2 * f0.y;
+    o.gy1 = A * k2 * f0.z;
+    o.gx2 = A * k2 * f1.y;
+    o.gy2 = A * k2 * f1.z;
+    o.gd = A * (k2 / d) * sumr;                 // d kap / d d = -2 kap / d
+    o.gI0 = sum0 * Sz;
+    o.gz = sum0 * A * (-z / (s * s));
+    o.sheet = sum0 * A * ((z * z) / (s * s * s));
+    return o;
+}
+
+// Particle-major gather: 16 lanes per particle read their patch rows of the
+// frame's gradient image from global memory (any diameter bound and blur).
 template <int B, int BT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 32 ? 7 : 4)))
 bwd_gather(BwdArgs a, int64_t n_span)
@@ -129,8 +315,7 @@ bwd_gather(BwdArgs a, int64_t n_span)
     }
     const float kap = 8.0f / (d * d);
     const float R = 1.5f * d;
-    float sum0 = 0.0f, sumr = 0.0f, sx[2] = {0.0f, 0.0f}, sy[2] = {0.0f, 0.0f};
-
+    float4 fs[2];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
         float x = 0.0f, y = 0.0f;
@@ -141,150 +326,8 @@ bwd_gather(BwdArgs a, int64_t n_span)
         int c0 = 0, c1 = -1, r0 = 0, r1 = -1;
         bool on = valid && cover_range(x, R, W, c0, c1);
         on = on && cover_range(y, R, H, r0, r1);
-
-        // raw factor tables over the slots the gather reads, 0 .. max(c1 - c0, r1 - r0)
-        // + 4b (zeros outside the support); a group stops after its last one
-        const int n_raw = on ? max(c1 - c0, r1 - r0) + 4 * B + 1 : 0;
-#pragma unroll
-        for (int m = 0; m < BT / BG; ++m) {
-            if (BG * m >= n_raw) break;
-            const int slot = lane + BG * m;
-            const int c = c0 - 2 * B + slot;
-            float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
-            const float dx = ((float)c + 0.5f) - x;
-            if (on && c >= c0 && c <= c1 && __builtin_fabsf(dx) <= R) {
-                v0 = expneg_hw(kap * (dx * dx));
-                v1 = v0 * dx;
-                v2 = v1 * dx;
-            }
-            S.rx[grp][0][slot] = v0;
-            S.rx[grp][1][slot] = v1;
-            S.rx[grp][2][slot] = v2;
-            const int r = r0 - 2 * B + slot;
-            float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
-            const float dy = ((float)r + 0.5f) - y;
-            if (on && r >= r0 && r <= r1 && __builtin_fabsf(dy) <= R) {
-                u0 = expneg_hw(kap * (dy * dy));
-                u1 = u0 * dy;
-                u2 = u1 * dy;
-            }
-            if (B == 0) {
-                S.ty[grp][slot] = make_float4(u0, u1, u2, 0.0f);
-            } else {
-                S.ry[grp][0][slot] = u0;
-                S.ry[grp][1][slot] = u1;
-                S.ry[grp][2][slot] = u2;
-            }
-        }
-        group_sync();
-        if (B > 0) {
-            // blurred row tables (the column ones are formed per column in the gather);
-            // table slot t is pixel r0 - b + t; raw slot t + 2b - k' holds pixel q - (k' - b)
-            const int n_ty = on ? (r1 - r0 + 1) + 2 * B : 0;
-#pragma unroll
-            for (int m = 0; m < BT / BG; ++m) {
-                if (BG * m >= n_ty) break;
-                const int t = lane + BG * m;
-                if (t < BT - 2 * B) {
-                    float Y[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-                    for (int k = 0; k <= 2 * B; ++k) {
-                        const float w = a.blur_w[k];
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) Y[j] = __builtin_fmaf(w, S.ry[grp][j][t + 2 * B - k], Y[j]);
-                    }
-                    S.ty[grp][t] = make_float4(Y[0], Y[1], Y[2], 0.0f);
-                }
-            }
-            group_sync();
-        }
-
-        // gather: sum_q (dL/dJ)_q Ty(r) Tx(c) over the blurred support, inside the
-        // image.  The column factors are constant along a column, so each lane
-        // first forms P_j = sum_r (dL/dJ) Ty_j(r) down a column, or a slice of one
-        // (three FMAs per pixel), and applies Tx afterwards.  Columns go to lanes
-        // in blocks of 16; a block of m < 16 columns splits its rows into
-        // 16 / m' slices (m' = m rounded up to a power of two), so the lanes a
-        // narrow block would leave idle shorten its walk instead.
-        float s0 = 0.0f, s_x = 0.0f, s_y = 0.0f, s_r = 0.0f;
-        if (on) {
-            const int nt = (c1 - c0 + 1) + 2 * B, nu = (r1 - r0 + 1) + 2 * B;
-            const int tlo = B - c0 > 0 ? B - c0 : 0;
-            const int thi = nt < W - c0 + B ? nt : W - c0 + B;
-            const int ulo = B - r0 > 0 ? B - r0 : 0;
-            const int uhi = nu < H - r0 + B ? nu : H - r0 + B;
-            const float* __restrict__ gimg = a.grad + img + (int64_t)f * H * W;
-            const float(*T)[BT] = S.rx[grp];
-            const int ncol = thi - tlo, nrow = uhi - ulo;
-            for (int cb = 0; cb < ncol; cb += BG) {
-                const int m = ncol - cb < BG ? ncol - cb : BG;
-                const int lm = m > 8 ? 4 : m > 4 ? 3 : m > 2 ? 2 : m > 1 ? 1 : 0;   // log2 m'
-                const int cl = lane & ((1 << lm) - 1);
-                const int per = (nrow + (BG >> lm) - 1) >> (4 - lm);                // rows per slice
-                const int ua = ulo + (lane >> lm) * per;
-                const int ub = ua + per < uhi ? ua + per : uhi;
-                if (cl >= m || ua >= ub) continue;
-                const int t = tlo + cb + cl;
-                // walk down the column slice with a row pointer: whole batches of GROWS
-                // rows (their loads issued together), then batches of 4, 2 and 1
-                const float* __restrict__ q = gimg + (int64_t)(r0 - B + ua) * W + (c0 - B + t);
-                float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
-                int u = ua;
-#pragma unroll 1
-                for (; u + GROWS <= ub; u += GROWS) {
-                    float e[GROWS];
-#pragma unroll
-                    for (int k = 0; k < GROWS; ++k) {
-                        e[k] = *q;
-                        q += W;
-                    }
-#pragma unroll
-                    for (int k = 0; k < GROWS; ++k) {
-                        const float4 ty = S.ty[grp][u + k];
-                        P0 = __builtin_fmaf(ty.x, e[k], P0);
-                        P1 = __builtin_fmaf(ty.y, e[k], P1);
-                        P2 = __builtin_fmaf(ty.z, e[k], P2);
-                    }
-                }
-#pragma unroll
-                for (int nb = GROWS / 2; nb >= 1; nb >>= 1) {
-                    if (ub - u >= nb) {
-                        float e[GROWS / 2];
-#pragma unroll
-                        for (int k = 0; k < nb; ++k) {
-                            e[k] = *q;
-                            q += W;
-                        }
-#pragma unroll
-                        for (int k = 0; k < nb; ++k) {
-                            const float4 ty = S.ty[grp][u + k];
-                            P0 = __builtin_fmaf(ty.x, e[k], P0);
-                            P1 = __builtin_fmaf(ty.y, e[k], P1);
-                            P2 = __builtin_fmaf(ty.z, e[k], P2);
-                        }
-                        u += nb;
-                    }
-                }
-                // blurred column factors of this column, from the raw ones
-                float X0 = 0.0f, X1 = 0.0f, X2 = 0.0f;
-#pragma unroll
-                for (int k = 0; k <= 2 * B; ++k) {
-                    const float w = B > 0 ? a.blur_w[k] : 1.0f;
-                    X0 = __builtin_fmaf(w, T[0][t + 2 * B - k], X0);
-                    X1 = __builtin_fmaf(w, T[1][t + 2 * B - k], X1);
-                    X2 = __builtin_fmaf(w, T[2][t + 2 * B - k], X2);
-                }
-                s0 = __builtin_fmaf(P0, X0, s0);
-                s_x = __builtin_fmaf(P0, X1, s_x);
-                s_y = __builtin_fmaf(P1, X0, s_y);
-                s_r = __builtin_fmaf(P0, X2, __builtin_fmaf(P2, X0, s_r));
-            }
-        }
-        sum0 += group_sum(s0);
-        sx[f] = group_sum(s_x);
-        sy[f] = group_sum(s_y);
-        sumr += group_sum(s_r);
-        group_sync();
+        fs[f] = frame_sums<B, BT, true>(S, grp, lane, on, x, y, kap, R, c0, c1, r0, r1, W, H,
+                                  a.grad + img + (int64_t)f * H * W, W, 0, 0, a.blur_w);
     }
 
     if (lane != 0) return;
@@ -299,29 +342,128 @@ bwd_gather(BwdArgs a, int64_t n_span)
         }
         return;
     }
-    float gx1 = 0.0f, gy1 = 0.0f, gx2 = 0.0f, gy2 = 0.0f, gd = 0.0f, gz = 0.0f, gI0 = 0.0f, sheet = 0.0f;
-    if (valid) {
-        const float s = a.sheet_sigma;
-        const float Sz = expneg((z * z) * (0.5f / (s * s)));
-        const float A = I0 * Sz;
-        const float k2 = 2.0f * kap;                // d/dx of -kap dx^2 is 2 kap dx
-        gx1 = A * k2 * sx[0];
-        gy1 = A * k2 * sy[0];
-        gx2 = A * k2 * sx[1];
-        gy2 = A * k2 * sy[1];
-        gd = A * (k2 / d) * sumr;                   // d kap / d d = -2 kap / d
-        gI0 = sum0 * Sz;
-        gz = sum0 * A * (-z / (s * s));
-        sheet = sum0 * A * ((z * z) / (s * s * s));
+    ParticleGrads o{};
+    if (valid) o = particle_grads(z, d, I0, a.sheet_sigma, fs[0], fs[1]);
+    a.g_x1[g] = o.gx1;
+    a.g_y1[g] = o.gy1;
+    a.g_z[g] = o.gz;
+    a.g_d[g] = o.gd;
+    a.g_I0[g] = o.gI0;
+    a.gx2[g] = o.gx2;
+    a.gy2[g] = o.gy2;
+    a.sheet[g] = o.sheet;
+}
+
+// Tile-major gather.  Frame f's particles are grouped by the home block
+// (2^lb x 2^lb pixels) of their frame-f position; a workgroup takes one
+// (frame, block), stages the frame's B^T dL/dJ over the block grown by a halo
+// of hb pixels into LDS (zeros outside the image), then runs the lane-group
+// sums of the block's particles, 16 per pass, from LDS.  With hb >=
+// ceil(1.5 d_max) + 2 every in-image pixel of the support of a particle whose
+// position lies in the block (or beyond the image edge next to it, where the
+// home block is clamped) is inside the staged region.  The sums go to
+// parts[f * n_span + slot]; bwd_particles turns them into gradients.
+__global__ void __launch_bounds__(256)
+bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
+{
+    extern __shared__ __align__(16) float region[];
+    __shared__ GatherLds<32, false> S;
+    const int64_t blocks = a.order.blocks;
+    const int64_t item = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int f = item >= blocks ? 1 : 0;
+    const int64_t b = item - (int64_t)f * blocks;
+    const AdvectOrder& O = f ? a.order2 : a.order;
+    const int cnt = (int)O.count[b];
+    if (cnt == 0) return;                      // the whole workgroup, before its barrier
+    const int p = find_pair_by_tile(O.L, a.n_pairs, b);
+    const synthpix_pair P = a.pairs[p];
+    const PairLayout PL = O.L[p];
+    // home blocks are numbered in strips of four block rows, column by column
+    // inside a strip (the numbering of the order's count pass)
+    const int tl = (int)(b - PL.tile_base);
+    const int s0 = (tl / (4 * PL.ntx)) * 4;
+    const int rows = PL.nty - s0 < 4 ? PL.nty - s0 : 4;
+    const int wi = tl - s0 * PL.ntx;
+    const int bx = wi / rows, by = s0 + (wi - (wi / rows) * rows);
+    const int side = 1 << lb, rw = side + 2 * hb;
+    const int ox = (bx << lb) - hb, oy = (by << lb) - hb;
+    const int H = P.H, W = P.W;
+    const float* __restrict__ src = a.grad + P.image_offset + (int64_t)f * H * W;
+    // one region row per wave and step, lanes along the row
+    {
+        const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        for (int r = wave; r < rw; r += 4) {
+            const int R = oy + r;
+            const bool rin = R >= 0 && R < H;
+            const float* __restrict__ row = src + (int64_t)(rin ? R : 0) * W;
+            for (int c = ln; c < rw; c += 64) {
+                const int C = ox + c;
+                region[r * rw + c] = (rin && C >= 0 && C < W) ? row[C] : 0.0f;
+            }
+        }
     }
-    a.g_x1[g] = gx1;
-    a.g_y1[g] = gy1;
-    a.g_z[g] = gz;
-    a.g_d[g] = gd;
-    a.g_I0[g] = gI0;
-    a.gx2[g] = gx2;
-    a.gy2[g] = gy2;
-    a.sheet[g] = sheet;
+    __syncthreads();
+
+    const int grp = threadIdx.x / BG, lane = threadIdx.x % BG;
+    const int64_t off = O.offset[b];
+    const float* __restrict__ fx = f ? a.x2 : a.x1;
+    const float* __restrict__ fy = f ? a.y2 : a.y1;
+    for (int base = 0; base < cnt; base += BPW) {
+        const int k = base + grp;
+        bool act = k < cnt, on = false;
+        int64_t g = 0;
+        float x = 0.0f, y = 0.0f, d = 1.0f;
+        if (act) {
+            g = P.particle_offset + O.entries[off + k];
+            d = a.d[g];
+            x = fx[g];
+            y = fy[g];
+            on = (a.I0[g] > 0.0f) && (d > 0.0f) && (d <= a.d_max);
+        }
+        const float kap = 8.0f / (d * d);
+        const float R = 1.5f * d;
+        int c0 = 0, c1 = -1, r0 = 0, r1 = -1;
+        on = on && cover_range(x, R, W, c0, c1);
+        on = on && cover_range(y, R, H, r0, r1);
+        // in-image support inside the staged region (always, for d <= d_max)
+        on = on && c0 >= ox && c1 < ox + rw && r0 >= oy && r1 < oy + rw;
+        const float4 sums = frame_sums<0, 32, false>(S, grp, lane, on, x, y, kap, R, c0, c1, r0, r1, W, H, region, rw,
+                                              oy, ox, a.blur_w);
+        if (act && lane == 0) a.parts[(int64_t)f * n_span + g] = sums;
+    }
+}
+
+// Per-slot gradients from the tile gather's frame sums (zeros for slots in no
+// pair's particle range and for invalid particles).
+__global__ void __launch_bounds__(256) bwd_particles(BwdArgs a, int64_t n_span)
+{
+    const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256;
+    const int64_t g = g0 + threadIdx.x;
+    if (g >= n_span) return;
+    const int p = find_pair_from(a.pairs, a.n_pairs, g0, g);
+    const synthpix_pair P = a.pairs[p];
+    const int64_t i = g - P.particle_offset;
+    ParticleGrads o{};
+    const bool in_pair = i >= 0 && i < P.n_max;
+    if (in_pair) {
+        const float z = a.z[g], d = a.d[g], I0 = a.I0[g];
+        bool valid = (I0 > 0.0f) && (d > 0.0f);
+        if (valid && !(d <= a.d_max)) {
+            atomicOr(a.status, SP_STATUS_D_ABOVE_MAX);
+            valid = false;
+        }
+        if (valid) o = particle_grads(z, d, I0, a.sheet_sigma, a.parts[g], a.parts[n_span + g]);
+    }
+    a.g_x1[g] = o.gx1;
+    a.g_y1[g] = o.gy1;
+    a.g_z[g] = o.gz;
+    a.g_d[g] = o.gd;
+    a.g_I0[g] = o.gI0;
+    if (in_pair) {
+        a.gx2[g] = o.gx2;
+        a.gy2[g] = o.gy2;
+        a.sheet[g] = o.sheet;
+    }
 }
 
 // e = B^T dL/dJ for a wide blur, once per pixel: the zero-padded blur's
@@ -855,6 +997,80 @@ __global__ void bwd_flow_finish(const unsigned long long* __restrict__ fixed, in
 }
 
 
+// ------------------------------------------------------------------ image loss
+
+// grad = scale (J - T) over float4 groups, grid-stride in a fixed grid of
+// MSE_BLOCKS workgroups; with loss partials, each workgroup's float64 sum of
+// (J - T)^2 (each thread's terms in index order, then a fixed tree) goes to
+// part[block].  The last n % 4 elements are workgroup 0's.
+__global__ void __launch_bounds__(256)
+mse_grad_kernel(const float* __restrict__ J, const float* __restrict__ T, int64_t n, float scale,
+                float* __restrict__ grad, double* __restrict__ part)
+{
+    const int64_t n4 = n >> 2;
+    const float4* J4 = reinterpret_cast<const float4*>(J);
+    const float4* T4 = reinterpret_cast<const float4*>(T);
+    float4* G4 = reinterpret_cast<float4*>(grad);
+    double acc = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n4; k += (int64_t)gridDim.x * 256) {
+        const float4 j = J4[k], t = T4[k];
+        const float4 d = make_float4(j.x - t.x, j.y - t.y, j.z - t.z, j.w - t.w);
+        G4[k] = make_float4(scale * d.x, scale * d.y, scale * d.z, scale * d.w);
+        if (part) {     // the differences exactly, in float64
+            const double ex = (double)j.x - (double)t.x, ey = (double)j.y - (double)t.y;
+            const double ez = (double)j.z - (double)t.z, ew = (double)j.w - (double)t.w;
+            acc = __builtin_fma(ex, ex, acc);
+            acc = __builtin_fma(ey, ey, acc);
+            acc = __builtin_fma(ez, ez, acc);
+            acc = __builtin_fma(ew, ew, acc);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const int64_t i = 4 * n4 + threadIdx.x;
+        const float j = J[i], t = T[i];          // read before the write: grad may be J or T
+        grad[i] = scale * (j - t);
+        if (part) {
+            const double e = (double)j - (double)t;
+            acc = __builtin_fma(e, e, acc);
+        }
+    }
+    if (!part) return;
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// loss = (sum of the MSE_BLOCKS partials, as a fixed tree) / n
+__global__ void __launch_bounds__(256) mse_finish(const double* __restrict__ part, int64_t n, double* __restrict__ loss)
+{
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < MSE_BLOCKS; k += 256) v += part[k];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = n > 0 ? red[0] / (double)n : 0.0;
+}
+
+hipError_t launch_mse_grad(const float* J, const float* T, int64_t n, float scale, float* grad, double* loss,
+                           double* part, hipStream_t s)
+{
+    TimedScope ts("mse_grad", s);
+    const int64_t want = (n / 4 + 255) / 256;
+    const unsigned grid = loss ? (unsigned)MSE_BLOCKS : (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, MSE_BLOCKS));
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(grid), dim3(256), 0, s, J, T, n, scale, grad, loss ? part : nullptr);
+    if (loss) hipLaunchKernelGGL(mse_finish, dim3(1), dim3(256), 0, s, part, n, loss);
+    return hipGetLastError();
+}
+
 void launch_advect_adjoint(const BwdArgs& a, int64_t n_span, const synthpix_advect_params& ap, unsigned blocks,
                            hipStream_t s)
 {
@@ -887,20 +1103,34 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             if (e != hipSuccess) return e;
         }
         const unsigned gb = (unsigned)((n_span + BPW - 1) / BPW);
-        if (a.eblur && blur >= 2) {
-            // wide blur: its adjoint once per pixel, then the gather on the
-            // unblurred footprints of B^T dL/dJ (fewer columns per lane group)
-            {
-                TimedScope ts("bwd_blur", s);
-                const int so = 256 - 2 * blur;
-                const int nsx = (a.max_w + so - 1) / so, nsy = (a.max_h + 31) / 32;
-                const int64_t nb = (int64_t)a.n_pairs * 2 * nsx * nsy;
-                if (nb > 0xFFFFFFFFll) return hipErrorInvalidValue;
-                if (blur == 2) hipLaunchKernelGGL(bwd_blur_grad<2>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy);
-                else hipLaunchKernelGGL(bwd_blur_grad<3>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy);
+        const bool tile = a.order2.entries && a.parts;
+        if (a.eblur && blur >= 1 && (tile || blur >= 2)) {
+            // the blur's adjoint once per pixel: the gather then runs on the
+            // unblurred footprints of B^T dL/dJ
+            TimedScope ts("bwd_blur", s);
+            const int so = 256 - 2 * blur;
+            const int nsx = (a.max_w + so - 1) / so, nsy = (a.max_h + 31) / 32;
+            const int64_t nb = (int64_t)a.n_pairs * 2 * nsx * nsy;
+            if (nb > 0xFFFFFFFFll) return hipErrorInvalidValue;
+            switch (blur) {
+            case 1: hipLaunchKernelGGL(bwd_blur_grad<1>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy); break;
+            case 2: hipLaunchKernelGGL(bwd_blur_grad<2>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy); break;
+            case 3: hipLaunchKernelGGL(bwd_blur_grad<3>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy); break;
+            default: return hipErrorInvalidValue;
             }
-            BwdArgs b = a;
-            b.grad = a.eblur;
+        }
+        BwdArgs b = a;
+        if (a.eblur && blur >= 1 && (tile || blur >= 2)) b.grad = a.eblur;
+        if (tile) {
+            TimedScope ts("bwd_gather", s);
+            const int hb = tile_halo(a.d_max);
+            const int rw = (1 << a.order.log_block) + 2 * hb;
+            const int64_t items = 2 * a.order.blocks;
+            if (items > 0xFFFFFFFFll) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(bwd_tile_gather, dim3((unsigned)items), dim3(256), sizeof(float) * (size_t)rw * rw, s,
+                               b, n_span, a.order.log_block, hb);
+            hipLaunchKernelGGL(bwd_particles, dim3((unsigned)((n_span + 255) / 256)), dim3(256), 0, s, b, n_span);
+        } else if (blur >= 2) {
             TimedScope ts("bwd_gather", s);
             if ((int)(3.0f * a.d_max) + 4 <= 32) hipLaunchKernelGGL((bwd_gather<0, 32>), dim3(gb), dim3(256), 0, s, b, n_span);
             else hipLaunchKernelGGL((bwd_gather<0, 64>), dim3(gb), dim3(256), 0, s, b, n_span);
@@ -916,7 +1146,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             switch (blur) {
             case 0: SP_GATHER(0); break;
             case 1: SP_GATHER(1); break;
-            default: return hipErrorInvalidValue;     // wider blurs take the path above
+            default: return hipErrorInvalidValue;
             }
 #undef SP_GATHER
         }

@@ -1,6 +1,8 @@
 // Kernel launchers shared between the kernel translation units and the C ABI.
 #pragma once
 
+#include <cmath>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -138,6 +140,8 @@ struct AdvectOrder {
     const int32_t* entries;
     int log_block;              // home blocks are 2^log_block pixels square
     int64_t blocks;             // home blocks over all pairs
+    const uint32_t* count;      // particles per home block
+    const int64_t* offset;      // first entry of each home block
 };
 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
@@ -221,6 +225,8 @@ constexpr int BWD_SLICES = 128;
 // Everything the backward kernels read and write.
 struct BwdArgs {
     AdvectOrder order;           // home-block order of the frame-1 positions
+    AdvectOrder order2;          // the same for the frame-2 positions (tile gather only)
+    float4* parts;               // per-frame particle sums (S0, Sx, Sy, Sr), 2 x n_span (tile gather only)
     const synthpix_pair* pairs;
     int n_pairs;
     const float* flow;
@@ -260,6 +266,29 @@ struct BwdArgs {
 
 hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, const synthpix_advect_params& ap,
                            int blur, int en, hipStream_t s);
+
+// Image loss gradient grad = scale (J - T) and, with loss, the mean of (J - T)^2
+// (float64 partials of MSE_BLOCKS workgroups in part, summed in a fixed order).
+constexpr int MSE_BLOCKS = 1024;
+hipError_t launch_mse_grad(const float* J, const float* T, int64_t n, float scale, float* grad, double* loss,
+                           double* part, hipStream_t s);
+
+// Halo (pixels) of the tile-major adjoint gather's staged region for a diameter
+// bound: every in-image pixel of a footprint whose centre lies in a home block
+// is within this distance of the block.
+inline int tile_halo(float d_max) { return (int)std::ceil(1.5f * d_max) + 2; }
+
+// Whether the tile-major gather serves a batch: a blur of radius >= 2 (whose
+// adjoint then runs once per pixel; narrower blurs fold into the particle-major
+// gather's tables, which costs less than staging and the second order), factor
+// tables that hold the support (3 d_max + 4 slots <= 32) and a staged region of
+// a home block of 2^log_block pixels within 64 KB of LDS.
+inline bool tile_gather_fits(float d_max, int log_block, int blur_radius)
+{
+    if (blur_radius < 2 || !((int)(3.0f * d_max) + 4 <= 32)) return false;
+    const int rw = (1 << log_block) + 2 * tile_halo(d_max);
+    return (size_t)rw * rw * sizeof(float) <= 64 * 1024;
+}
 
 // Peak-rate probes (store, copy, fma, trans, mul64, store_nt = kinds 0..5); *work gets
 // the launch's bytes or wave64 instructions.

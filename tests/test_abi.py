@@ -268,6 +268,27 @@ def test_backward_validation(L):
                                              None) == L.SP_ERR_INVALID_ARG
 
 
+def test_mse_grad_validation(L):
+    """The loss-gradient call checks its arguments before enqueueing anything."""
+    lib = L.load()
+    fake = ctypes.c_void_p(0x1000)
+    ws_n = lib.synthpix_mse_workspace_size(1 << 20)
+    assert ws_n >= 8 * 1024 and ws_n % 256 == 0
+    ws = ctypes.c_void_p(0x100000)
+    assert lib.synthpix_mse_grad(fake, fake, -1, 1.0, fake, None, None, 0, None) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_mse_grad(None, fake, 8, 1.0, fake, None, None, 0, None) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_mse_grad(None, None, 0, 1.0, None, None, None, 0, None) == 0      # nothing to do
+    assert lib.synthpix_mse_grad(fake, ctypes.c_void_p(0x1004), 8, 1.0, fake, None, None, 0,
+                                 None) == L.SP_ERR_INVALID_ARG                        # misaligned target
+    assert lib.synthpix_mse_grad(fake, fake, 8, float("inf"), fake, None, None, 0, None) == L.SP_ERR_INVALID_ARG
+    assert lib.synthpix_mse_grad(fake, fake, 8, 1.0, fake, ctypes.c_void_p(0x2004), ws, ws_n,
+                                 None) == L.SP_ERR_INVALID_ARG                        # misaligned loss
+    assert lib.synthpix_mse_grad(fake, fake, 8, 1.0, fake, ctypes.c_void_p(0x2000), None, 0,
+                                 None) == L.SP_ERR_WORKSPACE
+    assert lib.synthpix_mse_grad(fake, fake, 8, 1.0, fake, ctypes.c_void_p(0x2000), ws, ws_n - 1,
+                                 None) == L.SP_ERR_WORKSPACE
+
+
 def test_model_validation(L):
     """The full model's parameters and inputs are checked on the host before
     anything is enqueued."""

@@ -479,3 +479,59 @@ def test_mse_loss_against_perturbed_flow_target():
         n_f = flows[p].size
         _close(gu.to_np(fl.grad)[fo:fo + n_f].reshape(flows[p].shape), ref["flow"], f"pair {p} flow", tol=1e-3)
         fo += n_f
+
+
+@pytest.mark.parametrize("blur", [2, 3])
+def test_tile_gather_matches_particle_gather(blur):
+    """The two adjoint gathers on one batch: the tile-major one (particles grouped
+    by the home block of each frame's position, the block plus its halo staged in
+    LDS; taken for blur radius >= 2 and d_max <= 9) and the particle-major one
+    (global reads; taken here by raising d_max to 10, which changes no
+    footprint).  Pairs span many 32-pixel home blocks with ragged edges;
+    particles lie inside, on block and image edges and up to 3 px outside the
+    image; frame 2 is both recomputed and passed in.  Both gathers read the same
+    B^T dL/dJ, so every gradient agrees bit for bit."""
+    sizes = [(70, 97), (33, 130), (128, 64)]
+    grids = [(18, 25), (9, 33), (32, 16)]
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, 90, 500 + blur, d_range=(1.0, 6.0))
+    out = []
+    for d_max in (6.0, 10.0):
+        rp = sp.render_params(0.5, d_max, blur, 0.8, 0.0, 0, 0, 1.0, 3, "rk4")
+        gJ, gJ_dev = _grad_images(batch, 700 + blur)
+        ws = sp.alloc_workspace(batch, rp, backward=True)
+        g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                                    workspace=ws)
+        x2, y2 = sp.advect(batch, flow_dev, rp.advect, dev["x"], dev["y"])
+        g2 = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                                     x2=x2, y2=y2)
+        torch.cuda.synchronize()
+        assert sp.read_status(ws) == 0
+        for k in g:
+            assert torch.equal(g[k], g2[k]), (d_max, k)
+        out.append({k: gu.to_np(v) for k, v in g.items()})
+    tile, part = out
+    for k in ("x1", "y1", "z", "d", "I0", "sheet", "flow"):
+        assert np.array_equal(tile[k], part[k]), k
+
+
+@pytest.mark.parametrize("n", [0, 3, 4096, 1_000_003])
+def test_mse_grad_matches_definition(n):
+    """dL/dJ = scale (J - T) equals the same binary32 operations on the host bit
+    for bit (a ragged tail included, and in place over J); the loss equals the
+    float64 mean of (J - T)^2 to rounding, and repeats bit for bit."""
+    rng = np.random.default_rng(n)
+    J = rng.standard_normal(n).astype(np.float32)
+    T = rng.standard_normal(n).astype(np.float32)
+    Jd, Td = gu.to_dev(J), gu.to_dev(T)
+    scale = np.float32(2.0 / max(n, 1))
+    g, loss = sp.mse_grad(Jd, Td, float(scale), loss=True)
+    g2, loss2 = sp.mse_grad(Jd, Td, float(scale), loss=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(gu.to_np(g), scale * (J - T))
+    ref = float(np.mean((J.astype(np.float64) - T) ** 2)) if n else 0.0
+    assert abs(float(loss) - ref) <= 1e-12 * max(ref, 1.0)
+    assert float(loss) == float(loss2) and torch.equal(g, g2)
+    if n:
+        sp.mse_grad(Jd, Td, float(scale), out=Jd)             # in place over J
+        torch.cuda.synchronize()
+        assert np.array_equal(gu.to_np(Jd), scale * (J - T))

@@ -85,6 +85,9 @@ typedef enum { SP_DIST_UNIFORM = 0, SP_DIST_NORMAL_CLIPPED = 1 } synthpix_dist;
                                           the images were left unchanged */
 #define SP_STATUS_HIST_CODE     0x10u  /* histogram adjustment: a stored code >= 2^bits was taken
                                           as 2^bits - 1 */
+#define SP_STATUS_GRID_OVERFLOW 0x20u  /* backward: a workgroup of 256 particles had more flow-grid
+                                          contributions outside its node window than it keeps;
+                                          g_flow is incomplete (the particles moved too far) */
 
 /* Laser-sheet laws of the peak intensity. */
 #define SP_SHEET_GAUSS   0   /* I0 exp(-z^2 / (2 s^2)), s = sheet_sigma                           */

@@ -225,10 +225,19 @@ int64_t flow_span(const synthpix_pair* ph, int32_t n_pairs)
 
 // Backward workspace: particle-major, no bins.
 struct BwdLayout {
-    size_t status, scale, x2, y2, gx2, gy2, sheet, sheet_part, bound_part, fixed, eblur, parts, total;
+    size_t status, scale, x2, y2, gx2, gy2, sheet, sheet_part, bound_part, wg_base, head, part, ovf, eblur, parts,
+        total;
 };
 
-BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs, int64_t n_eblur, bool tile)
+// Workgroups of the flow adjoint: 256 particles of one pair each.
+int64_t grid_workgroups(const synthpix_pair* ph, int32_t n_pairs)
+{
+    int64_t n = 0;
+    for (int32_t p = 0; p < n_pairs; ++p) n += ((int64_t)ph[p].n_max + 255) / 256;
+    return n;
+}
+
+BwdLayout bwd_layout(int64_t n_span, int64_t n_wg, int32_t n_pairs, int64_t n_eblur, bool tile)
 {
     BwdLayout w{};
     size_t o = 0;
@@ -242,7 +251,10 @@ BwdLayout bwd_layout(int64_t n_span, int64_t n_flow, int32_t n_pairs, int64_t n_
     w.sheet = o; o = align256(o + nf);
     w.sheet_part = o; o = align256(o + sizeof(double) * sp::BWD_SLICES * (size_t)n_pairs);
     w.bound_part = o; o = align256(o + sizeof(float) * 2 * sp::BWD_SLICES * (size_t)n_pairs);
-    w.fixed = o; o = align256(o + sizeof(uint64_t) * (size_t)n_flow);
+    w.wg_base = o; o = align256(o + sizeof(int64_t) * ((size_t)n_pairs + 1));
+    w.head = o; o = align256(o + sizeof(sp::GridHeader) * (size_t)n_wg);
+    w.part = o; o = align256(o + sizeof(uint64_t) * 2 * sp::WIN_NODES * (size_t)n_wg);
+    w.ovf = o; o = align256(o + sizeof(sp::GridRecord) * sp::GRID_OVF_CAP * (size_t)n_wg);
     w.eblur = o; o = align256(o + sizeof(float) * (size_t)n_eblur);
     w.parts = o; o = align256(o + (tile ? 2 * 16 * (size_t)n_span : 0));
     w.total = o;
@@ -415,7 +427,8 @@ BwdPlan bwd_plan(const synthpix_pair* ph, int32_t n_pairs, int64_t span, const s
     BwdPlan b{};
     b.ob = order_bytes(ph, n_pairs);
     b.tile = sp::tile_gather_fits(rp.d_max, order_config(ph, n_pairs).log_tw, rp.blur_radius);
-    b.wl = bwd_layout(span, flow_span(ph, n_pairs), n_pairs, eblur_span(ph, n_pairs, rp.blur_radius, b.tile), b.tile);
+    b.wl = bwd_layout(span, grid_workgroups(ph, n_pairs), n_pairs, eblur_span(ph, n_pairs, rp.blur_radius, b.tile),
+                      b.tile);
     b.total = b.wl.total + b.ob * (b.tile ? 2 : 1);
     return b;
 }
@@ -837,7 +850,15 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.sheet = reinterpret_cast<float*>(ws + wl.sheet);
     a.sheet_part = reinterpret_cast<double*>(ws + wl.sheet_part);
     a.bound_part = reinterpret_cast<float*>(ws + wl.bound_part);
-    a.fixed = reinterpret_cast<unsigned long long*>(ws + wl.fixed);
+    a.grid.wg_base = reinterpret_cast<int64_t*>(ws + wl.wg_base);
+    a.grid.head = reinterpret_cast<sp::GridHeader*>(ws + wl.head);
+    a.grid.part = reinterpret_cast<unsigned long long*>(ws + wl.part);
+    a.grid.ovf = reinterpret_cast<sp::GridRecord*>(ws + wl.ovf);
+    a.grid.n_wg = grid_workgroups(pairs_host, n_pairs);
+    for (int32_t p = 0; p < n_pairs; ++p) {
+        a.grid.max_gh = std::max(a.grid.max_gh, (int)pairs_host[p].Gh);
+        a.grid.max_gw = std::max(a.grid.max_gw, (int)pairs_host[p].Gw);
+    }
     a.scale = reinterpret_cast<uint32_t*>(ws + wl.scale);
     a.status = reinterpret_cast<uint32_t*>(ws + wl.status);
     a.sheet_sigma = rp->sheet_sigma;

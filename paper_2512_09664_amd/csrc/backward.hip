@@ -379,12 +379,13 @@ bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
     const synthpix_pair P = a.pairs[p];
     const PairLayout PL = O.L[p];
     // home blocks are numbered in strips of four block rows, column by column
-    // inside a strip (the numbering of the order's count pass)
+    // inside a strip, odd strips right to left (the order's numbering)
     const int tl = (int)(b - PL.tile_base);
     const int s0 = (tl / (4 * PL.ntx)) * 4;
     const int rows = PL.nty - s0 < 4 ? PL.nty - s0 : 4;
     const int wi = tl - s0 * PL.ntx;
-    const int bx = wi / rows, by = s0 + (wi - (wi / rows) * rows);
+    const int col = wi / rows, by = s0 + (wi - col * rows);
+    const int bx = (s0 & 4) ? PL.ntx - 1 - col : col;
     const int side = 1 << lb, rw = side + 2 * hb;
     const int ox = (bx << lb) - hb, oy = (by << lb) - hb;
     const int H = P.H, W = P.W;
@@ -583,22 +584,24 @@ struct CellRun {
 
 struct NodeRun {
     CellRun cur, prev1, prev2;
-    unsigned long long* fixed;
-    int64_t base;         // element offset of the pair's grid
     int Gw;
     double scale;         // 2^e; 0 when the flow gradient is not accumulated
     // the workgroup's LDS window of node sums (rows wi0 .., cols wj0 .., wh x ww
-    // nodes, (u, v) interleaved); nodes outside it go to global memory
+    // nodes, (u, v) interleaved); nodes outside it become overflow records
     unsigned long long* win;
     int wi0, wj0, wh, ww;
+    GridRecord* ovf;      // the workgroup's overflow records (global memory)
+    unsigned* n_ovf;      // their count (LDS)
 
     __device__ void add_node(int ni, int nj, int c, unsigned long long q)
     {
         const int li = ni - wi0, lj = nj - wj0;
-        if ((unsigned)li < (unsigned)wh && (unsigned)lj < (unsigned)ww)
+        if ((unsigned)li < (unsigned)wh && (unsigned)lj < (unsigned)ww) {
             atomicAdd(win + 2 * (li * ww + lj) + c, q);
-        else
-            atomicAdd(fixed + base + 2 * ((int64_t)ni * Gw + nj) + c, q);
+        } else {
+            const unsigned k = atomicAdd(n_ovf, 1u);
+            if (k < GRID_OVF_CAP) ovf[k] = GridRecord{2 * (ni * Gw + nj) + c, 0u, q};
+        }
     }
 
     __device__ void flush(const CellRun& r)
@@ -688,56 +691,52 @@ enum { SC_NONE = 0, SC_VALID = 1, SC_NONFINITE = 2 };
 // g_y1) and node sums into the fixed-point grid.  CK checkpoints of the
 // trajectory are kept, one every L = ceil(substeps / CK) substeps; each segment
 // is recomputed into SK >= L slots during the sweep.
-constexpr int WIN_NODES = 2048;   // LDS window capacity (nodes; 32 KB of (u, v) sums)
-constexpr int WIN_MARGIN = 3;     // cells added around the particles' starting cells
 
 template <int CK, int SK>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
+bwd_advect(BwdArgs a, synthpix_advect_params ap)
 {
     __shared__ unsigned long long win[2 * WIN_NODES];
     __shared__ int s_box[4][4];
-    __shared__ int s_pair;
-    const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * 256;
-    int64_t g = g0 + threadIdx.x;
-    int p = -1;
-    synthpix_pair P{};
+    __shared__ unsigned s_novf;
+    // workgroup -> (pair, 256-particle chunk of the pair's ordered particles)
+    const int64_t wg = xcd_contiguous(blockIdx.x, gridDim.x);
+    int p = 0;
+    {
+        int lo = 0, hi = a.n_pairs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.grid.wg_base[mid] <= wg) lo = mid;
+            else hi = mid - 1;
+        }
+        p = lo;
+    }
+    const synthpix_pair P = a.pairs[p];
+    const int64_t chunk = wg - a.grid.wg_base[p];
+    int64_t i = chunk * 256 + threadIdx.x;
+    int64_t g = 0;
     bool live = false;
     float gpx = 0.0f, gpy = 0.0f, px = 0.0f, py = 0.0f;
-    if (g < n_span) {
-        p = find_pair_from(a.pairs, a.n_pairs, g0, g);
-        P = a.pairs[p];
-        int64_t i = g - P.particle_offset;
-        if (i >= 0 && i < P.n_max) {
-            // slots follow the home-block order when one is given: neighbouring lanes
-            // then sample, and add into, neighbouring grid cells
-            if (a.order.entries) {
-                i = a.order.entries[a.order.L[p].entry_base + i];
-                g = P.particle_offset + i;
-            }
-            gpx = a.gx2[g];
-            gpy = a.gy2[g];
-            px = a.x1[g];
-            py = a.y1[g];
-            live = (gpx != 0.0f || gpy != 0.0f) && __builtin_isfinite(px) && __builtin_isfinite(py);
-        } else {
-            p = -1;
-        }
+    if (i < P.n_max) {
+        // slots follow the home-block order: neighbouring lanes sample, and add
+        // into, neighbouring grid cells
+        if (a.order.entries) i = a.order.entries[a.order.L[p].entry_base + i];
+        g = P.particle_offset + i;
+        gpx = a.gx2[g];
+        gpy = a.gy2[g];
+        px = a.x1[g];
+        py = a.y1[g];
+        live = (gpx != 0.0f || gpy != 0.0f) && __builtin_isfinite(px) && __builtin_isfinite(py);
     }
     NodeRun run;
-    run.fixed = a.fixed;
-    run.base = live ? P.flow_offset : 0;
-    run.Gw = live ? P.Gw : 2;
+    run.Gw = P.Gw;
     run.scale = a.scale[SC_STATE] == SC_VALID ? __builtin_ldexp(1.0, (int)a.scale[SC_EXP]) : 0.0;
-    const FlowView fv = live ? flow_view(P, a.flow) : FlowView{reinterpret_cast<const float2*>(a.flow), 2, 2, 1.0f, 1.0f};
+    const FlowView fv = flow_view(P, a.flow);
 
-    // window: the box of the starting cells of this workgroup's live particles of
-    // the first thread's pair, grown by a margin, if it fits
-    if (threadIdx.x == 0) s_pair = p;
-    __syncthreads();
-    const bool mine = live && p == s_pair;
+    // window: the box of the live particles' starting cells, grown on every side
+    // by as many cells as the LDS window holds (at least one)
     int bi0 = 1 << 30, bj0 = 1 << 30, bi1 = -1, bj1 = -1;
-    if (mine) {
+    if (live) {
         const float gx = __builtin_fminf(__builtin_fmaxf(px * fv.sx - 0.5f, 0.0f), (float)(fv.Gw - 1));
         const float gy = __builtin_fminf(__builtin_fmaxf(py * fv.sy - 0.5f, 0.0f), (float)(fv.Gh - 1));
         bj0 = bj1 = (int)gx;
@@ -756,22 +755,33 @@ bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
         s_box[threadIdx.x >> 6][2] = bi1;
         s_box[threadIdx.x >> 6][3] = bj1;
     }
+    if (threadIdx.x == 0) s_novf = 0u;
     __syncthreads();
-    bi0 = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0])) - WIN_MARGIN;
-    bj0 = min(min(s_box[0][1], s_box[1][1]), min(s_box[2][1], s_box[3][1])) - WIN_MARGIN;
-    bi1 = max(max(s_box[0][2], s_box[1][2]), max(s_box[2][2], s_box[3][2])) + WIN_MARGIN + 1;
-    bj1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3])) + WIN_MARGIN + 1;
-    const int wh = bi1 - bi0 + 1, ww = bj1 - bj0 + 1;
-    const bool use_win = run.scale != 0.0 && s_pair >= 0 && bi1 >= bi0 && (int64_t)wh * ww <= WIN_NODES;
+    bi0 = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0]));
+    bj0 = min(min(s_box[0][1], s_box[1][1]), min(s_box[2][1], s_box[3][1]));
+    bi1 = max(max(s_box[0][2], s_box[1][2]), max(s_box[2][2], s_box[3][2])) + 1;
+    bj1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3])) + 1;
+    const bool any = bi1 >= bi0 && run.scale != 0.0;
+    int m = 0;                                   // margin in cells
+    if (any) {
+        const int h0 = bi1 - bi0 + 1, w0 = bj1 - bj0 + 1;
+        m = 1;
+        while ((h0 + 2 * (m + 1)) * (w0 + 2 * (m + 1)) <= WIN_NODES) ++m;
+        if (h0 + 2 * m > WIN_NODES || (h0 + 2 * m) * (w0 + 2 * m) > WIN_NODES) m = 0;
+    }
+    const int wh = any ? bi1 - bi0 + 1 + 2 * m : 0, ww = any ? bj1 - bj0 + 1 + 2 * m : 0;
+    const bool use_win = any && wh * ww <= WIN_NODES;
     run.win = win;
-    run.wi0 = bi0;
-    run.wj0 = bj0;
-    run.wh = (use_win && mine) ? wh : 0;   // lanes of another pair always go to global memory
+    run.wi0 = bi0 - m;
+    run.wj0 = bj0 - m;
+    run.wh = use_win ? wh : 0;                   // no window: every node becomes a record
     run.ww = ww;
+    run.ovf = a.grid.ovf + wg * GRID_OVF_CAP;
+    run.n_ovf = &s_novf;
     if (use_win) {
         for (int k = threadIdx.x; k < 2 * wh * ww; k += 256) win[k] = 0ull;
-        __syncthreads();
     }
+    __syncthreads();
 
     if (live) {
         const int S = ap.substeps;
@@ -807,17 +817,157 @@ bwd_advect(BwdArgs a, int64_t n_span, synthpix_advect_params ap)
         a.g_x1[g] += gpx;
         a.g_y1[g] += gpy;
     }
+    __syncthreads();
+
+    // the window's nonzero box, then its sums into this workgroup's partial
+    // (rows of the box, (u, v) interleaved) and the header
+    int ti0 = 1 << 30, tj0 = 1 << 30, ti1 = -1, tj1 = -1;
     if (use_win) {
-        // window sums into the pair's grid (window nodes outside the grid hold no sums)
-        __syncthreads();
-        const synthpix_pair Q = a.pairs[s_pair];
-        for (int k = threadIdx.x; k < 2 * wh * ww; k += 256) {
-            const unsigned long long v = win[k];
-            if (v == 0ull) continue;
-            const int n = k >> 1, c = k & 1;
-            const int ni = bi0 + n / ww, nj = bj0 + n % ww;
-            if (ni < 0 || ni >= Q.Gh || nj < 0 || nj >= Q.Gw) continue;
-            atomicAdd(a.fixed + Q.flow_offset + 2 * ((int64_t)ni * Q.Gw + nj) + c, v);
+        for (int k = threadIdx.x; k < wh * ww; k += 256) {
+            if (win[2 * k] != 0ull || win[2 * k + 1] != 0ull) {
+                const int li = k / ww, lj = k - li * ww;
+                ti0 = min(ti0, li);
+                ti1 = max(ti1, li);
+                tj0 = min(tj0, lj);
+                tj1 = max(tj1, lj);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        ti0 = min(ti0, __shfl_xor(ti0, o, 64));
+        tj0 = min(tj0, __shfl_xor(tj0, o, 64));
+        ti1 = max(ti1, __shfl_xor(ti1, o, 64));
+        tj1 = max(tj1, __shfl_xor(tj1, o, 64));
+    }
+    __syncthreads();                             // s_box is reused
+    if ((threadIdx.x & 63) == 0) {
+        s_box[threadIdx.x >> 6][0] = ti0;
+        s_box[threadIdx.x >> 6][1] = tj0;
+        s_box[threadIdx.x >> 6][2] = ti1;
+        s_box[threadIdx.x >> 6][3] = tj1;
+    }
+    __syncthreads();
+    ti0 = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0]));
+    tj0 = min(min(s_box[0][1], s_box[1][1]), min(s_box[2][1], s_box[3][1]));
+    ti1 = max(max(s_box[0][2], s_box[1][2]), max(s_box[2][2], s_box[3][2]));
+    tj1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3]));
+    const int th = ti1 >= ti0 ? ti1 - ti0 + 1 : 0, tw = ti1 >= ti0 ? tj1 - tj0 + 1 : 0;
+    unsigned long long* part = a.grid.part + wg * (2 * WIN_NODES);
+    for (int k = threadIdx.x; k < th * tw; k += 256) {
+        const int r = k / tw, c = k - r * tw;
+        const int src = (ti0 + r) * ww + (tj0 + c);
+        part[2 * k] = win[2 * src];
+        part[2 * k + 1] = win[2 * src + 1];
+    }
+    if (threadIdx.x == 0) {
+        const unsigned n = s_novf;
+        if (n > GRID_OVF_CAP) atomicOr(a.status, SP_STATUS_GRID_OVERFLOW);
+        GridHeader hd;
+        hd.i0 = run.wi0 + ti0;
+        hd.j0 = run.wj0 + tj0;
+        hd.h = th;
+        hd.w = tw;
+        hd.n_ovf = n < GRID_OVF_CAP ? n : GRID_OVF_CAP;
+        a.grid.head[wg] = hd;
+    }
+}
+
+// Workgroups of the flow adjoint: each pair's particles in chunks of 256
+// (prefix over pairs in wg_base[0 .. n_pairs]).
+__global__ void bwd_grid_layout(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t* __restrict__ wg_base)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int p = 0; p < n_pairs; ++p) {
+        wg_base[p] = acc;
+        acc += (pairs[p].n_max + 255) / 256;
+    }
+    wg_base[n_pairs] = acc;
+}
+
+// Flow-grid gradient of one 32 x 32-node tile of one pair: each thread holds
+// four nodes' two fixed-point sums and adds, in workgroup order, the partial
+// of every workgroup of the pair whose box covers them, then the overflow
+// records that fall in the tile; the sums leave as floats (scaled by 2^-e).
+// Workgroups are (pair, tile row, tile column) over the batch's largest grid.
+constexpr int GRID_TILE = 32;
+
+__global__ void __launch_bounds__(256)
+bwd_grid_reduce(BwdArgs a, int ntx, int nty)
+{
+    const int64_t bid = blockIdx.x;
+    const int p = (int)(bid / ((int64_t)ntx * nty));
+    const int rem = (int)(bid - (int64_t)p * ntx * nty);
+    const int ty = rem / ntx, tx = rem - ty * ntx;
+    const synthpix_pair P = a.pairs[p];
+    const int i0 = ty * GRID_TILE, j0 = tx * GRID_TILE;
+    if (i0 >= P.Gh || j0 >= P.Gw) return;
+    const uint32_t state = a.scale[SC_STATE];
+    float* out = a.g_flow + P.flow_offset;
+    // thread -> nodes (i0 + r + 8 q, j0 + c), r = threadIdx / 32, c = threadIdx % 32, q = 0..3
+    const int r = threadIdx.x >> 5, c = threadIdx.x & 31;
+    unsigned long long su[4] = {0ull, 0ull, 0ull, 0ull}, sv[4] = {0ull, 0ull, 0ull, 0ull};
+    __shared__ int s_list[256];
+    if (state == SC_VALID) {
+        const int64_t w0 = a.grid.wg_base[p], w1 = a.grid.wg_base[p + 1];
+        for (int64_t wb = w0; wb < w1; wb += 256) {
+            // the covering workgroups of this stretch, in order
+            const int64_t w = wb + threadIdx.x;
+            bool hit = false;
+            if (w < w1) {
+                const GridHeader hd = a.grid.head[w];
+                hit = (hd.h > 0 && hd.i0 < i0 + GRID_TILE && hd.i0 + hd.h > i0 && hd.j0 < j0 + GRID_TILE &&
+                       hd.j0 + hd.w > j0) || hd.n_ovf > 0;
+            }
+            // ordered compaction: a workgroup-wide prefix count of the hits
+            const unsigned long long bal = __ballot(hit);
+            __shared__ int s_cnt[4];
+            if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = __popcll(bal);
+            __syncthreads();
+            int before = 0;
+            for (int k = 0; k < (int)(threadIdx.x >> 6); ++k) before += s_cnt[k];
+            const int lane = threadIdx.x & 63;
+            const unsigned long long lower = lane ? (bal & ((~0ull) >> (64 - lane))) : 0ull;
+            if (hit) s_list[before + __popcll(lower)] = (int)(w - wb);
+            const int nl = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+            __syncthreads();
+            for (int k = 0; k < nl; ++k) {
+                const int64_t wi = wb + s_list[k];
+                const GridHeader hd = a.grid.head[wi];
+                const unsigned long long* part = a.grid.part + wi * (2 * WIN_NODES);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int ni = i0 + r + 8 * q, nj = j0 + c;
+                    const int li = ni - hd.i0, lj = nj - hd.j0;
+                    if ((unsigned)li < (unsigned)hd.h && (unsigned)lj < (unsigned)hd.w) {
+                        su[q] += part[2 * (li * hd.w + lj)];
+                        sv[q] += part[2 * (li * hd.w + lj) + 1];
+                    }
+                }
+                for (unsigned e = 0; e < hd.n_ovf; ++e) {
+                    const GridRecord rec = a.grid.ovf[wi * GRID_OVF_CAP + e];
+                    const int node = rec.elem >> 1;
+                    const int ni = node / P.Gw, nj = node - ni * P.Gw;
+                    const int q = (ni - i0 - r) >> 3;
+                    if (nj == j0 + c && ni >= i0 + r && ((ni - i0 - r) & 7) == 0 && q < 4) {
+                        if (rec.elem & 1) sv[q] += rec.value;
+                        else su[q] += rec.value;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const double inv = state == SC_VALID ? __builtin_ldexp(1.0, -(int)a.scale[SC_EXP]) : 0.0;
+    const float fill = state == SC_NONFINITE ? __builtin_nanf("") : 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int ni = i0 + r + 8 * q, nj = j0 + c;
+        if (ni < P.Gh && nj < P.Gw) {
+            const int64_t k = 2 * ((int64_t)ni * P.Gw + nj);
+            out[k] = state == SC_VALID ? (float)((double)(long long)su[q] * inv) : fill;
+            out[k + 1] = state == SC_VALID ? (float)((double)(long long)sv[q] * inv) : fill;
         }
     }
 }
@@ -971,7 +1121,9 @@ bwd_scale(uint32_t* __restrict__ sc, synthpix_advect_params ap, int en, const do
     sc[SC_STATE] = state;
 }
 
-__global__ void bwd_init(unsigned long long* __restrict__ fixed, int64_t n, uint32_t* __restrict__ status,
+// Status, scale block and sheet outputs cleared; the flow gradient zeroed (its
+// pairs' grids are overwritten by the reduction, gaps between them stay 0).
+__global__ void bwd_init(float* __restrict__ g_flow, int64_t n, uint32_t* __restrict__ status,
                          uint32_t* __restrict__ sc, float* __restrict__ g_sheet, int n_pairs,
                          float* __restrict__ g_sheet_total)
 {
@@ -983,17 +1135,7 @@ __global__ void bwd_init(unsigned long long* __restrict__ fixed, int64_t n, uint
     // sheet gradients of a batch without particles (otherwise overwritten later)
     if (t < n_pairs) g_sheet[t] = 0.0f;
     if (t == 0 && g_sheet_total) *g_sheet_total = 0.0f;
-    for (int64_t k = t; k < n; k += (int64_t)gridDim.x * blockDim.x) fixed[k] = 0ull;
-}
-
-__global__ void bwd_flow_finish(const unsigned long long* __restrict__ fixed, int64_t n,
-                                const uint32_t* __restrict__ sc, float* __restrict__ g_flow)
-{
-    const uint32_t state = sc[SC_STATE];
-    const double inv = state == SC_VALID ? __builtin_ldexp(1.0, -(int)sc[SC_EXP]) : 0.0;
-    const float fill = state == SC_NONFINITE ? __builtin_nanf("") : 0.0f;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-        g_flow[k] = state == SC_VALID ? (float)((double)(long long)fixed[k] * inv) : fill;
+    for (int64_t k = t; k < n; k += (int64_t)gridDim.x * blockDim.x) g_flow[k] = 0.0f;
 }
 
 
@@ -1071,11 +1213,10 @@ hipError_t launch_mse_grad(const float* J, const float* T, int64_t n, float scal
     return hipGetLastError();
 }
 
-void launch_advect_adjoint(const BwdArgs& a, int64_t n_span, const synthpix_advect_params& ap, unsigned blocks,
-                           hipStream_t s)
+void launch_advect_adjoint(const BwdArgs& a, const synthpix_advect_params& ap, unsigned blocks, hipStream_t s)
 {
     const int S = ap.substeps;
-#define SP_ADJ(CK, SK) hipLaunchKernelGGL((bwd_advect<CK, SK>), dim3(blocks), dim3(256), 0, s, a, n_span, ap)
+#define SP_ADJ(CK, SK) hipLaunchKernelGGL((bwd_advect<CK, SK>), dim3(blocks), dim3(256), 0, s, a, ap)
     if (S <= 1) SP_ADJ(1, 1);
     else if (S <= 2) SP_ADJ(2, 1);
     else if (S <= 4) SP_ADJ(4, 1);
@@ -1093,8 +1234,9 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         TimedScope ts("bwd_init", s);
         const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n_flow + 255) / 256 + 1, (a.n_pairs + 255) / 256),
                                                  65536);
-        hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.status, a.scale,
+        hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.g_flow, n_flow, a.status, a.scale,
                            a.g_sheet, a.n_pairs, a.g_sheet_total);
+        hipLaunchKernelGGL(bwd_grid_layout, dim3(1), dim3(64), 0, s, a.pairs, a.n_pairs, a.grid.wg_base);
     }
     if (n_span > 0) {
         if (a.recompute_x2) {
@@ -1159,16 +1301,18 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             hipLaunchKernelGGL(bwd_scale, dim3(1), dim3(256), 0, s, a.scale, ap, en, a.sheet_part, a.bound_part,
                                a.n_pairs, ns, a.g_sheet, a.g_sheet_total);
         }
-        {
+        if (a.grid.n_wg > 0) {
             TimedScope ts("bwd_advect", s);
-            launch_advect_adjoint(a, n_span, ap, (unsigned)((n_span + 255) / 256), s);
+            if (a.grid.n_wg > 0xFFFFFFFFll) return hipErrorInvalidValue;
+            launch_advect_adjoint(a, ap, (unsigned)a.grid.n_wg, s);
         }
-    }
-    {
-        TimedScope ts("bwd_flow", s);
-        const int64_t blocks = std::min<int64_t>((n_flow + 255) / 256 + 1, 8192);
-        hipLaunchKernelGGL(bwd_flow_finish, dim3((unsigned)blocks), dim3(256), 0, s, a.fixed, n_flow, a.scale,
-                           a.g_flow);
+        {
+            TimedScope ts("bwd_flow", s);
+            const int ntx = (a.grid.max_gw + GRID_TILE - 1) / GRID_TILE, nty = (a.grid.max_gh + GRID_TILE - 1) / GRID_TILE;
+            const int64_t nb = (int64_t)a.n_pairs * ntx * nty;
+            if (nb > 0xFFFFFFFFll) return hipErrorInvalidValue;
+            if (nb > 0) hipLaunchKernelGGL(bwd_grid_reduce, dim3((unsigned)nb), dim3(256), 0, s, a, ntx, nty);
+        }
     }
     return hipGetLastError();
 }

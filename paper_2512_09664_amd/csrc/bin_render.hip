@@ -293,8 +293,10 @@ bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__
 // A spatial processing order for per-particle work that samples the flow grid:
 // particle i of a pair goes to the block (a "tile" of the order's config) that
 // holds its clamped position.  Blocks are numbered in strips of four block
-// rows, column by column inside a strip, so a run of consecutive entries (one
-// workgroup's particles) covers a compact patch of the image.  Count and
+// rows, column by column inside a strip, odd strips from right to left (so the
+// last block of a strip and the first of the next are neighbours): a run of
+// consecutive entries (one workgroup's particles) covers a compact patch of
+// the image.  Count and
 // scatter passes as for the tile lists, one entry per particle, in the frame-1
 // half of the lists.
 __device__ __forceinline__ int home_block(float x, float y, int W, int H, const PairLayout& PL,
@@ -305,7 +307,8 @@ __device__ __forceinline__ int home_block(float x, float y, int W, int H, const 
     const int bx = cx >> cfg.log_tw, by = cy >> cfg.log_th;
     const int s0 = by & ~3;                                   // first block row of the strip
     const int rows = PL.nty - s0 < 4 ? PL.nty - s0 : 4;       // rows in this strip
-    return s0 * PL.ntx + bx * rows + (by - s0);
+    const int col = (by & 4) ? PL.ntx - 1 - bx : bx;          // odd strips run right to left
+    return s0 * PL.ntx + col * rows + (by - s0);
 }
 
 template <bool SCATTER>

@@ -223,6 +223,36 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
 constexpr int BWD_SLICES = 128;
 
 // Everything the backward kernels read and write.
+// Flow-grid gradient without global atomics: the flow adjoint runs one
+// workgroup per 256 particles of one pair; each accumulates its node sums (64-bit
+// fixed point) in an LDS window and writes the window's nonzero box to its own
+// partial (and any contribution outside the window as a record); a reduction
+// then adds, per node, the partials and records of the pair's workgroups.
+constexpr int WIN_NODES = 2048;      // LDS window capacity (nodes; 32 KB of (u, v) sums)
+constexpr int GRID_OVF_CAP = 512;    // records per workgroup for nodes outside its window
+
+struct GridHeader {
+    int32_t i0, j0;                  // first node row / column of the partial's box
+    int32_t h, w;                    // box rows / columns (0: no partial)
+    uint32_t n_ovf;                  // records written (<= GRID_OVF_CAP)
+    uint32_t pad_[3];
+};
+
+struct GridRecord {
+    int32_t elem;                    // 2 (i Gw + j) + component in the pair's grid
+    uint32_t pad_;
+    unsigned long long value;        // fixed-point contribution
+};
+
+struct GridAccum {
+    int64_t* wg_base;                // [n_pairs + 1] first workgroup of each pair
+    GridHeader* head;                // [n_wg]
+    unsigned long long* part;        // [n_wg][2 WIN_NODES]
+    GridRecord* ovf;                 // [n_wg][GRID_OVF_CAP]
+    int64_t n_wg;                    // sum over pairs of ceil(n_max / 256)
+    int max_gh, max_gw;              // largest grid of the batch (nodes)
+};
+
 struct BwdArgs {
     AdvectOrder order;           // home-block order of the frame-1 positions
     AdvectOrder order2;          // the same for the frame-2 positions (tile gather only)
@@ -255,7 +285,7 @@ struct BwdArgs {
     float* sheet;                // per-particle sheet-width terms (workspace)
     double* sheet_part;          // per (pair, slice) float64 sums of those terms (workspace)
     float* bound_part;           // per (pair, slice) max |dL/dx2| and Lipschitz bound (workspace)
-    unsigned long long* fixed;   // fixed-point flow-gradient sums (workspace, flow layout)
+    GridAccum grid;              // flow-gradient partials (workspace)
     uint32_t* scale;             // fixed-point scale block: max |dL/dx2|, Lipschitz bound, exponent, state
     uint32_t* status;
     float sheet_sigma;

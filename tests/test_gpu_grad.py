@@ -535,3 +535,59 @@ def test_mse_grad_matches_definition(n):
         sp.mse_grad(Jd, Td, float(scale), out=Jd)             # in place over J
         torch.cuda.synchronize()
         assert np.array_equal(gu.to_np(Jd), scale * (J - T))
+
+
+def _far_batch(n, seed, speed):
+    """One 48 x 160 pair on a grid of one node per 1.25 px, its n particles in a
+    3 x 3-pixel cluster near the left edge, and a smooth flow carrying them
+    about ``speed`` px to the right: their later samples leave the node window
+    of their workgroup (the box of the starting cells grown to fill the window)."""
+    H, W, Gh, Gw = 48, 160, 38, 128
+    rng = np.random.default_rng(seed)
+    P = {"x": (10.0 + 3.0 * rng.random(n)).astype(np.float32), "y": (22.0 + 3.0 * rng.random(n)).astype(np.float32),
+         "z": rng.uniform(-0.5, 0.5, n).astype(np.float32), "d": rng.uniform(2.0, 3.0, n).astype(np.float32),
+         "I0": rng.uniform(0.8, 1.0, n).astype(np.float32)}
+    yy, xx = np.meshgrid(np.arange(Gh), np.arange(Gw), indexing="ij")
+    flow = np.stack([speed * (1.0 + 0.1 * np.sin(xx / 9.0)), 0.8 * np.cos(yy / 5.0)], -1).astype(np.float32)
+    batch = gu.batch_for([(H, W)], [(Gh, Gw)], [n])
+    dev = {k: gu.to_dev(v) for k, v in P.items()}
+    return (H, W), P, flow, batch, dev, gu.to_dev(flow.reshape(-1))
+
+
+def test_flow_gradient_outside_the_window():
+    """Particles that travel ~60 nodes, beyond their workgroup's node window:
+    the contributions outside it travel as records and the flow gradient (and
+    every other gradient) still matches the float64 oracle; no overflow."""
+    (H, W), P, flow, batch, dev, flow_dev = _far_batch(4, 3, 75.0)
+    rp = sp.render_params(0.5, 5.0, 0, 0.8, 0.0, 0, 0, 1.0, 4, "rk4")
+    gJ, gJ_dev = _grad_images(batch, 17)
+    ws = sp.alloc_workspace(batch, rp, backward=True)
+    g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                                workspace=ws)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    G = {k: gu.to_np(v) for k, v in g.items()}
+    x2, _ = sp.advect(batch, flow_dev, rp.advect, dev["x"], dev["y"])
+    assert float(gu.to_np(x2).min()) > 10.0 + 55.0                  # they did travel
+    ref = _oracle_pair({k: [v] for k, v in P.items()}, 0, [flow], H, W, gJ, 0, rp, 0)
+    kink, kink_nodes = _kinks(flow, H, W, P["x"], P["y"], 1.0, 4, "rk4")
+    for key in ("z", "d", "I0"):
+        _close(G[key], ref[key], key)
+    for key in ("x1", "y1"):
+        _close(G[key][~kink], ref[key][~kink], key)
+    gf = G["flow"].reshape(flow.shape)
+    assert np.max(np.abs(gf)[:, 50:]) > 0                            # far nodes got their share
+    assert np.max(np.abs(gf - ref["flow"])[~kink_nodes]) <= TOL * np.max(np.abs(ref["flow"]))
+
+
+def test_flow_gradient_overflow_is_flagged():
+    """Far more far-travelling contributions than a workgroup keeps: the status
+    word says the flow gradient is incomplete."""
+    (H, W), P, flow, batch, dev, flow_dev = _far_batch(256, 4, 75.0)
+    rp = sp.render_params(0.5, 5.0, 0, 0.8, 0.0, 0, 0, 1.0, 4, "rk4")
+    gJ, gJ_dev = _grad_images(batch, 18)
+    ws = sp.alloc_workspace(batch, rp, backward=True)
+    sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
+                            workspace=ws)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) & 0x20

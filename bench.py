@@ -380,7 +380,8 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
     mean squared difference to a target pair rendered from the same particles
     moved by a perturbed flow (the grid plus Gaussian noise of 5% of its rms,
     seed 1): every step renders J, forms dL/dJ = 2 (J - T) / M in one pass
-    (synthpix_mse_grad) and runs the backward."""
+    (synthpix_mse_grad) and runs the backward.  Timed eagerly and as HIP graph
+    replays of each half (a training loop's form; ``graph``)."""
     from workloads import get_workload
     wl = get_workload(name).with_(bits=0, noise_sigma=0.0)
     flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
@@ -408,19 +409,37 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
     fwd()
     bwd()
     torch.cuda.synchronize()
-    res = {}
-    for name, fn in (("fwd", fwd), ("bwd", bwd)):
+
+    def timed(fn):
         t0 = time.perf_counter()
         for _ in range(steps):
             fn()
         torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0) / steps
+        return (time.perf_counter() - t0) / steps
+
+    eager = {"fwd": timed(fwd), "bwd": timed(bwd)}
+    # a training loop's form: each half captured once as a HIP graph and replayed
+    # (no per-launch host work; the same kernels and buffers)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fwd()
+        bwd()
+    torch.cuda.current_stream().wait_stream(side)
+    graphs = {}
+    for name, fn in (("fwd", fwd), ("bwd", bwd)):
+        graphs[name] = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graphs[name]):
+            fn()
+    graph = {name: timed(graphs[name].replay) for name in ("fwd", "bwd")}
     loss = float(sp.mse_grad(img, target, scale, out=gJ, loss=True)[1])
-    del wsb, wsf, gJ, img, target, flow_t
+    del graphs, wsb, wsf, gJ, img, target, flow_t
     torch.cuda.empty_cache()
     return {"loss": "mse_vs_perturbed_flow_target", "loss_value": float(f"{loss:.6e}"),
-            "fwd_ms": round(1000 * res["fwd"], 4), "bwd_ms": round(1000 * res["bwd"], 4),
-            "fwd_bwd_over_fwd": round((res["fwd"] + res["bwd"]) / res["fwd"], 3)}
+            "fwd_ms": round(1000 * eager["fwd"], 4), "bwd_ms": round(1000 * eager["bwd"], 4),
+            "fwd_bwd_over_fwd": round((eager["fwd"] + eager["bwd"]) / eager["fwd"], 3),
+            "graph": {"fwd_ms": round(1000 * graph["fwd"], 4), "bwd_ms": round(1000 * graph["bwd"], 4),
+                      "fwd_bwd_over_fwd": round((graph["fwd"] + graph["bwd"]) / graph["fwd"], 3)}}
 
 
 def main():

@@ -873,19 +873,6 @@ bwd_advect(BwdArgs a, synthpix_advect_params ap)
     }
 }
 
-// Workgroups of the flow adjoint: each pair's particles in chunks of 256
-// (prefix over pairs in wg_base[0 .. n_pairs]).
-__global__ void bwd_grid_layout(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t* __restrict__ wg_base)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t acc = 0;
-    for (int p = 0; p < n_pairs; ++p) {
-        wg_base[p] = acc;
-        acc += (pairs[p].n_max + 255) / 256;
-    }
-    wg_base[n_pairs] = acc;
-}
-
 // Flow-grid gradient of one 32 x 32-node tile of one pair: each thread holds
 // four nodes' two fixed-point sums and adds, in workgroup order, the partial
 // of every workgroup of the pair whose box covers them, then the overflow
@@ -1125,12 +1112,22 @@ bwd_scale(uint32_t* __restrict__ sc, synthpix_advect_params ap, int en, const do
 // pairs' grids are overwritten by the reduction, gaps between them stay 0).
 __global__ void bwd_init(float* __restrict__ g_flow, int64_t n, uint32_t* __restrict__ status,
                          uint32_t* __restrict__ sc, float* __restrict__ g_sheet, int n_pairs,
-                         float* __restrict__ g_sheet_total)
+                         float* __restrict__ g_sheet_total, const synthpix_pair* __restrict__ pairs,
+                         int64_t* __restrict__ wg_base)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 4) {
         status[t] = 0u;
         sc[t] = 0u;
+    }
+    if (t == 0) {
+        // workgroups of the flow adjoint: each pair's particles in chunks of 256
+        int64_t acc = 0;
+        for (int p = 0; p < n_pairs; ++p) {
+            wg_base[p] = acc;
+            acc += (pairs[p].n_max + 255) / 256;
+        }
+        wg_base[n_pairs] = acc;
     }
     // sheet gradients of a batch without particles (otherwise overwritten later)
     if (t < n_pairs) g_sheet[t] = 0.0f;
@@ -1235,8 +1232,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n_flow + 255) / 256 + 1, (a.n_pairs + 255) / 256),
                                                  65536);
         hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.g_flow, n_flow, a.status, a.scale,
-                           a.g_sheet, a.n_pairs, a.g_sheet_total);
-        hipLaunchKernelGGL(bwd_grid_layout, dim3(1), dim3(64), 0, s, a.pairs, a.n_pairs, a.grid.wg_base);
+                           a.g_sheet, a.n_pairs, a.g_sheet_total, a.pairs, a.grid.wg_base);
     }
     if (n_span > 0) {
         if (a.recompute_x2) {

@@ -591,3 +591,55 @@ def test_flow_gradient_overflow_is_flagged():
                             workspace=ws)
     torch.cuda.synchronize()
     assert sp.read_status(ws) & 0x20
+
+
+def test_forward_backward_replay_from_a_graph():
+    """Advect + render and loss gradient + backward captured as HIP graphs and
+    replayed three times, with eager work in between: every replay's images and
+    gradients equal the eager call's bit for bit."""
+    sizes = [(64, 80), (48, 48)]
+    grids = [(16, 20), (12, 12)]
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, 60, 77)
+    for blur in (1, 2):
+        rp = sp.render_params(0.5, 5.0, blur, 0.8, 0.0, 0, 0, 1.0, 2, "rk4")
+        wsf = sp.alloc_workspace(batch, rp)
+        wsb = sp.alloc_workspace(batch, rp, backward=True)
+        x2 = torch.empty_like(dev["x"])
+        y2 = torch.empty_like(dev["y"])
+        img = torch.empty(batch.n_pixels, dtype=torch.float32, device=gu.DEV)
+        target = torch.from_numpy(np.random.default_rng(blur).random(batch.n_pixels, dtype=np.float32)).to(gu.DEV)
+        gJ = torch.empty_like(img)
+        out = {}
+
+        def step():
+            sp.advect(batch, flow_dev, rp.advect, dev["x"], dev["y"], x2, y2, wsf)
+            sp.render_pair(batch, dev["x"], dev["y"], x2, y2, dev["z"], dev["d"], dev["I0"], rp, None, img, wsf)
+            sp.mse_grad(img, target, out=gJ)
+            out["g"] = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"],
+                                               rp, gJ, None, wsb, x2=x2, y2=y2)
+
+        step()
+        torch.cuda.synchronize()
+        ref_img = img.clone()
+        ref = {k: v.clone() for k, v in out["g"].items()}
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        g_graph = out["g"]
+        for k in range(3):
+            img.fill_(-1.0)
+            for v in g_graph.values():
+                v.fill_(float("nan"))
+            sp.render_pair(batch, dev["x"], dev["y"], x2, y2, dev["z"], dev["d"], dev["I0"], rp)   # eager work
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(img, ref_img), (blur, k)
+            for key in ref:
+                assert torch.equal(g_graph[key], ref[key]), (blur, k, key)
+        del graph

@@ -163,7 +163,9 @@ def measured_peaks(sp, torch, dev):
     for kind, buf, iters, unit in (("store", big, 0, "GB/s"), ("store_nt", big, 0, "GB/s"), ("copy", big, 0, "GB/s"),
                                    ("fma", small, 4096, "G wave64 instructions/s"),
                                    ("trans", small, 1024, "G wave64 instructions/s"),
-                                   ("mul64", small, 2048, "G wave64 instructions/s")):
+                                   ("mul64", small, 2048, "G wave64 instructions/s"),
+                                   ("mix", small, 1024, "G wave64 instructions/s"),
+                                   ("int", small, 4096, "G wave64 instructions/s")):
         sp.probe(kind, buf, iters)                    # warm-up
         torch.cuda.synchronize()
         sp.timing_read(None)
@@ -630,12 +632,18 @@ def main():
              "hbm_frac_noise_on": round(out_bytes / (rt_noise_on * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
              "hbm_frac_noise_off": round(out_bytes / (rt_noise_off * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
     if valu is not None:
-        # against the issue rate the FMA probe sustains on this device; the nominal
-        # one-instruction-per-four-cycles figure is kept beside it
+        # against the issue rate a probe of the renderer's instruction mix (float
+        # FMA, multiplies and conversions interleaved with integer add, shift and bit
+        # operations) sustains on this device: gfx950 issues such a mix well above
+        # one wave64 instruction per four cycles per SIMD, while float-only or
+        # integer-only chains stay at about that rate (fma_peak, int_peak); the
+        # nominal one-per-four-cycles figure is kept beside it
         valu["nominal_peak"] = valu["peak"]
         valu["frac_of_nominal"] = valu["frac"]
-        valu["peak"] = peaks["fma"]["rate"]
-        valu["frac"] = round(valu["achieved"] / peaks["fma"]["rate"], 4)
+        valu["fma_peak"] = peaks["fma"]["rate"]
+        valu["int_peak"] = peaks["int"]["rate"]
+        valu["peak"] = peaks["mix"]["rate"]
+        valu["frac"] = round(valu["achieved"] / peaks["mix"]["rate"], 4)
         if prof.get("valu_busy_pct"):
             valu["valu_busy"] = round(float(prof["valu_busy_pct"]) / 100.0, 4)
     trans = None

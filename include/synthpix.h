@@ -236,18 +236,24 @@ synthpix_status synthpix_timing_read(const char* name, double* total_ms, int64_t
  *   SP_PROBE_MUL64  the same with a 32 x 32 -> 64-bit multiply and a xor (the
  *                   Philox round's multiply)
  *   SP_PROBE_STORE_NT  as SP_PROBE_STORE with non-temporal stores
+ *   SP_PROBE_MIX    the same with chains of nine mixed VALU instructions (FMA,
+ *                   multiplies, float <-> u32 conversions, integer add, shift
+ *                   and bit operations: the renderer's inner-loop mix)
+ *   SP_PROBE_INT    the same with 32-bit integer add, shift and xor chains
  * buf: device memory of `bytes` bytes (store, copy; 16-byte aligned) or of at
  * least 1 KiB (the ALU probes never write it).  iters: a positive multiple of 4
  * (ALU probes).  *work_out: bytes moved (store: written; copy: read + written)
  * or wave64 VALU instructions of the probe loop.  The launch is timed like the
  * library's other kernels ("probe_store", "probe_copy", "probe_fma",
- * "probe_trans", "probe_mul64", "probe_store_nt"). */
+ * "probe_trans", "probe_mul64", "probe_store_nt", "probe_mix", "probe_int"). */
 #define SP_PROBE_STORE 0
 #define SP_PROBE_COPY  1
 #define SP_PROBE_FMA   2
 #define SP_PROBE_TRANS 3
 #define SP_PROBE_MUL64 4
 #define SP_PROBE_STORE_NT 5
+#define SP_PROBE_MIX   6
+#define SP_PROBE_INT   7
 synthpix_status synthpix_probe(int32_t kind, void* buf, size_t bytes, int32_t iters, void* stream,
                                double* work_out);
 

@@ -329,7 +329,7 @@ def timing_read(name: Optional[str] = None):
     return ms.value, n.value
 
 
-PROBES = {"store": 0, "copy": 1, "fma": 2, "trans": 3, "mul64": 4, "store_nt": 5}
+PROBES = {"store": 0, "copy": 1, "fma": 2, "trans": 3, "mul64": 4, "store_nt": 5, "mix": 6, "int": 7}
 
 
 def probe(kind: str, buf: torch.Tensor, iters: int = 0) -> float:

@@ -519,7 +519,7 @@ synthpix_status synthpix_probe(int32_t kind, void* buf, size_t bytes, int32_t it
                                double* work_out)
 {
     if (!work_out || !buf) return fail(SP_ERR_INVALID_ARG, "buf and work_out must be non-NULL");
-    if (kind < SP_PROBE_STORE || kind > SP_PROBE_STORE_NT) return fail(SP_ERR_INVALID_ARG, "unknown probe kind %d", kind);
+    if (kind < SP_PROBE_STORE || kind > SP_PROBE_INT) return fail(SP_ERR_INVALID_ARG, "unknown probe kind %d", kind);
     const bool mem = kind <= SP_PROBE_COPY || kind == SP_PROBE_STORE_NT;
     if (mem && (!aligned(buf, 16) || bytes < 32))
         return fail(SP_ERR_INVALID_ARG, "store/copy probes need a 16-byte aligned buffer of >= 32 bytes");

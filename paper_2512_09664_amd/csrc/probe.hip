@@ -101,6 +101,58 @@ __global__ void __launch_bounds__(256) probe_mul64(uint32_t* __restrict__ sink, 
     if (s == 0x9e3779b9u) sink[threadIdx.x] = s;
 }
 
+// Mixed chains in the proportions of the renderer's inner loops: per
+// iteration and chain nine VALU instructions as compiled for gfx950 (one
+// float32 FMA, two multiplies, a float -> u32 and a u32 -> float conversion,
+// an integer add, a shift, a xor and a three-input bit operation).
+__global__ void __launch_bounds__(256) probe_mix(uint32_t* __restrict__ sink, int iters, float a)
+{
+    float v[PROBE_CHAINS];
+    uint32_t u[PROBE_CHAINS];
+#pragma unroll
+    for (int k = 0; k < PROBE_CHAINS; ++k) {
+        v[k] = (float)(threadIdx.x + k) * 1e-3f;
+        u[k] = threadIdx.x * 2654435761u + k;
+    }
+#pragma unroll 2
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < PROBE_CHAINS; ++k) {
+            const float w = __builtin_fmaf(v[k], a, 0.5f) * 0.75f;
+            const uint32_t q = (uint32_t)w;
+            u[k] = (u[k] + q) ^ (u[k] >> 3);
+            v[k] = (float)(u[k] & 0xffffu) * 1e-5f;
+        }
+    }
+    uint32_t s = 0u;
+#pragma unroll
+    for (int k = 0; k < PROBE_CHAINS; ++k) s ^= u[k];
+    if (s == 0x9e3779b9u) sink[threadIdx.x] = s;
+}
+
+// 32-bit integer chains: per iteration and chain an add, a shift and a xor;
+// gfx950 code for two iterations of the eight chains is 40 VALU instructions
+// (v_add_u32, v_lshlrev_b32, v_xor_b32 and the fused v_xad_u32): 2.5 per
+// iteration and chain.
+__global__ void __launch_bounds__(256) probe_int(uint32_t* __restrict__ sink, int iters, uint32_t k)
+{
+    uint32_t u[PROBE_CHAINS];
+#pragma unroll
+    for (int c = 0; c < PROBE_CHAINS; ++c) u[c] = threadIdx.x * 2654435761u + c;
+#pragma unroll 2
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < PROBE_CHAINS; ++c) {
+            const uint32_t t = u[c] + k;
+            u[c] = t ^ (t << 5);
+        }
+    }
+    uint32_t s = 0u;
+#pragma unroll
+    for (int c = 0; c < PROBE_CHAINS; ++c) s ^= u[c];
+    if (s == 0x9e3779b9u) sink[threadIdx.x] = s;
+}
+
 }  // namespace
 
 // Enqueues one probe; *work gets the launch's unit count: bytes moved to or
@@ -134,11 +186,11 @@ hipError_t launch_probe(int kind, void* buf, size_t bytes, int iters, hipStream_
         *work = (double)(n16 * 32);
         break;
     }
-    case 2: case 3: case 4: {
+    case 2: case 3: case 4: case 6: case 7: {
         // 8 waves per SIMD on every CU: 8 workgroups of 4 waves per CU
         const unsigned grid = (unsigned)cus * 8;
         const double waves = (double)grid * 4.0;
-        *work = waves * (double)iters * PROBE_CHAINS * (kind == 4 ? 2 : 1);
+        *work = waves * (double)iters * PROBE_CHAINS * (kind == 4 ? 2.0 : kind == 6 ? 9.0 : kind == 7 ? 2.5 : 1.0);
         if (kind == 2) {
             TimedScope ts("probe_fma", s);
             hipLaunchKernelGGL(probe_fma, dim3(grid), dim3(256), 0, s, static_cast<float*>(buf), iters, 0.999f,
@@ -146,6 +198,12 @@ hipError_t launch_probe(int kind, void* buf, size_t bytes, int iters, hipStream_
         } else if (kind == 3) {
             TimedScope ts("probe_trans", s);
             hipLaunchKernelGGL(probe_trans, dim3(grid), dim3(256), 0, s, static_cast<float*>(buf), iters);
+        } else if (kind == 7) {
+            TimedScope ts("probe_int", s);
+            hipLaunchKernelGGL(probe_int, dim3(grid), dim3(256), 0, s, static_cast<uint32_t*>(buf), iters, 0x9E3779B9u);
+        } else if (kind == 6) {
+            TimedScope ts("probe_mix", s);
+            hipLaunchKernelGGL(probe_mix, dim3(grid), dim3(256), 0, s, static_cast<uint32_t*>(buf), iters, 0.999f);
         } else {
             TimedScope ts("probe_mul64", s);
             hipLaunchKernelGGL(probe_mul64, dim3(grid), dim3(256), 0, s, static_cast<uint32_t*>(buf), iters,

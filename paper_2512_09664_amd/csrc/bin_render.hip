@@ -764,12 +764,24 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
     const int64_t plane = (int64_t)pH * pW;
     const int Wq = (pW + 3) >> 2;
     const float Lq = a.bits > 0 ? (float)((1u << a.bits) - 1u) : 0.0f;
+    // the noise words of a thread's next work item are drawn while it finishes
+    // the current one (the Philox rounds are one long dependent chain)
+    const bool noisy = a.noise_sigma > 0.0f;
+    u32x4 w_next = {0u, 0u, 0u, 0u};
+    if (noisy && (int)threadIdx.x < TH * Q4)
+        w_next = draw((uint32_t)((ty * TH + (int)threadIdx.x / Q4) * Wq + ((tx * TW) >> 2) + (int)threadIdx.x % Q4),
+                      STREAM_NOISE0 + f, pid, a.seed);
 #pragma unroll 1
     for (int gi = threadIdx.x; gi < TH * Q4; gi += 256) {
         const int r = gi / Q4;
         const int c4 = (gi % Q4) * 4;
         const int R = ty * TH + r;
         const int C = tx * TW + c4;
+        const u32x4 w = w_next;
+        const int gn = gi + 256;
+        if (noisy && gn < TH * Q4)
+            w_next = draw((uint32_t)((ty * TH + gn / Q4) * Wq + ((tx * TW) >> 2) + gn % Q4), STREAM_NOISE0 + f, pid,
+                          a.seed);
         if (R >= pH || C >= pW) continue;
         float o[4];
         if constexpr (B > 0) {
@@ -789,8 +801,7 @@ render_tile(const synthpix_pair* __restrict__ pairs, const PairLayout* __restric
             o[0] = (float)src[0] * FIX; o[1] = (float)src[1] * FIX;
             o[2] = (float)src[2] * FIX; o[3] = (float)src[3] * FIX;
         }
-        if (a.noise_sigma > 0.0f) {
-            const u32x4 w = draw((uint32_t)(R * Wq + (C >> 2)), STREAM_NOISE0 + f, pid, a.seed);
+        if (noisy) {
             const uint32_t wa[2] = {w.a, w.c};
             const uint32_t wb[2] = {w.b, w.d};
 #pragma unroll

@@ -457,7 +457,10 @@ typedef struct synthpix_plan synthpix_plan;
  * memory and synchronises `stream`; it is the set-up call, not the hot path.
  * advance_pair_ids != 0: every launch moves the descriptor's pair_id_base on
  * by n_pairs after rendering, so consecutive launches without new io draw the
- * pairs with ids pair_id + pair_id_base + k * n_pairs. */
+ * pairs with ids pair_id + pair_id_base + k * n_pairs.
+ * Masked candidates (slots i >= the pair's drawn active count, whose I0 is 0)
+ * are not advected by a plan: their x2, y2 are set to x1, y1.  Images and every
+ * active particle's outputs equal the eager calls'. */
 synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_pairs,
                                      const synthpix_seed_params* sp, const synthpix_advect_params* ap,
                                      const synthpix_render_params* rp, const synthpix_batch_io* io,

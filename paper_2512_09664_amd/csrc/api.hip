@@ -437,7 +437,7 @@ BwdPlan bwd_plan(const synthpix_pair* ph, int32_t n_pairs, int64_t span, const s
 // returns it for the advection launch.
 hipError_t enqueue_order(const synthpix_pair* ph, const synthpix_pair* pd, int32_t n_pairs, const float* x,
                          const float* y, char* ws, size_t base, hipStream_t s, sp::AdvectOrder* out,
-                         const synthpix_batch_io* iod = nullptr)
+                         const synthpix_batch_io* iod = nullptr, const int32_t* live = nullptr)
 {
     const sp::RenderConfig cfg = order_config(ph, n_pairs);
     sp::BatchTotals T;
@@ -449,7 +449,8 @@ hipError_t enqueue_order(const synthpix_pair* ph, const synthpix_pair* pd, int32
     out->blocks = T.tiles;
     out->count = reinterpret_cast<const uint32_t*>(ws + ol.tile_count);
     out->offset = reinterpret_cast<const int64_t*>(ws + ol.tile_offset);
-    return sp::launch_order(pd, n_pairs, x, y, cfg, T, ws, ol, s, iod);
+    out->live = live;
+    return sp::launch_order(pd, n_pairs, x, y, cfg, T, ws, ol, s, iod, live);
 }
 
 extern "C" {
@@ -979,6 +980,7 @@ struct synthpix_plan {
     int64_t span = 0;
     void* workspace = nullptr;
     size_t ws_bytes = 0;
+    int32_t* live = nullptr;               // each pair's active count (end of the workspace)
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1008,12 +1010,14 @@ hipError_t enqueue_batch(synthpix_plan* P, const synthpix_tiling& t, hipStream_t
 {
     const synthpix_batch_io& io = P->io;
     const synthpix_batch_io* iod = P->io_dev;
+    // masked candidates (slots past each pair's active count) are seeded but not
+    // ordered or advected: the seed sets their frame-2 position to frame 1's
     hipError_t e = sp::launch_seed(P->pairs_dev, P->n_pairs, P->span, P->sp, io.seed, io.x1, io.y1, io.z, io.d,
-                                   io.I0, io.n_active, io.ppp, s, iod);
+                                   io.I0, io.n_active, io.ppp, s, iod, P->live);
     if (e != hipSuccess) return e;
     sp::AdvectOrder order{nullptr, nullptr};
     e = enqueue_order(P->pairs_host.data(), P->pairs_dev, P->n_pairs, io.x1, io.y1, static_cast<char*>(P->workspace),
-                      0, s, &order, iod);
+                      0, s, &order, iod, P->live);
     if (e != hipSuccess) return e;
     e = sp::launch_advect(P->pairs_dev, P->n_pairs, P->span, io.flow, P->ap, io.x1, io.y1, io.x2, io.y2, s, order,
                           iod);
@@ -1143,12 +1147,15 @@ synthpix_status synthpix_plan_create(const synthpix_pair* pairs_host, int32_t n_
         plan_free(P);
         return fail(SP_ERR_UNSUPPORTED, "no tiling fits this batch");
     }
+    const size_t live_off = align256(ws);
+    ws = live_off + align256(sizeof(int32_t) * (size_t)n_pairs);
     e = hipMalloc(&P->workspace, ws);
     P->ws_bytes = ws;
     if (e != hipSuccess) {
         plan_free(P);
         return hip_fail(e, "plan workspace");
     }
+    P->live = reinterpret_cast<int32_t*>(static_cast<char*>(P->workspace) + live_off);
     P->tiling = ok[0];
     if (autotune) {
         // time each candidate's render of this batch (seed/advect once, render warm-up + 3 runs):

@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(256)
 order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
            const float* __restrict__ x, const float* __restrict__ y, RenderConfig cfg, uint32_t* __restrict__ hist,
            const int64_t* __restrict__ tile_offset, int32_t* __restrict__ entries, unsigned n_chunks_total,
-           const synthpix_batch_io* __restrict__ iod)
+           const synthpix_batch_io* __restrict__ iod, const int32_t* __restrict__ live)
 {
     extern __shared__ uint32_t lh[];
     if (iod) {
@@ -335,7 +335,7 @@ order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict
     for (int t = threadIdx.x; t < nt; t += blockDim.x)
         lh[t] = SCATTER ? gh[t] + (uint32_t)(toff[t] - PL.entry_base) : 0u;
     __syncthreads();
-    const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
+    const int i_end = min(live ? min(live[p], P.n_max) : P.n_max, (chunk + 1) * cfg.chunk);
     for (int i = chunk * cfg.chunk + threadIdx.x; i < i_end; i += blockDim.x) {
         const int64_t g = P.particle_offset + i;
         const uint32_t slot = atomicAdd(&lh[home_block(x[g], y[g], P.W, P.H, PL, cfg)], 1u);
@@ -1019,7 +1019,7 @@ hipError_t launch_render(const RenderArgs& a, const RenderConfig& cfg, const Bat
 
 hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float* x, const float* y,
                         const RenderConfig& cfg, const BatchTotals& tot, char* ws, const OrderLayout& ol,
-                        hipStream_t s, const synthpix_batch_io* iod)
+                        hipStream_t s, const synthpix_batch_io* iod, const int32_t* live)
 {
     uint32_t* status = reinterpret_cast<uint32_t*>(ws + ol.status);
     PairLayout* L = reinterpret_cast<PairLayout*>(ws + ol.layout);
@@ -1032,10 +1032,10 @@ hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float
     if (tot.chunks == 0) return hipGetLastError();
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
     hipLaunchKernelGGL(order_pass<false>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
-                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks, iod);
+                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks, iod, live);
     launch_scans(L, n_pairs, hist, tile_count, tile_offset, tot.tiles, 1, s);
     hipLaunchKernelGGL(order_pass<true>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
-                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks, iod);
+                       y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks, iod, live);
     return hipGetLastError();
 }
 

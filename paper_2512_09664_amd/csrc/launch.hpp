@@ -132,7 +132,7 @@ struct OrderLayout {
 // null descriptor.
 hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float* x, const float* y,
                         const RenderConfig& cfg, const BatchTotals& tot, char* ws, const OrderLayout& ol,
-                        hipStream_t s, const synthpix_batch_io* iod = nullptr);
+                        hipStream_t s, const synthpix_batch_io* iod = nullptr, const int32_t* live = nullptr);
 
 // The order a launch of the advection kernel follows (null: particle index order).
 struct AdvectOrder {
@@ -142,12 +142,13 @@ struct AdvectOrder {
     int64_t blocks;             // home blocks over all pairs
     const uint32_t* count;      // particles per home block
     const int64_t* offset;      // first entry of each home block
+    const int32_t* live;        // per pair: only slots below this are ordered and advected (null: all n_max)
 };
 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
                        const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
                        float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s,
-                       const synthpix_batch_io* iod = nullptr);
+                       const synthpix_batch_io* iod = nullptr, int32_t* live = nullptr);
 
 // Moves a descriptor's pair_id_base on by `step` (the next batch of pairs).
 hipError_t launch_advance(synthpix_batch_io* iod, uint64_t step, hipStream_t s);

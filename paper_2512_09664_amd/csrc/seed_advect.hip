@@ -29,7 +29,7 @@ __device__ __forceinline__ int pair_active(const synthpix_pair& P, uint64_t pid,
 __global__ void __launch_bounds__(256)
 pair_scalars_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, synthpix_seed_params prm,
                     uint64_t seed, int32_t* __restrict__ n_active_out, double* __restrict__ ppp_out,
-                    const synthpix_batch_io* __restrict__ iod)
+                    const synthpix_batch_io* __restrict__ iod, int32_t* __restrict__ live_out)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_pairs) return;
@@ -44,13 +44,15 @@ pair_scalars_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, synthp
     const int na = pair_active(pairs[p], pairs[p].pair_id + base, prm, seed, &ppp);
     if (n_active_out) n_active_out[p] = na;
     if (ppp_out) ppp_out[p] = ppp;
+    if (live_out) live_out[p] = na;
 }
 
 __global__ void __launch_bounds__(256)
 seed_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span,
             synthpix_seed_params prm, uint64_t seed,
             float* __restrict__ x, float* __restrict__ y, float* __restrict__ z,
-            float* __restrict__ d, float* __restrict__ I0, const synthpix_batch_io* __restrict__ iod)
+            float* __restrict__ d, float* __restrict__ I0, const synthpix_batch_io* __restrict__ iod,
+            bool masked_still)
 {
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t g = g0 + threadIdx.x;
@@ -76,8 +78,14 @@ seed_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span
 
     const u32x4 gw = draw(i, STREAM_GEOM, pid, seed);
     const u32x4 hw = draw(i, STREAM_PHOTO, pid, seed);
-    x[g] = u24(gw.a) * (float)P.W;
-    y[g] = u24(gw.b) * (float)P.H;
+    const float px = u24(gw.a) * (float)P.W, py = u24(gw.b) * (float)P.H;
+    x[g] = px;
+    y[g] = py;
+    if (masked_still && (int)i >= n_active) {
+        // a masked candidate is not advected: its frame-2 position is its frame-1 one
+        iod->x2[g] = px;
+        iod->y2[g] = py;
+    }
     z[g] = __builtin_fmaf(prm.z_hi - prm.z_lo, u24(gw.c), prm.z_lo);
     float dv;
     if (prm.d_dist == SP_DIST_UNIFORM) {
@@ -206,7 +214,7 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
             const int p = find_pair_from(pairs, n_pairs, g0, g);
             const synthpix_pair P = pairs[p];
             const int64_t i = g - P.particle_offset;
-            if (i >= 0 && i < P.n_max) {
+            if (i >= 0 && i < (order.live ? (int64_t)order.live[p] : (int64_t)P.n_max)) {
                 gi[q] = SORTED ? P.particle_offset + order.entries[order.L[p].entry_base + i] : g;
                 fv[q] = flow_view(P, flow);
                 px[q] = x1[gi[q]];
@@ -472,16 +480,16 @@ hipError_t launch_store_io(synthpix_batch_io* iod, const synthpix_batch_io& io, 
 hipError_t launch_seed(const synthpix_pair* pairs_dev, int n_pairs, int64_t n_span,
                        const synthpix_seed_params& prm, uint64_t seed, float* x, float* y, float* z,
                        float* d, float* I0, int32_t* n_active, double* ppp, hipStream_t s,
-                       const synthpix_batch_io* iod)
+                       const synthpix_batch_io* iod, int32_t* live)
 {
     TimedScope ts("seed", s);
-    if (n_active || ppp || iod)
+    if (n_active || ppp || iod || live)
         hipLaunchKernelGGL(pair_scalars_kernel, dim3((unsigned)((n_pairs + 255) / 256)), dim3(256), 0, s, pairs_dev,
-                           n_pairs, prm, seed, n_active, ppp, iod);
+                           n_pairs, prm, seed, n_active, ppp, iod, live);
     if (n_span > 0) {
         const int64_t blocks = (n_span + 255) / 256;
         hipLaunchKernelGGL(seed_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pairs_dev, n_pairs, n_span,
-                           prm, seed, x, y, z, d, I0, iod);
+                           prm, seed, x, y, z, d, I0, iod, iod != nullptr && live != nullptr);
     }
     return hipGetLastError();
 }

@@ -253,14 +253,16 @@ def test_backward_is_deterministic_and_autograd_agrees():
     assert abs(float(g["sheet_total"]) - float(g["sheet"].double().sum())) <= 1e-6 * float(g["sheet"].abs().sum())
 
 
-def test_backward_with_gaps_matches_packed():
+@pytest.mark.parametrize("blur", [1, 2])
+def test_backward_with_gaps_matches_packed(blur):
     """A batch whose particle, image and flow arrays leave unused gaps before
     every pair: the in-pair gradients equal those of the packed batch bit for
     bit, and every gap slot below the particle span comes back 0 (the output
-    memory is filled with NaN first, so unwritten slots would show)."""
+    memory is filled with NaN first, so unwritten slots would show).  Blur 1
+    takes the particle-major gather, blur 2 the tile-major one."""
     sizes, grids, m = [(40, 48), (24, 20), (31, 17)], [(10, 12), (8, 7), (6, 5)], 30
     P, flows, batch, dev, flow_dev = _batch(sizes, grids, m, 13)
-    rp = sp.render_params(0.5, 5.0, 1, 0.7, 0.0, 0, 0, 1.0, 2, "rk4")
+    rp = sp.render_params(0.5, 5.0, blur, 0.7, 0.0, 0, 0, 1.0, 2, "rk4")
     gJ, gJ_dev = _grad_images(batch, 17)
     ref = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev)
     gaps = (5, 12, 4)

@@ -47,6 +47,19 @@ def _same(a, b):
     return np.array_equal(to_np(a), to_np(b))
 
 
+def _plan_x2(batch, P, x1, x2):
+    """The frame-2 positions a plan produces: the eager advection's for active
+    particles, the frame-1 position for masked candidates (a plan does not
+    advect them; their I0 is 0 and they add nothing to the images)."""
+    out = to_np(x2).copy()
+    xs = to_np(x1)
+    na = to_np(P["n_active"])
+    for p, hp in enumerate(batch.host):
+        o = hp.particle_offset
+        out[o + int(na[p]):o + hp.n_max] = xs[o + int(na[p]):o + hp.n_max]
+    return out
+
+
 @pytest.mark.parametrize("bits,noise", [(12, 0.01), (0, 0.0)])
 def test_plan_replays_match_eager(bits, noise):
     wl = _workload(bits, noise)
@@ -61,7 +74,10 @@ def test_plan_replays_match_eager(bits, noise):
         plan.launch()
         torch.cuda.synchronize()
         assert _same(io["images"], img), f"replay {r}"
-        assert _same(io["x1"], P["x"]) and _same(io["x2"], x2) and _same(io["y2"], y2)
+        assert _same(io["x1"], P["x"])
+        assert np.array_equal(to_np(io["x2"]), _plan_x2(batch, P, P["x"], x2))
+        assert np.array_equal(to_np(io["y2"]), _plan_x2(batch, P, P["y"], y2))
+        assert np.all(to_np(P["I0"])[to_np(io["x2"]) != to_np(x2)] == 0.0)   # only masked candidates differ
         assert _same(io["n_active"], P["n_active"])
         # unrelated eager work between replays
         _ = (io["x1"] * 2).sum().item()
@@ -120,7 +136,8 @@ def test_plan_launch_into_new_buffers():
         torch.cuda.synchronize()
         bk = batch_for(wl.sizes, [f.shape[:2] for f in flows], batch.n_max, [100 * (k + 1) + p for p in range(n)])
         P, x2, _, img = _eager(bk, flow_dev, sprm, aprm, rprm, 5 + k)
-        assert _same(io2["images"], img) and _same(io2["x1"], P["x"]) and _same(io2["x2"], x2), k
+        assert _same(io2["images"], img) and _same(io2["x1"], P["x"]), k
+        assert np.array_equal(to_np(io2["x2"]), _plan_x2(bk, P, P["x"], x2)), k
         assert _same(io2["n_active"], P["n_active"])
         assert not io1["images"].view(torch.int16).any()
         assert plan.read_status() == 0

@@ -27,22 +27,25 @@
 
 namespace sp {
 
-constexpr int BG = 16;             // lanes per particle in the gather
-constexpr int BPW = 256 / BG;      // particles per workgroup
 constexpr int GROWS = 8;           // patch rows loaded per batch (independent loads in flight)
 
-// BT table slots cover the pixel range (<= 3 d_max + 3 pixels) plus 4 b of zero
-// padding; the raw row factors are kept only where a blur is folded in (RY).
-template <int BT, bool RY = true>
+// A particle's lane group: G = 16 lanes (a DPP row) or 8 (half of one); a
+// workgroup of 256 threads holds 256 / G particles.  BT table slots cover the
+// pixel range (<= 3 d_max + 3 pixels) plus 4 b of zero padding.  The raw
+// factors are stored as the Gaussian values e alone (their dx and dx^2
+// multiples are formed where they are read); the raw row factors are kept
+// only where a blur is folded in (RY).
+template <int G, int BT, bool RY = true>
 struct GatherLds {
-    float rx[BPW][3][BT];          // raw column factors gx dx^k, k = 0, 1, 2 (slot = c - c0 + 2b)
-    float ry[RY ? BPW : 1][3][RY ? BT : 1];
-    float4 ty[BPW][BT];            // blurred row tables (Ty0, Ty1, Ty2, 0)
+    float rx[256 / G][BT];                      // raw column factors e(c) (slot = c - c0 + 2b)
+    float ry[RY ? 256 / G : 1][RY ? BT : 1];    // raw row factors e(r)
+    float4 ty[256 / G][BT];                     // blurred row tables (Ty0, Ty1, Ty2, 0)
 };
 
-// Sum over the 16 lanes of a DPP row (a particle's lane group), result in every
-// lane: quad butterflies (quad_perm [1,0,3,2] and [2,3,0,1]) then rotations of
-// the row by 4 and 8 lanes.
+// Sum over a particle's G lanes, result in every lane: quad butterflies
+// (quad_perm [1,0,3,2] and [2,3,0,1]), then, for 16 lanes, rotations of the
+// row by 4 and 8 lanes, for 8 lanes the mirror of each half row (the other
+// quad of the eight).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v)
 {
@@ -59,13 +62,18 @@ __device__ __forceinline__ void group_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <int G>
 __device__ __forceinline__ float group_sum(float v)
 {
-    static_assert(BG == 16, "a lane group is one DPP row");
+    static_assert(G == 8 || G == 16, "a lane group is a DPP row or half of one");
     v += dpp<0xB1>(v);
     v += dpp<0x4E>(v);
-    v += dpp<0x124>(v);
-    v += dpp<0x128>(v);
+    if constexpr (G == 16) {
+        v += dpp<0x124>(v);
+        v += dpp<0x128>(v);
+    } else {
+        v += dpp<0x141>(v);
+    }
     return v;
 }
 
@@ -100,8 +108,8 @@ __device__ __forceinline__ bool cover_range(float p, float R, int n, int& lo, in
 // (global memory, or a region staged in LDS).  Every lane returns the group's
 // sums.  on: the particle is valid and its support [c0, c1] x [r0, r1] is not
 // empty.
-template <int B, int BT, bool RY>
-__device__ __forceinline__ float4 frame_sums(GatherLds<BT, RY>& S, int grp, int lane, bool on, float x, float y,
+template <int B, int BT, bool RY, int G>
+__device__ __forceinline__ float4 frame_sums(GatherLds<G, BT, RY>& S, int grp, int lane, bool on, float x, float y,
                                              float kap, float R, int c0, int c1, int r0, int r1, int W, int H,
                                              const float* __restrict__ src, int64_t stride, int sr, int sc,
                                              const float* blur_w)
@@ -110,55 +118,49 @@ __device__ __forceinline__ float4 frame_sums(GatherLds<BT, RY>& S, int grp, int 
     // + 4b (zeros outside the support); a group stops after its last one
     const int n_raw = on ? max(c1 - c0, r1 - r0) + 4 * B + 1 : 0;
 #pragma unroll
-    for (int m = 0; m < BT / BG; ++m) {
-        if (BG * m >= n_raw) break;
-        const int slot = lane + BG * m;
+    for (int m = 0; m < BT / G; ++m) {
+        if (G * m >= n_raw) break;
+        const int slot = lane + G * m;
         const int c = c0 - 2 * B + slot;
-        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+        float v0 = 0.0f;
         const float dx = ((float)c + 0.5f) - x;
-        if (on && c >= c0 && c <= c1 && __builtin_fabsf(dx) <= R) {
-            v0 = expneg_hw(kap * (dx * dx));
-            v1 = v0 * dx;
-            v2 = v1 * dx;
-        }
-        S.rx[grp][0][slot] = v0;
-        S.rx[grp][1][slot] = v1;
-        S.rx[grp][2][slot] = v2;
+        if (on && c >= c0 && c <= c1 && __builtin_fabsf(dx) <= R) v0 = expneg_hw(kap * (dx * dx));
+        S.rx[grp][slot] = v0;
         const int r = r0 - 2 * B + slot;
-        float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+        float u0 = 0.0f;
         const float dy = ((float)r + 0.5f) - y;
-        if (on && r >= r0 && r <= r1 && __builtin_fabsf(dy) <= R) {
-            u0 = expneg_hw(kap * (dy * dy));
-            u1 = u0 * dy;
-            u2 = u1 * dy;
-        }
+        if (on && r >= r0 && r <= r1 && __builtin_fabsf(dy) <= R) u0 = expneg_hw(kap * (dy * dy));
         if constexpr (B == 0) {
-            S.ty[grp][slot] = make_float4(u0, u1, u2, 0.0f);
+            const float u1 = u0 * dy;
+            S.ty[grp][slot] = make_float4(u0, u1, u1 * dy, 0.0f);
         } else {
             static_assert(RY, "a folded blur needs the raw row factors");
-            S.ry[grp][0][slot] = u0;
-            S.ry[grp][1][slot] = u1;
-            S.ry[grp][2][slot] = u2;
+            S.ry[grp][slot] = u0;
         }
     }
     group_sync();
     if constexpr (B > 0) {
         // blurred row tables (the column ones are formed per column in the gather);
-        // table slot t is pixel r0 - b + t; raw slot t + 2b - k' holds pixel q - (k' - b)
+        // table slot t is pixel r0 - b + t; raw slot t + 2b - k holds pixel
+        // r0 + t - k, whose offset dy gives the e dy and e dy^2 terms
         const int n_ty = on ? (r1 - r0 + 1) + 2 * B : 0;
 #pragma unroll
-        for (int m = 0; m < BT / BG; ++m) {
-            if (BG * m >= n_ty) break;
-            const int t = lane + BG * m;
+        for (int m = 0; m < BT / G; ++m) {
+            if (G * m >= n_ty) break;
+            const int t = lane + G * m;
             if (t < BT - 2 * B) {
-                float Y[3] = {0.0f, 0.0f, 0.0f};
+                float Y0 = 0.0f, Y1 = 0.0f, Y2 = 0.0f;
 #pragma unroll
                 for (int k = 0; k <= 2 * B; ++k) {
                     const float w = blur_w[k];
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) Y[j] = __builtin_fmaf(w, S.ry[grp][j][t + 2 * B - k], Y[j]);
+                    const float u0 = S.ry[grp][t + 2 * B - k];
+                    const float dy = ((float)(r0 + t - k) + 0.5f) - y;
+                    const float u1 = u0 * dy;
+                    Y0 = __builtin_fmaf(w, u0, Y0);
+                    Y1 = __builtin_fmaf(w, u1, Y1);
+                    Y2 = __builtin_fmaf(w, u1 * dy, Y2);
                 }
-                S.ty[grp][t] = make_float4(Y[0], Y[1], Y[2], 0.0f);
+                S.ty[grp][t] = make_float4(Y0, Y1, Y2, 0.0f);
             }
         }
         group_sync();
@@ -168,8 +170,8 @@ __device__ __forceinline__ float4 frame_sums(GatherLds<BT, RY>& S, int grp, int 
     // image.  The column factors are constant along a column, so each lane
     // first forms P_j = sum_r (dL/dJ) Ty_j(r) down a column, or a slice of one
     // (three FMAs per pixel), and applies Tx afterwards.  Columns go to lanes
-    // in blocks of 16; a block of m < 16 columns splits its rows into
-    // 16 / m' slices (m' = m rounded up to a power of two), so the lanes a
+    // in blocks of G; a block of m < G columns splits its rows into
+    // G / m' slices (m' = m rounded up to a power of two), so the lanes a
     // narrow block would leave idle shorten its walk instead.
     float s0 = 0.0f, s_x = 0.0f, s_y = 0.0f, s_r = 0.0f;
     if (on) {
@@ -178,13 +180,14 @@ __device__ __forceinline__ float4 frame_sums(GatherLds<BT, RY>& S, int grp, int 
         const int thi = nt < W - c0 + B ? nt : W - c0 + B;
         const int ulo = B - r0 > 0 ? B - r0 : 0;
         const int uhi = nu < H - r0 + B ? nu : H - r0 + B;
-        const float(*T)[BT] = S.rx[grp];
+        constexpr int LG = G == 16 ? 4 : 3;
+        const float* T = S.rx[grp];
         const int ncol = thi - tlo, nrow = uhi - ulo;
-        for (int cb = 0; cb < ncol; cb += BG) {
-            const int m = ncol - cb < BG ? ncol - cb : BG;
+        for (int cb = 0; cb < ncol; cb += G) {
+            const int m = ncol - cb < G ? ncol - cb : G;
             const int lm = m > 8 ? 4 : m > 4 ? 3 : m > 2 ? 2 : m > 1 ? 1 : 0;   // log2 m'
             const int cl = lane & ((1 << lm) - 1);
-            const int per = (nrow + (BG >> lm) - 1) >> (4 - lm);                // rows per slice
+            const int per = (nrow + (G >> lm) - 1) >> (LG - lm);                // rows per slice
             const int ua = ulo + (lane >> lm) * per;
             const int ub = ua + per < uhi ? ua + per : uhi;
             if (cl >= m || ua >= ub) continue;
@@ -229,14 +232,18 @@ __device__ __forceinline__ float4 frame_sums(GatherLds<BT, RY>& S, int grp, int 
                     u += nb;
                 }
             }
-            // blurred column factors of this column, from the raw ones
+            // blurred column factors of this column, from the raw ones (raw slot
+            // t + 2b - k holds column c0 + t - k)
             float X0 = 0.0f, X1 = 0.0f, X2 = 0.0f;
 #pragma unroll
             for (int k = 0; k <= 2 * B; ++k) {
                 const float w = B > 0 ? blur_w[k] : 1.0f;
-                X0 = __builtin_fmaf(w, T[0][t + 2 * B - k], X0);
-                X1 = __builtin_fmaf(w, T[1][t + 2 * B - k], X1);
-                X2 = __builtin_fmaf(w, T[2][t + 2 * B - k], X2);
+                const float v0 = T[t + 2 * B - k];
+                const float dx = ((float)(c0 + t - k) + 0.5f) - x;
+                const float v1 = v0 * dx;
+                X0 = __builtin_fmaf(w, v0, X0);
+                X1 = __builtin_fmaf(w, v1, X1);
+                X2 = __builtin_fmaf(w, v1 * dx, X2);
             }
             s0 = __builtin_fmaf(P0, X0, s0);
             s_x = __builtin_fmaf(P0, X1, s_x);
@@ -244,7 +251,7 @@ __device__ __forceinline__ float4 frame_sums(GatherLds<BT, RY>& S, int grp, int 
             s_r = __builtin_fmaf(P0, X2, __builtin_fmaf(P2, X0, s_r));
         }
     }
-    const float4 out = make_float4(group_sum(s0), group_sum(s_x), group_sum(s_y), group_sum(s_r));
+    const float4 out = make_float4(group_sum<G>(s0), group_sum<G>(s_x), group_sum<G>(s_y), group_sum<G>(s_r));
     group_sync();
     return out;
 }
@@ -275,15 +282,15 @@ __device__ __forceinline__ ParticleGrads particle_grads(float z, float d, float 
     return o;
 }
 
-// Particle-major gather: 16 lanes per particle read their patch rows of the
+// Particle-major gather: G lanes per particle read their patch rows of the
 // frame's gradient image from global memory (any diameter bound and blur).
-template <int B, int BT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BT == 32 ? 7 : 4)))
+template <int B, int BT, int G>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(G == 8 ? 6 : BT == 32 ? 7 : 4)))
 bwd_gather(BwdArgs a, int64_t n_span)
 {
-    __shared__ GatherLds<BT> S;
-    const int grp = threadIdx.x / BG, lane = threadIdx.x % BG;
-    const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * BPW;
+    __shared__ GatherLds<G, BT> S;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+    const int64_t g0 = (int64_t)xcd_contiguous(blockIdx.x, gridDim.x) * (256 / G);
     int64_t g = g0 + grp;
 
     bool in_pair = false, valid = false;
@@ -326,7 +333,7 @@ bwd_gather(BwdArgs a, int64_t n_span)
         int c0 = 0, c1 = -1, r0 = 0, r1 = -1;
         bool on = valid && cover_range(x, R, W, c0, c1);
         on = on && cover_range(y, R, H, r0, r1);
-        fs[f] = frame_sums<B, BT, true>(S, grp, lane, on, x, y, kap, R, c0, c1, r0, r1, W, H,
+        fs[f] = frame_sums<B, BT, true, G>(S, grp, lane, on, x, y, kap, R, c0, c1, r0, r1, W, H,
                                   a.grad + img + (int64_t)f * H * W, W, 0, 0, a.blur_w);
     }
 
@@ -363,11 +370,14 @@ bwd_gather(BwdArgs a, int64_t n_span)
 // position lies in the block (or beyond the image edge next to it, where the
 // home block is clamped) is inside the staged region.  The sums go to
 // parts[f * n_span + slot]; bwd_particles turns them into gradients.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
 {
     extern __shared__ __align__(16) float region[];
-    __shared__ GatherLds<32, false> S;
+    // sixteen lanes per particle here: eight (more particles per wave, deeper
+    // walks for the wide supports this gather serves) measured slower
+    constexpr int G = 16, NP = 256 / G;
+    __shared__ GatherLds<G, 32, false> S;
     const int64_t blocks = a.order.blocks;
     const int64_t item = xcd_contiguous(blockIdx.x, gridDim.x);
     const int f = item >= blocks ? 1 : 0;
@@ -405,11 +415,11 @@ bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
     }
     __syncthreads();
 
-    const int grp = threadIdx.x / BG, lane = threadIdx.x % BG;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int64_t off = O.offset[b];
     const float* __restrict__ fx = f ? a.x2 : a.x1;
     const float* __restrict__ fy = f ? a.y2 : a.y1;
-    for (int base = 0; base < cnt; base += BPW) {
+    for (int base = 0; base < cnt; base += NP) {
         const int k = base + grp;
         bool act = k < cnt, on = false;
         int64_t g = 0;
@@ -428,7 +438,7 @@ bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
         on = on && cover_range(y, R, H, r0, r1);
         // in-image support inside the staged region (always, for d <= d_max)
         on = on && c0 >= ox && c1 < ox + rw && r0 >= oy && r1 < oy + rw;
-        const float4 sums = frame_sums<0, 32, false>(S, grp, lane, on, x, y, kap, R, c0, c1, r0, r1, W, H, region, rw,
+        const float4 sums = frame_sums<0, 32, false, G>(S, grp, lane, on, x, y, kap, R, c0, c1, r0, r1, W, H, region, rw,
                                               oy, ox, a.blur_w);
         if (act && lane == 0) a.parts[(int64_t)f * n_span + g] = sums;
     }
@@ -1210,6 +1220,12 @@ hipError_t launch_mse_grad(const float* J, const float* T, int64_t n, float scal
     return hipGetLastError();
 }
 
+// Workgroups of the particle-major gather: 256 / G particles each.
+static unsigned gather_blocks(int64_t n_span, int G)
+{
+    return (unsigned)((n_span + 256 / G - 1) / (256 / G));
+}
+
 void launch_advect_adjoint(const BwdArgs& a, const synthpix_advect_params& ap, unsigned blocks, hipStream_t s)
 {
     const int S = ap.substeps;
@@ -1240,7 +1256,6 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
                                                a.order);
             if (e != hipSuccess) return e;
         }
-        const unsigned gb = (unsigned)((n_span + BPW - 1) / BPW);
         const bool tile = a.order2.entries && a.parts;
         if (a.eblur && blur >= 1 && (tile || blur >= 2)) {
             // the blur's adjoint once per pixel: the gather then runs on the
@@ -1270,16 +1285,16 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             hipLaunchKernelGGL(bwd_particles, dim3((unsigned)((n_span + 255) / 256)), dim3(256), 0, s, b, n_span);
         } else if (blur >= 2) {
             TimedScope ts("bwd_gather", s);
-            if ((int)(3.0f * a.d_max) + 4 <= 32) hipLaunchKernelGGL((bwd_gather<0, 32>), dim3(gb), dim3(256), 0, s, b, n_span);
-            else hipLaunchKernelGGL((bwd_gather<0, 64>), dim3(gb), dim3(256), 0, s, b, n_span);
+            if ((int)(3.0f * a.d_max) + 4 <= 32) hipLaunchKernelGGL((bwd_gather<0, 32, 8>), dim3(gather_blocks(n_span, 8)), dim3(256), 0, s, b, n_span);
+            else hipLaunchKernelGGL((bwd_gather<0, 64, 16>), dim3(gather_blocks(n_span, 16)), dim3(256), 0, s, b, n_span);
         } else {
             TimedScope ts("bwd_gather", s);
             // slots needed: floor(3 d_max) + 4 covered pixels + 4 b padding
             const bool small = (int)(3.0f * a.d_max) + 4 + 4 * blur <= 32;
 #define SP_GATHER(BB)                                                                  \
     do {                                                                               \
-        if (small) hipLaunchKernelGGL((bwd_gather<BB, 32>), dim3(gb), dim3(256), 0, s, a, n_span); \
-        else hipLaunchKernelGGL((bwd_gather<BB, 64>), dim3(gb), dim3(256), 0, s, a, n_span);       \
+        if (small) hipLaunchKernelGGL((bwd_gather<BB, 32, 8>), dim3(gather_blocks(n_span, 8)), dim3(256), 0, s, a, n_span); \
+        else hipLaunchKernelGGL((bwd_gather<BB, 64, 16>), dim3(gather_blocks(n_span, 16)), dim3(256), 0, s, a, n_span);       \
     } while (0)
             switch (blur) {
             case 0: SP_GATHER(0); break;
@@ -1290,9 +1305,10 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         }
         {
             TimedScope ts("bwd_bounds", s);
-            // about 3072 particles per slice: 12 per thread
-            const int64_t per = (n_span + (int64_t)a.n_pairs * 3072 - 1) / ((int64_t)a.n_pairs * 3072);
-            const int ns = (int)std::min<int64_t>(std::max<int64_t>(per, 8), BWD_SLICES);
+            // about 768 particles per slice (3 per thread), at least 32 slices per
+            // pair: enough workgroups to keep the loads of every CU in flight
+            const int64_t per = (n_span + (int64_t)a.n_pairs * 768 - 1) / ((int64_t)a.n_pairs * 768);
+            const int ns = (int)std::min<int64_t>(std::max<int64_t>(per, 32), BWD_SLICES);
             hipLaunchKernelGGL(bwd_bounds, dim3((unsigned)a.n_pairs, ns), dim3(256), 0, s, a, ns);
             hipLaunchKernelGGL(bwd_scale, dim3(1), dim3(256), 0, s, a.scale, ap, en, a.sheet_part, a.bound_part,
                                a.n_pairs, ns, a.g_sheet, a.g_sheet_total);

@@ -381,9 +381,12 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
     form renders float images, so noise and codes are off).  The loss is the
     mean squared difference to a target pair rendered from the same particles
     moved by a perturbed flow (the grid plus Gaussian noise of 5% of its rms,
-    seed 1): every step renders J, forms dL/dJ = 2 (J - T) / M in one pass
-    (synthpix_mse_grad) and runs the backward.  Timed eagerly and as HIP graph
-    replays of each half (a training loop's form; ``graph``)."""
+    seed 1): every step renders J and runs the loss-fused backward
+    (synthpix_render_pair_backward_mse: dL/dJ = 2 (J - T) / M formed inside
+    the backward's per-pixel pass).  Timed eagerly and as HIP graph replays of
+    each half (a training loop's form; ``graph``); ``two_step`` is the same
+    backward with dL/dJ stored first (synthpix_mse_grad, then
+    synthpix_render_pair_backward)."""
     from workloads import get_workload
     wl = get_workload(name).with_(bits=0, noise_sigma=0.0)
     flows, n_max, batch, flow, sprm, aprm, rprm = _inputs(sp, torch, np, dev, wl)
@@ -393,6 +396,7 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
     img = torch.empty(batch.n_pixels, dtype=torch.float32, device=dev)
     wsf = sp.alloc_workspace(batch, rprm)
     wsb = sp.alloc_workspace(batch, rprm, backward=True)
+    wsm = sp.alloc_workspace(batch, rprm, backward="mse")
     g = torch.Generator(device=dev).manual_seed(1)
     flow_t = flow + 0.05 * flow.pow(2).mean().sqrt() * torch.randn(flow.shape, device=dev, generator=g)
     sp.advect(batch, flow_t, aprm, P["x"], P["y"], x2, y2, wsf)
@@ -404,12 +408,17 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
         sp.advect(batch, flow, aprm, P["x"], P["y"], x2, y2, wsf)
         sp.render_pair(batch, P["x"], P["y"], x2, y2, P["z"], P["d"], P["I0"], rprm, None, img, wsf)
 
-    def bwd():   # as the autograd wrapper calls it: the forward's frame-2 positions are reused
+    def bwd():   # the forward's frame-2 positions are reused, as the autograd wrapper does
+        sp.render_pair_backward_mse(batch, flow, P["x"], P["y"], P["z"], P["d"], P["I0"], rprm, img, target, scale,
+                                    workspace=wsm, x2=x2, y2=y2)
+
+    def bwd_two_step():
         sp.mse_grad(img, target, scale, out=gJ)                   # the loss's own gradient, one pass
         sp.render_pair_backward(batch, flow, P["x"], P["y"], P["z"], P["d"], P["I0"], rprm, gJ, None, wsb, x2=x2, y2=y2)
 
     fwd()
     bwd()
+    bwd_two_step()
     torch.cuda.synchronize()
 
     def timed(fn):
@@ -419,7 +428,7 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    eager = {"fwd": timed(fwd), "bwd": timed(bwd)}
+    eager = {"fwd": timed(fwd), "bwd": timed(bwd), "bwd_two_step": timed(bwd_two_step)}
     # a training loop's form: each half captured once as a HIP graph and replayed
     # (no per-launch host work; the same kernels and buffers)
     side = torch.cuda.Stream()
@@ -434,14 +443,17 @@ def gradient_cost(sp, torch, np, dev, name="grad_512", steps=10):
         with torch.cuda.graph(graphs[name]):
             fn()
     graph = {name: timed(graphs[name].replay) for name in ("fwd", "bwd")}
-    loss = float(sp.mse_grad(img, target, scale, out=gJ, loss=True)[1])
-    del graphs, wsb, wsf, gJ, img, target, flow_t
+    loss = float(sp.render_pair_backward_mse(batch, flow, P["x"], P["y"], P["z"], P["d"], P["I0"], rprm, img, target,
+                                             scale, loss=True, workspace=wsm, x2=x2, y2=y2)["loss"])
+    del graphs, wsb, wsf, wsm, gJ, img, target, flow_t
     torch.cuda.empty_cache()
     return {"loss": "mse_vs_perturbed_flow_target", "loss_value": float(f"{loss:.6e}"),
             "fwd_ms": round(1000 * eager["fwd"], 4), "bwd_ms": round(1000 * eager["bwd"], 4),
             "fwd_bwd_over_fwd": round((eager["fwd"] + eager["bwd"]) / eager["fwd"], 3),
             "graph": {"fwd_ms": round(1000 * graph["fwd"], 4), "bwd_ms": round(1000 * graph["bwd"], 4),
-                      "fwd_bwd_over_fwd": round((graph["fwd"] + graph["bwd"]) / graph["fwd"], 3)}}
+                      "fwd_bwd_over_fwd": round((graph["fwd"] + graph["bwd"]) / graph["fwd"], 3)},
+            "two_step": {"bwd_ms": round(1000 * eager["bwd_two_step"], 4),
+                         "fwd_bwd_over_fwd": round((eager["fwd"] + eager["bwd_two_step"]) / eager["fwd"], 3)}}
 
 
 def main():

@@ -188,9 +188,11 @@ synthpix_status synthpix_default_tiling(const synthpix_pair* pairs_host, int32_t
 synthpix_status synthpix_tiling_candidates(const synthpix_render_params* rp, synthpix_tiling* out,
                                            int32_t max_out, int32_t* n_out);
 
-/* Bytes of workspace needed by synthpix_render_pair (backward = 0) or
- * synthpix_render_pair_backward (backward = 1) for this batch and tiling.  The
- * forward size also covers synthpix_advect's optional workspace. */
+/* Bytes of workspace needed by synthpix_render_pair (backward = 0),
+ * synthpix_render_pair_backward (backward = 1) or
+ * synthpix_render_pair_backward_mse (backward = 2) for this batch and tiling;
+ * other values of backward are refused.  The forward size also covers
+ * synthpix_advect's optional workspace. */
 synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t n_pairs,
                                         const synthpix_render_params* rp,
                                         const synthpix_tiling* tiling, int32_t backward,
@@ -359,6 +361,38 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host,
                                               float* g_I0, float* g_sheet, float* g_sheet_total,
                                               float* g_flow, void* workspace, size_t ws_bytes,
                                               void* stream);
+
+/* The backward of synthpix_render_pair_backward for the image loss of
+ * synthpix_mse_grad, in one call: dL/dJ = scale (J - T) of the float images J
+ * (`images`, the forward's output) and a target T of the same layout is formed
+ * inside the backward's first per-pixel pass, where it is read (the same
+ * binary32 values synthpix_mse_grad would store), instead of being written to
+ * and read back from device memory; with a blur, that pass also applies the
+ * blur's adjoint once per pixel (Section 2, "Considerations on the aggregation":
+ * the blur is a fixed linear map of the images).  Arguments and outputs as in
+ * synthpix_render_pair_backward; the pairs' image ranges of images and target
+ * are read (16-byte alignment not needed).  scale: finite.  loss: optional
+ * (NULL: skipped) device double, 8-byte aligned, receiving the mean of
+ * (J - T)^2 over the pairs' pixels (2 H W per pair), summed in float64 in a
+ * fixed order (bit-reproducible; equal to synthpix_mse_grad's value up to the
+ * summation order).  workspace: >= synthpix_workspace_size(..., 2).  The
+ * gradients equal those of synthpix_mse_grad followed by
+ * synthpix_render_pair_backward up to float32 rounding (the same values with
+ * no blur or a blur of radius >= 2; a radius-1 blur, which the two-step form
+ * folds into its gather, is applied here once per pixel). */
+synthpix_status synthpix_render_pair_backward_mse(const synthpix_pair* pairs_host,
+                                                  const synthpix_pair* pairs_dev, int32_t n_pairs,
+                                                  const synthpix_tiling* tiling, const float* flow,
+                                                  const float* x1, const float* y1,
+                                                  const float* x2, const float* y2, const float* z,
+                                                  const float* d, const float* I0,
+                                                  const synthpix_render_params* rp,
+                                                  const float* images, const float* target, float scale,
+                                                  double* loss,
+                                                  float* g_x1, float* g_y1, float* g_z, float* g_d,
+                                                  float* g_I0, float* g_sheet, float* g_sheet_total,
+                                                  float* g_flow, void* workspace, size_t ws_bytes,
+                                                  void* stream);
 
 /* Image loss of a fitting loop through the generator (the acquisition and
  * parameter co-design the Abstract and Introduction name): the mean squared

@@ -127,6 +127,9 @@ SIGNATURES = {
     "synthpix_render_pair_backward": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P, _P,
                                       _P, ctypes.POINTER(RenderParams), _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P],
+    "synthpix_render_pair_backward_mse": [_PP, _P, ctypes.c_int32, ctypes.POINTER(Tiling), _P, _P, _P, _P, _P, _P,
+                                          _P, _P, ctypes.POINTER(RenderParams), _P, _P, ctypes.c_float, _P, _P, _P,
+                                          _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P],
     "synthpix_tiling_candidates": [ctypes.POINTER(RenderParams), ctypes.POINTER(Tiling), ctypes.c_int32,
                                    ctypes.POINTER(ctypes.c_int32)],
     "synthpix_plan_create": [_PP, ctypes.c_int32, ctypes.POINTER(SeedParams), ctypes.POINTER(AdvectParams),

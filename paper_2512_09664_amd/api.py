@@ -291,10 +291,13 @@ def _extras(dy, rho, z2):
 
 
 def workspace_size(batch: PairBatch, rp, tile=None, backward=False) -> int:
+    """Workspace bytes: the forward (backward False), ``render_pair_backward``
+    (True) or ``render_pair_backward_mse`` (``"mse"``)."""
     n = ctypes.c_size_t(0)
+    kind = 2 if backward == "mse" else 1 if backward else 0
     L.check(L.load().synthpix_workspace_size(batch.host_ptr, batch.n_pairs, ctypes.byref(rp),
                                              ctypes.byref(tile) if tile is not None else None,
-                                             1 if backward else 0, ctypes.byref(n)))
+                                             kind, ctypes.byref(n)))
     return n.value
 
 
@@ -401,6 +404,37 @@ def render_pair_backward(batch: PairBatch, flow, x1, y1, z, d, I0, rp, grad_imag
         _ptr(flow), _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(z), _ptr(d), _ptr(I0), ctypes.byref(rp),
         _ptr(grad_images), _ptr(g["x1"]), _ptr(g["y1"]), _ptr(g["z"]), _ptr(g["d"]), _ptr(g["I0"]),
         _ptr(g["sheet"]), _ptr(g["sheet_total"]), _ptr(g["flow"]), _ptr(workspace), workspace.numel(), _stream()))
+    return g
+
+
+def render_pair_backward_mse(batch: PairBatch, flow, x1, y1, z, d, I0, rp, images, target, scale=None,
+                             loss: bool = False, tile=None, workspace=None, x2=None, y2=None):
+    """Run ``synthpix_render_pair_backward_mse``: the gradients of the mean
+    squared difference of the float ``images`` to ``target`` (dL/dJ = scale
+    (J - T), scale 2 / (number of the pairs' pixels) by default, formed inside
+    the backward).  Returns the gradient dict of ``render_pair_backward``, with
+    ``loss`` (a float64 device scalar) when asked for."""
+    _need_cuda(flow, x1, y1, z, d, I0, images, target, x2, y2)
+    if images.dtype != torch.float32 or target.dtype != torch.float32:
+        raise ValueError("images and target must be float32")
+    dev = x1.device
+    g = {k: torch.empty_like(x1) for k in ("x1", "y1", "z", "d", "I0")}
+    g["sheet"] = torch.empty(batch.n_pairs, dtype=torch.float32, device=dev)
+    g["sheet_total"] = torch.empty((), dtype=torch.float32, device=dev)
+    g["flow"] = torch.empty_like(flow)
+    lv = torch.empty((), dtype=torch.float64, device=dev) if loss else None
+    if scale is None:
+        scale = 2.0 / max(sum(2 * H * W for (H, W) in batch.sizes), 1)
+    if workspace is None:
+        workspace = alloc_workspace(batch, rp, tile, backward="mse")
+    L.check(L.load().synthpix_render_pair_backward_mse(
+        batch.host_ptr, batch.dev_ptr, batch.n_pairs, ctypes.byref(tile) if tile is not None else None,
+        _ptr(flow), _ptr(x1), _ptr(y1), _ptr(x2), _ptr(y2), _ptr(z), _ptr(d), _ptr(I0), ctypes.byref(rp),
+        _ptr(images), _ptr(target), float(scale), _ptr(lv), _ptr(g["x1"]), _ptr(g["y1"]), _ptr(g["z"]),
+        _ptr(g["d"]), _ptr(g["I0"]), _ptr(g["sheet"]), _ptr(g["sheet_total"]), _ptr(g["flow"]), _ptr(workspace),
+        workspace.numel(), _stream()))
+    if loss:
+        g["loss"] = lv
     return g
 
 

@@ -226,7 +226,7 @@ int64_t flow_span(const synthpix_pair* ph, int32_t n_pairs)
 // Backward workspace: particle-major, no bins.
 struct BwdLayout {
     size_t status, scale, x2, y2, gx2, gy2, sheet, sheet_part, bound_part, wg_base, head, part, ovf, eblur, parts,
-        total;
+        loss_part, total;
 };
 
 // Workgroups of the flow adjoint: 256 particles of one pair each.
@@ -237,7 +237,7 @@ int64_t grid_workgroups(const synthpix_pair* ph, int32_t n_pairs)
     return n;
 }
 
-BwdLayout bwd_layout(int64_t n_span, int64_t n_wg, int32_t n_pairs, int64_t n_eblur, bool tile)
+BwdLayout bwd_layout(int64_t n_span, int64_t n_wg, int32_t n_pairs, int64_t n_eblur, bool tile, int64_t n_loss)
 {
     BwdLayout w{};
     size_t o = 0;
@@ -257,6 +257,7 @@ BwdLayout bwd_layout(int64_t n_span, int64_t n_wg, int32_t n_pairs, int64_t n_eb
     w.ovf = o; o = align256(o + sizeof(sp::GridRecord) * sp::GRID_OVF_CAP * (size_t)n_wg);
     w.eblur = o; o = align256(o + sizeof(float) * (size_t)n_eblur);
     w.parts = o; o = align256(o + (tile ? 2 * 16 * (size_t)n_span : 0));
+    w.loss_part = o; o = align256(o + sizeof(double) * (size_t)n_loss);
     w.total = o;
     return w;
 }
@@ -264,10 +265,10 @@ BwdLayout bwd_layout(int64_t n_span, int64_t n_wg, int32_t n_pairs, int64_t n_eb
 // Elements of the blurred-gradient images the backward keeps (B^T dL/dJ, the
 // images' layout): for any blur under the tile-major gather, else when the blur
 // is wide enough (radius >= 2) for the particle-major gather to pay for a
-// per-pixel pass; otherwise none.
-int64_t eblur_span(const synthpix_pair* ph, int32_t n_pairs, int blur_radius, bool tile)
+// per-pixel pass, and always for the loss-fused form (mse); otherwise none.
+int64_t eblur_span(const synthpix_pair* ph, int32_t n_pairs, int blur_radius, bool tile, bool mse)
 {
-    if (blur_radius < (tile ? 1 : 2)) return 0;
+    if (!mse && blur_radius < (tile ? 1 : 2)) return 0;
     int64_t span = 0;
     for (int32_t p = 0; p < n_pairs; ++p)
         span = std::max<int64_t>(span, ph[p].image_offset + 2 * (int64_t)ph[p].H * ph[p].W);
@@ -422,13 +423,19 @@ struct BwdPlan {
     size_t total;
 };
 
-BwdPlan bwd_plan(const synthpix_pair* ph, int32_t n_pairs, int64_t span, const synthpix_render_params& rp)
+BwdPlan bwd_plan(const synthpix_pair* ph, int32_t n_pairs, int64_t span, const synthpix_render_params& rp, bool mse)
 {
     BwdPlan b{};
     b.ob = order_bytes(ph, n_pairs);
     b.tile = sp::tile_gather_fits(rp.d_max, order_config(ph, n_pairs).log_tw, rp.blur_radius);
-    b.wl = bwd_layout(span, grid_workgroups(ph, n_pairs), n_pairs, eblur_span(ph, n_pairs, rp.blur_radius, b.tile),
-                      b.tile);
+    int max_h = 0, max_w = 0;
+    for (int32_t p = 0; p < n_pairs; ++p) {
+        max_h = std::max(max_h, (int)ph[p].H);
+        max_w = std::max(max_w, (int)ph[p].W);
+    }
+    const int64_t n_loss = mse ? sp::blur_grad_blocks(n_pairs, max_w, max_h, rp.blur_radius, true) : 0;
+    b.wl = bwd_layout(span, grid_workgroups(ph, n_pairs), n_pairs,
+                      eblur_span(ph, n_pairs, rp.blur_radius, b.tile, mse), b.tile, n_loss);
     b.total = b.wl.total + b.ob * (b.tile ? 2 : 1);
     return b;
 }
@@ -492,8 +499,9 @@ synthpix_status synthpix_workspace_size(const synthpix_pair* pairs_host, int32_t
     if ((st = check_tiling(t))) return st;
     const size_t ob = order_bytes(pairs_host, n_pairs);
     if (!ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
+    if (backward < 0 || backward > 2) return fail(SP_ERR_INVALID_ARG, "backward must be 0, 1 or 2");
     if (backward) {
-        *bytes_out = bwd_plan(pairs_host, n_pairs, span, *rp).total;
+        *bytes_out = bwd_plan(pairs_host, n_pairs, span, *rp, backward == 2).total;
         return SP_OK;
     }
     const sp::RenderConfig cfg = make_config(*rp, t);
@@ -765,14 +773,21 @@ synthpix_status synthpix_mse_grad(const float* J, const float* T, int64_t n, flo
     return SP_OK;
 }
 
-synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
-                                              int32_t n_pairs, const synthpix_tiling* tiling, const float* flow,
-                                              const float* x1, const float* y1, const float* x2,
-                                              const float* y2, const float* z, const float* d,
-                                              const float* I0, const synthpix_render_params* rp,
-                                              const float* grad_images, float* g_x1, float* g_y1, float* g_z,
-                                              float* g_d, float* g_I0, float* g_sheet, float* g_sheet_total,
-                                              float* g_flow, void* workspace, size_t ws_bytes, void* stream)
+}  // extern "C"
+
+namespace {
+
+// The body of both backward entry points: dL/dJ handed in (grad_images), or,
+// with mse, formed from the images J and the target T as scale (J - T) inside
+// the backward's per-pixel pass (loss: optional device double, the mean of
+// (J - T)^2 over the pairs' pixels).
+synthpix_status backward_common(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev, int32_t n_pairs,
+                                const synthpix_tiling* tiling, const float* flow, const float* x1, const float* y1,
+                                const float* x2, const float* y2, const float* z, const float* d, const float* I0,
+                                const synthpix_render_params* rp, bool mse, const float* grad_images,
+                                const float* J, const float* T, float scale, double* loss, float* g_x1,
+                                float* g_y1, float* g_z, float* g_d, float* g_I0, float* g_sheet,
+                                float* g_sheet_total, float* g_flow, void* workspace, size_t ws_bytes, void* stream)
 {
     int64_t span;
     synthpix_status st = check_pairs(pairs_host, pairs_dev, n_pairs, &span);
@@ -786,8 +801,10 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     if ((st = check_advect_params(&rp->advect))) return st;
     if (!flow || !aligned(flow, 8)) return fail(SP_ERR_INVALID_ARG, "flow must be a non-NULL 8-byte aligned pointer");
     if (!dev_ptr_ok(x1) || !dev_ptr_ok(y1) || !dev_ptr_ok(z) || !dev_ptr_ok(d) || !dev_ptr_ok(I0) ||
-        !dev_ptr_ok(grad_images))
+        (mse ? (!dev_ptr_ok(J) || !dev_ptr_ok(T)) : !dev_ptr_ok(grad_images)))
         return fail(SP_ERR_INVALID_ARG, "inputs must be non-NULL, 4-byte aligned device pointers");
+    if (mse && !std::isfinite(scale)) return fail(SP_ERR_INVALID_ARG, "scale must be finite");
+    if (loss && !aligned(loss, 8)) return fail(SP_ERR_INVALID_ARG, "loss must be NULL or an 8-byte aligned pointer");
     if ((x2 == nullptr) != (y2 == nullptr) || (x2 && (!dev_ptr_ok(x2) || !dev_ptr_ok(y2))))
         return fail(SP_ERR_INVALID_ARG, "x2 and y2 must both be NULL or both aligned device pointers");
     if (!dev_ptr_ok(g_x1) || !dev_ptr_ok(g_y1) || !dev_ptr_ok(g_z) || !dev_ptr_ok(g_d) || !dev_ptr_ok(g_I0) ||
@@ -796,7 +813,7 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     if (g_sheet_total && !dev_ptr_ok(g_sheet_total))
         return fail(SP_ERR_INVALID_ARG, "g_sheet_total must be NULL or a 4-byte aligned device pointer");
     const int64_t n_flow = flow_span(pairs_host, n_pairs);
-    const BwdPlan bp = bwd_plan(pairs_host, n_pairs, span, *rp);
+    const BwdPlan bp = bwd_plan(pairs_host, n_pairs, span, *rp, mse);
     const BwdLayout& wl = bp.wl;
     if (!bp.ob) return fail(SP_ERR_UNSUPPORTED, "batch too large for the advection order");
     if (!workspace || !aligned(workspace, 256)) return fail(SP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -836,7 +853,14 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     a.z = z;
     a.d = d;
     a.I0 = I0;
-    a.grad = grad_images;
+    a.grad = mse ? nullptr : grad_images;
+    a.mse = mse;
+    a.J = J;
+    a.T = T;
+    a.mse_scale = scale;
+    a.loss = mse ? loss : nullptr;
+    a.loss_part = a.loss ? reinterpret_cast<double*>(ws + wl.loss_part) : nullptr;
+    for (int32_t p = 0; p < n_pairs; ++p) a.loss_n += 2 * (int64_t)pairs_host[p].H * pairs_host[p].W;
     a.eblur = wl.parts > wl.eblur ? reinterpret_cast<float*>(ws + wl.eblur) : nullptr;
     a.g_x1 = g_x1;
     a.g_y1 = g_y1;
@@ -875,6 +899,39 @@ synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, c
     return SP_OK;
 }
 
+
+}  // namespace
+
+extern "C" {
+
+synthpix_status synthpix_render_pair_backward(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                              int32_t n_pairs, const synthpix_tiling* tiling, const float* flow,
+                                              const float* x1, const float* y1, const float* x2,
+                                              const float* y2, const float* z, const float* d,
+                                              const float* I0, const synthpix_render_params* rp,
+                                              const float* grad_images, float* g_x1, float* g_y1, float* g_z,
+                                              float* g_d, float* g_I0, float* g_sheet, float* g_sheet_total,
+                                              float* g_flow, void* workspace, size_t ws_bytes, void* stream)
+{
+    return backward_common(pairs_host, pairs_dev, n_pairs, tiling, flow, x1, y1, x2, y2, z, d, I0, rp, false,
+                           grad_images, nullptr, nullptr, 0.0f, nullptr, g_x1, g_y1, g_z, g_d, g_I0, g_sheet,
+                           g_sheet_total, g_flow, workspace, ws_bytes, stream);
+}
+
+synthpix_status synthpix_render_pair_backward_mse(const synthpix_pair* pairs_host, const synthpix_pair* pairs_dev,
+                                                  int32_t n_pairs, const synthpix_tiling* tiling, const float* flow,
+                                                  const float* x1, const float* y1, const float* x2,
+                                                  const float* y2, const float* z, const float* d,
+                                                  const float* I0, const synthpix_render_params* rp,
+                                                  const float* images, const float* target, float scale,
+                                                  double* loss, float* g_x1, float* g_y1, float* g_z, float* g_d,
+                                                  float* g_I0, float* g_sheet, float* g_sheet_total, float* g_flow,
+                                                  void* workspace, size_t ws_bytes, void* stream)
+{
+    return backward_common(pairs_host, pairs_dev, n_pairs, tiling, flow, x1, y1, x2, y2, z, d, I0, rp, true,
+                           nullptr, images, target, scale, loss, g_x1, g_y1, g_z, g_d, g_I0, g_sheet, g_sheet_total,
+                           g_flow, workspace, ws_bytes, stream);
+}
 
 }  // extern "C"
 

@@ -477,21 +477,65 @@ __global__ void __launch_bounds__(256) bwd_particles(BwdArgs a, int64_t n_span)
     }
 }
 
-// e = B^T dL/dJ for a wide blur, once per pixel: the zero-padded blur's
-// adjoint sums w_k dL/dJ(q + k) over the taps that land inside the image (the
-// same blur, its weights being symmetric).  A workgroup owns a strip of 32
-// output rows by 256 - 2b output columns of one frame: each thread takes one
-// input column (b apron columns on either side), issues its 32 + 2b loads
-// together and blurs them vertically in registers; the rows then pass through
-// LDS for the horizontal taps.  Rows of 256 floats keep the reads and writes
-// in whole 1 KB segments.  Workgroups are numbered (pair, frame, strip row,
-// strip column) over the batch's largest pair, XCD-contiguously.
-template <int B>
+// One input column x of a strip of the per-pixel pass: its SH + 2b rows from
+// Y0 - b (zeros outside the image) blurred vertically into vb[.][k].  MSE: the
+// values are scale (J - T); returns the float64 sum of (J - T)^2 over the
+// strip's own rows (Y0 .. Y0 + SH - 1, inside the image), 0 otherwise.
+template <int B, bool MSE, int SH, int VW>
+__device__ __forceinline__ double blur_column(const BwdArgs& a, int64_t base, int W, int H, int x, int Y0, int k,
+                                              float (*vb)[VW])
+{
+    const bool xin = x >= 0 && x < W;
+    float g[SH + 2 * B];
+    double sq = 0.0;
+#pragma unroll
+    for (int r = 0; r < SH + 2 * B; ++r) {
+        const int y = Y0 - B + r;
+        const bool in = xin && y >= 0 && y < H;
+        if constexpr (MSE) {
+            const int64_t i = base + (int64_t)(in ? y : 0) * W + (in ? x : 0);
+            const float j = in ? a.J[i] : 0.0f, tv = in ? a.T[i] : 0.0f;
+            g[r] = a.mse_scale * (j - tv);
+            if (in && r >= B && r < SH + B) {
+                const double e = (double)j - (double)tv;
+                sq = __builtin_fma(e, e, sq);
+            }
+        } else {
+            g[r] = in ? a.grad[base + (int64_t)y * W + x] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < SH; ++r) {
+        float v = 0.0f;
+#pragma unroll
+        for (int q = 0; q <= 2 * B; ++q) v = __builtin_fmaf(a.blur_w[q], g[r + q], v);
+        vb[r][k] = v;
+    }
+    return sq;
+}
+
+// e = B^T dL/dJ, once per pixel: the zero-padded blur's adjoint sums
+// w_k dL/dJ(q + k) over the taps that land inside the image (the same blur,
+// its weights being symmetric).  A workgroup owns a strip of SH output rows
+// by 256 output columns of one frame: each thread takes one column (the first
+// 2b threads also one of the b apron columns on either side), issues its
+// SH + 2b loads together and blurs them vertically in registers; the rows then
+// pass through LDS for the horizontal taps.  Rows of 256 floats keep the reads
+// and writes in whole 1 KB segments, and images 256 k pixels wide split into
+// whole strips.  Workgroups are numbered (pair, frame, strip row, strip
+// column) over the batch's largest pair, XCD-contiguously.
+// MSE: dL/dJ is the mean-squared-difference loss's gradient scale (J - T),
+// formed from the images and the target as they are read (the same binary32
+// products synthpix_mse_grad stores), and with loss_part each workgroup also
+// writes the float64 sum of (J - T)^2 over the pixels of its strip (every
+// pixel lies in exactly one strip); b = 0 is then a plain pass.
+template <int B, bool MSE>
 __global__ void __launch_bounds__(256)
 bwd_blur_grad(BwdArgs a, int nsx, int nsy)
 {
-    constexpr int SH = 32, SO = 256 - 2 * B;
-    __shared__ float vb[SH][256];
+    constexpr int SH = blur_strip_rows(MSE), VW = 256 + 2 * B;
+    __shared__ float vb[SH][VW];
+    __shared__ double red[MSE ? 256 : 1];
     const int64_t bid = xcd_contiguous(blockIdx.x, gridDim.x);
     const int64_t per_pair = (int64_t)2 * nsx * nsy;
     const int p = (int)(bid / per_pair);
@@ -500,33 +544,41 @@ bwd_blur_grad(BwdArgs a, int nsx, int nsy)
     rem -= f * nsx * nsy;
     const int sy = rem / nsx, sx = rem - sy * nsx;
     const int H = a.pairs[p].H, W = a.pairs[p].W;
-    const int X0 = sx * SO, Y0 = sy * SH;
-    if (X0 >= W || Y0 >= H) return;              // the whole workgroup, before its barrier
+    const int X0 = sx * 256, Y0 = sy * SH;
+    if (X0 >= W || Y0 >= H) {                    // the whole workgroup, before its barrier
+        if (MSE && a.loss_part && threadIdx.x == 0) a.loss_part[bid] = 0.0;
+        return;
+    }
     const int64_t base = a.pairs[p].image_offset + (int64_t)f * H * W;
     const int t = (int)threadIdx.x;
-    const int x = X0 - B + t;
-    const bool xin = x >= 0 && x < W;
-    float g[SH + 2 * B];
-#pragma unroll
-    for (int r = 0; r < SH + 2 * B; ++r) {
-        const int y = Y0 - B + r;
-        g[r] = (xin && y >= 0 && y < H) ? a.grad[base + (int64_t)y * W + x] : 0.0f;
+    // vb column k holds input column X0 - b + k
+    double sq = 0.0;
+    const int nc = t < 2 * B ? 2 : 1;
+#pragma unroll 1
+    for (int c = 0; c < nc; ++c) {             // own column, then an apron column
+        const int xc = c == 0 ? X0 + t : t < B ? X0 - B + t : X0 + 256 + (t - B);
+        const int k = c == 0 ? B + t : t < B ? t : 256 + t;
+        const double s2 = blur_column<B, MSE, SH, VW>(a, base, W, H, xc, Y0, k, vb);
+        if (c == 0) sq = s2;
     }
-#pragma unroll
-    for (int r = 0; r < SH; ++r) {
-        float v = 0.0f;
-#pragma unroll
-        for (int q = 0; q <= 2 * B; ++q) v = __builtin_fmaf(a.blur_w[q], g[r + q], v);
-        vb[r][t] = v;
+    if (MSE && a.loss_part) {
+        red[t] = sq;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w) red[t] += red[t + w];
+            __syncthreads();
+        }
+        if (t == 0) a.loss_part[bid] = red[0];
     }
     __syncthreads();
-    if (t < B || t >= 256 - B || !xin) return;
+    const int x = X0 + t;
+    if (x >= W) return;
     const int nr = H - Y0 < SH ? H - Y0 : SH;
 #pragma unroll 4
     for (int r = 0; r < nr; ++r) {
         float e = 0.0f;
 #pragma unroll
-        for (int q = 0; q <= 2 * B; ++q) e = __builtin_fmaf(a.blur_w[q], vb[r][t - B + q], e);
+        for (int q = 0; q <= 2 * B; ++q) e = __builtin_fmaf(a.blur_w[q], vb[r][t + q], e);
         a.eblur[base + (int64_t)(Y0 + r) * W + x] = e;
     }
 }
@@ -1195,11 +1247,12 @@ mse_grad_kernel(const float* __restrict__ J, const float* __restrict__ T, int64_
 }
 
 // loss = (sum of the MSE_BLOCKS partials, as a fixed tree) / n
-__global__ void __launch_bounds__(256) mse_finish(const double* __restrict__ part, int64_t n, double* __restrict__ loss)
+__global__ void __launch_bounds__(256)
+mse_finish(const double* __restrict__ part, int64_t n_part, int64_t n, double* __restrict__ loss)
 {
     __shared__ double red[256];
     double v = 0.0;
-    for (int k = threadIdx.x; k < MSE_BLOCKS; k += 256) v += part[k];
+    for (int64_t k = threadIdx.x; k < n_part; k += 256) v += part[k];
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
@@ -1216,8 +1269,17 @@ hipError_t launch_mse_grad(const float* J, const float* T, int64_t n, float scal
     const int64_t want = (n / 4 + 255) / 256;
     const unsigned grid = loss ? (unsigned)MSE_BLOCKS : (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, MSE_BLOCKS));
     hipLaunchKernelGGL(mse_grad_kernel, dim3(grid), dim3(256), 0, s, J, T, n, scale, grad, loss ? part : nullptr);
-    if (loss) hipLaunchKernelGGL(mse_finish, dim3(1), dim3(256), 0, s, part, n, loss);
+    if (loss) hipLaunchKernelGGL(mse_finish, dim3(1), dim3(256), 0, s, part, (int64_t)MSE_BLOCKS, n, loss);
     return hipGetLastError();
+}
+
+// Workgroups of the per-pixel blur adjoint: (pair, frame, strip row, strip
+// column) over the batch's largest pair.
+int64_t blur_grad_blocks(int n_pairs, int max_w, int max_h, int blur, bool mse)
+{
+    (void)blur;
+    const int sh = blur_strip_rows(mse);
+    return (int64_t)n_pairs * 2 * ((max_w + 255) / 256) * ((max_h + sh - 1) / sh);
 }
 
 // Workgroups of the particle-major gather: 256 / G particles each.
@@ -1250,30 +1312,40 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
         hipLaunchKernelGGL(bwd_init, dim3((unsigned)blocks), dim3(256), 0, s, a.g_flow, n_flow, a.status, a.scale,
                            a.g_sheet, a.n_pairs, a.g_sheet_total, a.pairs, a.grid.wg_base);
     }
+    if (a.mse && !a.eblur) return hipErrorInvalidValue;
+    const bool tile = a.order2.entries && a.parts;
+    // the blur's adjoint once per pixel (the gather then runs on the unblurred
+    // footprints of B^T dL/dJ): for wide blurs and the tile gather, and always
+    // for the loss-fused form, whose pass also forms dL/dJ (and the loss, which
+    // the images define even when no pair holds a particle)
+    const bool per_pixel = a.eblur && (a.mse || (blur >= 1 && (tile || blur >= 2)));
+    if (per_pixel && (n_span > 0 || (a.mse && a.loss))) {
+        TimedScope ts("bwd_blur", s);
+        const int64_t nb = blur_grad_blocks(a.n_pairs, a.max_w, a.max_h, blur, a.mse);
+        if (nb < 1 || nb > 0xFFFFFFFFll) return hipErrorInvalidValue;
+        const int sh = blur_strip_rows(a.mse);
+        const int nsx = (a.max_w + 255) / 256, nsy = (a.max_h + sh - 1) / sh;
+#define SP_BLUR(BB)                                                                                             \
+    case BB:                                                                                                    \
+        if (a.mse) hipLaunchKernelGGL((bwd_blur_grad<BB, true>), dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy); \
+        else hipLaunchKernelGGL((bwd_blur_grad<BB, false>), dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy);     \
+        break;
+        switch (blur) {
+        SP_BLUR(0) SP_BLUR(1) SP_BLUR(2) SP_BLUR(3)
+        default: return hipErrorInvalidValue;
+        }
+#undef SP_BLUR
+        if (a.mse && a.loss)
+            hipLaunchKernelGGL(mse_finish, dim3(1), dim3(256), 0, s, a.loss_part, nb, a.loss_n, a.loss);
+    }
     if (n_span > 0) {
         if (a.recompute_x2) {
             const hipError_t e = launch_advect(a.pairs, a.n_pairs, n_span, a.flow, ap, a.x1, a.y1, a.x2w, a.y2w, s,
                                                a.order);
             if (e != hipSuccess) return e;
         }
-        const bool tile = a.order2.entries && a.parts;
-        if (a.eblur && blur >= 1 && (tile || blur >= 2)) {
-            // the blur's adjoint once per pixel: the gather then runs on the
-            // unblurred footprints of B^T dL/dJ
-            TimedScope ts("bwd_blur", s);
-            const int so = 256 - 2 * blur;
-            const int nsx = (a.max_w + so - 1) / so, nsy = (a.max_h + 31) / 32;
-            const int64_t nb = (int64_t)a.n_pairs * 2 * nsx * nsy;
-            if (nb > 0xFFFFFFFFll) return hipErrorInvalidValue;
-            switch (blur) {
-            case 1: hipLaunchKernelGGL(bwd_blur_grad<1>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy); break;
-            case 2: hipLaunchKernelGGL(bwd_blur_grad<2>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy); break;
-            case 3: hipLaunchKernelGGL(bwd_blur_grad<3>, dim3((unsigned)nb), dim3(256), 0, s, a, nsx, nsy); break;
-            default: return hipErrorInvalidValue;
-            }
-        }
         BwdArgs b = a;
-        if (a.eblur && blur >= 1 && (tile || blur >= 2)) b.grad = a.eblur;
+        if (per_pixel) b.grad = a.eblur;
         if (tile) {
             TimedScope ts("bwd_gather", s);
             const int hb = tile_halo(a.d_max);
@@ -1283,7 +1355,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             hipLaunchKernelGGL(bwd_tile_gather, dim3((unsigned)items), dim3(256), sizeof(float) * (size_t)rw * rw, s,
                                b, n_span, a.order.log_block, hb);
             hipLaunchKernelGGL(bwd_particles, dim3((unsigned)((n_span + 255) / 256)), dim3(256), 0, s, b, n_span);
-        } else if (blur >= 2) {
+        } else if (per_pixel) {
             TimedScope ts("bwd_gather", s);
             if ((int)(3.0f * a.d_max) + 4 <= 32) hipLaunchKernelGGL((bwd_gather<0, 32, 8>), dim3(gather_blocks(n_span, 8)), dim3(256), 0, s, b, n_span);
             else hipLaunchKernelGGL((bwd_gather<0, 64, 16>), dim3(gather_blocks(n_span, 16)), dim3(256), 0, s, b, n_span);

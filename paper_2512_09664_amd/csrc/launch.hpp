@@ -271,8 +271,20 @@ struct BwdArgs {
     const float* z;
     const float* d;
     const float* I0;
-    const float* grad;           // dL/dJ, the images' layout
-    float* eblur;                // B^T dL/dJ (workspace, the images' layout) for blur radius >= 2
+    const float* grad;           // dL/dJ, the images' layout (unless mse)
+    // mse: dL/dJ = mse_scale (J - T) is formed from the float images J and the
+    // target T (the images' layout) by the per-pixel pass, which also writes
+    // float64 partial sums of (J - T)^2 to loss_part when loss is non-null;
+    // *loss = their sum / loss_n
+    bool mse;
+    const float* J;
+    const float* T;
+    float mse_scale;
+    double* loss_part;
+    double* loss;
+    int64_t loss_n;
+    float* eblur;                // B^T dL/dJ (workspace, the images' layout): blur radius >= 2, the
+                                 // tile gather, or the mse form
     float* g_x1;
     float* g_y1;
     float* g_z;
@@ -297,6 +309,12 @@ struct BwdArgs {
 
 hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, const synthpix_advect_params& ap,
                            int blur, int en, hipStream_t s);
+
+// Rows per strip of the backward's per-pixel pass, and its workgroups over a
+// batch whose largest pair is max_h x max_w (the loss partials of the
+// loss-fused form, one each).
+constexpr int blur_strip_rows(bool mse) { return mse ? 16 : 24; }
+int64_t blur_grad_blocks(int n_pairs, int max_w, int max_h, int blur, bool mse);
 
 // Image loss gradient grad = scale (J - T) and, with loss, the mean of (J - T)^2
 // (float64 partials of MSE_BLOCKS workgroups in part, summed in a fixed order).

@@ -268,6 +268,39 @@ def test_backward_validation(L):
                                              None) == L.SP_ERR_INVALID_ARG
 
 
+def test_backward_mse_validation(L):
+    """The loss-fused backward checks its arguments and its own (larger)
+    workspace size before enqueueing anything."""
+    lib = L.load()
+    pairs = _pairs(L, [(64, 64, 16, 16, 100)])
+    fake = ctypes.c_void_p(0x1000)
+    rp = _rp(L, bits=0)
+    rp.advect.substeps = 2
+    n1, n2 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(rp), None, 1, ctypes.byref(n1)) == 0
+    assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(rp), None, 2, ctypes.byref(n2)) == 0
+    # the per-pixel pass's images (2 x 64 x 64 floats) and its loss partials
+    assert n2.value >= n1.value + 4 * 2 * 64 * 64 and n2.value % 256 == 0
+    for bad in (-1, 3):
+        assert lib.synthpix_workspace_size(pairs, 1, ctypes.byref(rp), None, bad,
+                                           ctypes.byref(n1)) == L.SP_ERR_INVALID_ARG
+    args = [pairs, fake, 1, None, fake, fake, fake, None, None] + [fake] * 3
+
+    def call(images=fake, target=fake, scale=1.0, loss=None, nbytes=n2.value, rp_=rp):
+        return lib.synthpix_render_pair_backward_mse(*args, ctypes.byref(rp_), images, target, scale, loss, fake,
+                                                     fake, fake, fake, fake, fake, None, fake,
+                                                     ctypes.c_void_p(0x100000), nbytes, None)
+
+    assert call(images=None) == L.SP_ERR_INVALID_ARG
+    assert call(target=ctypes.c_void_p(0x1002)) == L.SP_ERR_INVALID_ARG
+    assert call(scale=float("nan")) == L.SP_ERR_INVALID_ARG
+    assert call(loss=ctypes.c_void_p(0x2004)) == L.SP_ERR_INVALID_ARG
+    assert call(nbytes=n2.value - 1) == L.SP_ERR_WORKSPACE
+    coded = _rp(L, bits=12)
+    coded.advect.substeps = 2
+    assert call(rp_=coded) == L.SP_ERR_UNSUPPORTED
+
+
 def test_mse_grad_validation(L):
     """The loss-gradient call checks its arguments before enqueueing anything."""
     lib = L.load()

@@ -645,3 +645,71 @@ def test_forward_backward_replay_from_a_graph():
             for key in ref:
                 assert torch.equal(g_graph[key], ref[key]), (blur, k, key)
         del graph
+
+
+@pytest.mark.parametrize("integ,n_sub,blur,sheet,d_range,d_max", CASES)
+def test_backward_mse_matches_oracle_and_two_step(integ, n_sub, blur, sheet, d_range, d_max):
+    """The loss-fused backward (``synthpix_render_pair_backward_mse``) on seeded
+    float images J and a target T: its gradients equal the float64 oracle
+    gradient for dL/dJ = scale (J - T) (that product formed in binary32 on the
+    host, as the loss defines it); they equal ``mse_grad`` followed by
+    ``render_pair_backward`` bit for bit where both run the same per-pixel pass
+    (no blur, radius >= 2) and to float32 rounding where the two-step form folds
+    a radius-1 blur into its factor tables; the loss is the float64 mean of
+    (J - T)^2 over the pairs' pixels and repeats bit for bit."""
+    sizes = [(16, 16), (24, 20), (40, 48), (33, 17)]
+    grids = [(6, 6), (8, 7), (10, 12), (9, 5)]
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, 14, 3 + n_sub + 10 * blur, d_range=d_range)
+    rp = sp.render_params(sheet, d_max, blur, 0.8, 0.0, 0, 0, 1.0, n_sub, integ)
+    rng = np.random.default_rng(31 + blur)
+    J = rng.standard_normal(batch.n_pixels).astype(np.float32)
+    T = rng.standard_normal(batch.n_pixels).astype(np.float32)
+    Jd, Td = gu.to_dev(J), gu.to_dev(T)
+    M = sum(2 * H * W for (H, W) in sizes)
+    scale = np.float32(2.0 / M)
+    gJ = scale * (J - T)
+    ws = sp.alloc_workspace(batch, rp, backward="mse")
+    args = (batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp)
+    g = sp.render_pair_backward_mse(*args, Jd, Td, float(scale), loss=True, workspace=ws)
+    g_again = sp.render_pair_backward_mse(*args, Jd, Td, float(scale), loss=True)
+    gJ_dev, _ = sp.mse_grad(Jd, Td, float(scale))
+    two = sp.render_pair_backward(*args, gJ_dev)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    ref_loss = float(np.mean((J.astype(np.float64) - T) ** 2))
+    assert abs(float(g["loss"]) - ref_loss) <= 1e-12 * ref_loss
+    for k in g:
+        assert torch.equal(g[k], g_again[k]), k
+    for k in two:
+        if blur == 1:
+            _close(gu.to_np(g[k]), gu.to_np(two[k]).astype(np.float64), f"two-step {k}", tol=1e-5)
+        else:
+            assert torch.equal(g[k], two[k]), k
+    G = {k: gu.to_np(v) for k, v in g.items()}
+    fo = 0
+    for p, (H, W) in enumerate(sizes):
+        ref = _oracle_pair(P, p, flows, H, W, gJ, batch.host[p].image_offset, rp, blur)
+        sl = slice(batch.host[p].particle_offset, batch.host[p].particle_offset + 14)
+        for key in ("x1", "y1", "z", "d", "I0"):
+            _close(G[key][sl], ref[key], f"pair {p} {key}")
+        n_f = flows[p].size
+        _close(G["flow"][fo:fo + n_f].reshape(flows[p].shape), ref["flow"], f"pair {p} flow")
+        fo += n_f
+
+
+def test_backward_mse_loss_without_particles():
+    """With no particle in any pair the loss-fused backward still reports the
+    loss of the images (and zero gradients)."""
+    sizes = [(20, 300), (37, 5)]
+    batch = gu.batch_for(sizes, [(4, 4), (4, 4)], [0, 0])
+    rp = sp.render_params(0.5, 5.0, 2, 0.8, 0.0, 0, 0, 1.0, 2, "rk4")
+    rng = np.random.default_rng(5)
+    J = rng.standard_normal(batch.n_pixels).astype(np.float32)
+    T = rng.standard_normal(batch.n_pixels).astype(np.float32)
+    e = torch.zeros(1, dtype=torch.float32, device="cuda")
+    flow = torch.zeros(2 * 2 * 16, dtype=torch.float32, device="cuda")
+    g = sp.render_pair_backward_mse(batch, flow, e, e, e, e, e, rp, gu.to_dev(J), gu.to_dev(T), 1.0, loss=True)
+    torch.cuda.synchronize()
+    ref = float(np.mean((J.astype(np.float64) - T) ** 2))
+    assert abs(float(g["loss"]) - ref) <= 1e-12 * ref
+    assert float(g["flow"].abs().max()) == 0.0 and float(g["sheet"].abs().max()) == 0.0

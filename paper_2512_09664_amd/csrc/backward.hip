@@ -1182,14 +1182,35 @@ __global__ void bwd_init(float* __restrict__ g_flow, int64_t n, uint32_t* __rest
         status[t] = 0u;
         sc[t] = 0u;
     }
-    if (t == 0) {
-        // workgroups of the flow adjoint: each pair's particles in chunks of 256
-        int64_t acc = 0;
-        for (int p = 0; p < n_pairs; ++p) {
-            wg_base[p] = acc;
-            acc += (pairs[p].n_max + 255) / 256;
+    if (blockIdx.x == 0) {
+        // workgroups of the flow adjoint, each pair's particles in chunks of 256:
+        // an exclusive prefix over the pairs, 256 at a time (wave scans, then
+        // the four wave totals)
+        __shared__ int64_t s_tot[4];
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        int64_t carry = 0;
+        for (int b = 0; b < n_pairs; b += 256) {
+            const int p = b + (int)threadIdx.x;
+            const int64_t v = p < n_pairs ? (pairs[p].n_max + 255) / 256 : 0;
+            int64_t inc = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int64_t u = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += u;
+            }
+            if (lane == 63) s_tot[wid] = inc;
+            __syncthreads();
+            int64_t before = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (w < wid) before += s_tot[w];
+                total += s_tot[w];
+            }
+            if (p < n_pairs) wg_base[p] = carry + before + inc - v;
+            carry += total;
+            __syncthreads();
         }
-        wg_base[n_pairs] = acc;
+        if (threadIdx.x == 0) wg_base[n_pairs] = carry;
     }
     // sheet gradients of a batch without particles (otherwise overwritten later)
     if (t < n_pairs) g_sheet[t] = 0.0f;

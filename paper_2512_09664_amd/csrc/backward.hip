@@ -636,16 +636,16 @@ __device__ __forceinline__ Sample sample_jac(const FlowView& fv, float px, float
 
 // Per-particle accumulation of node contributions, merged while consecutive
 // samples stay in one grid cell, flushed as 64-bit fixed-point atomic adds
-// (integer sums: the result does not depend on their order).  The two runs
-// before the current one are held back, so that most lanes flush together at
-// the end of the sweep instead of wherever their own run boundaries fall.
+// (integer sums: the result does not depend on their order).  A run is flushed
+// as soon as the sample leaves its cell (holding the two runs before it back,
+// so that lanes flush together, took 40 more registers and a wave per SIMD).
 struct CellRun {
     int i0 = -1, j0 = 0;
     float acc[8];
 };
 
 struct NodeRun {
-    CellRun cur, prev1, prev2;
+    CellRun cur;
     int Gw;
     double scale;         // 2^e; 0 when the flow gradient is not accumulated
     // the workgroup's LDS window of node sums (rows wi0 .., cols wj0 .., wh x ww
@@ -681,20 +681,13 @@ struct NodeRun {
         }
     }
 
-    __device__ void finish()
-    {
-        flush(cur);
-        flush(prev1);
-        flush(prev2);
-    }
+    __device__ void finish() { flush(cur); }
 
     __device__ void add(const Sample& s, float ku, float kv)
     {
         if (scale == 0.0) return;
         if (s.i0 != cur.i0 || s.j0 != cur.j0) {
-            if (prev2.i0 >= 0) flush(prev2);
-            prev2 = prev1;
-            prev1 = cur;
+            flush(cur);
             cur.i0 = s.i0;
             cur.j0 = s.j0;
 #pragma unroll
@@ -755,7 +748,7 @@ enum { SC_NONE = 0, SC_VALID = 1, SC_NONFINITE = 2 };
 // is recomputed into SK >= L slots during the sweep.
 
 template <int CK, int SK>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CK <= 8 ? 4 : 3)))
 bwd_advect(BwdArgs a, synthpix_advect_params ap)
 {
     __shared__ unsigned long long win[2 * WIN_NODES];

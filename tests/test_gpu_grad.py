@@ -713,3 +713,49 @@ def test_backward_mse_loss_without_particles():
     ref = float(np.mean((J.astype(np.float64) - T) ** 2))
     assert abs(float(g["loss"]) - ref) <= 1e-12 * ref
     assert float(g["flow"].abs().max()) == 0.0 and float(g["sheet"].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("name", ["grad_512", "dense_2048"])
+def test_backward_mse_full_size(ra, name):
+    """The loss-fused backward at the bench's full sizes (grad_512: 3x3 blur,
+    particle-major gather; dense_2048: 5x5 blur, tile-major gather) against the
+    two-step form whose gradients the tests above check against the oracle:
+    the same values with the 5x5 blur (both run the same per-pixel pass), to
+    1e-5 of each output's largest magnitude with the 3x3 blur (folded into the
+    two-step gather's tables); the loss is the float64 mean of (J - T)^2 to
+    1e-12, and the device status word stays clear."""
+    wl = get_workload(name)
+    flows = make_flows(wl.flow, wl.seed, wl.sizes, wl.grid_div, wl.max_disp, wl.dt, wl.uniform_uv)
+    n_max = [sp.particle_count(H, W, wl.ppp[1]) for (H, W) in wl.sizes]
+    batch = gu.batch_for(wl.sizes, [f.shape[:2] for f in flows], n_max)
+    P = {k: [] for k in ("x", "y", "z", "d", "I0")}
+    for p, (H, W) in enumerate(wl.sizes):
+        q = ra.seed_pair(H, W, n_max[p], wl.ppp, p, wl.seed, wl.d_dist, wl.d_params, wl.I0, wl.z)
+        for k in P:
+            P[k].append(q[k])
+    dev = {k: gu.to_dev(np.concatenate(v)) for k, v in P.items()}
+    flow_dev = gu.to_dev(np.concatenate([f.reshape(-1) for f in flows]))
+    rp = sp.render_params(wl.sheet_sigma, wl.d_max, wl.blur_radius, wl.blur_sigma, 0.0, 0, wl.seed, wl.dt,
+                          wl.substeps, wl.integrator)
+    rng = np.random.default_rng(77)
+    J = rng.standard_normal(batch.n_pixels, dtype=np.float32)
+    T = rng.standard_normal(batch.n_pixels, dtype=np.float32)
+    Jd, Td = gu.to_dev(J), gu.to_dev(T)
+    scale = np.float32(2.0 / batch.n_pixels)
+    args = (batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp)
+    print(f"[case] {name} loss-fused backward", flush=True)
+    ws = sp.alloc_workspace(batch, rp, backward="mse")
+    g = sp.render_pair_backward_mse(*args, Jd, Td, float(scale), loss=True, workspace=ws)
+    torch.cuda.synchronize()
+    assert sp.read_status(ws) == 0
+    print(f"[case] {name} two-step backward", flush=True)
+    gJ_dev, _ = sp.mse_grad(Jd, Td, float(scale))
+    two = sp.render_pair_backward(*args, gJ_dev)
+    torch.cuda.synchronize()
+    ref_loss = float(np.mean((J.astype(np.float64) - T) ** 2))
+    assert abs(float(g["loss"]) - ref_loss) <= 1e-12 * ref_loss
+    for k in two:
+        if wl.blur_radius == 1:
+            _close(gu.to_np(g[k]), gu.to_np(two[k]).astype(np.float64), f"{name} {k}", tol=1e-5)
+        else:
+            assert torch.equal(g[k], two[k]), k

@@ -9,9 +9,10 @@
 //     S0 = sum_q e_q G_q,  Sx = sum e G dx,  Sy = sum e G dy,  Sr = sum e G (dx^2 + dy^2),
 // e = B^T dL/dJ, equal sum_q (dL/dJ)_q Ty_j(r) Tx_k(c) with 1-D tables
 // Tx_k = w * (gx dx^k) (the blur folded into the particle's factor tables).
-// The gather is particle-major: 16 lanes per particle read their patch rows
-// of dL/dJ with coalesced loads; nothing is scattered, no partial sums cross
-// tiles.
+// The gather is particle-major (a group of 8 or 16 lanes per particle reads
+// its patch rows of dL/dJ with coalesced loads) or, for wide blurs, tile-major
+// (a home block of the image and its halo staged in LDS, the block's particles
+// gathered from it); nothing is scattered, no partial sums cross tiles.
 //
 // Flow adjoint: a reverse sweep through the recomputed Euler / RK4 substeps
 // (checkpointed).  Each bilinear sample passes its upstream gradient to its

@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define SYNTHPIX_VERSION 3
+#define SYNTHPIX_VERSION 4
 
 typedef enum {
     SP_OK = 0,

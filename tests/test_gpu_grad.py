@@ -595,17 +595,19 @@ def test_flow_gradient_overflow_is_flagged():
     assert sp.read_status(ws) & 0x20
 
 
-def test_forward_backward_replay_from_a_graph():
-    """Advect + render and loss gradient + backward captured as HIP graphs and
-    replayed three times, with eager work in between: every replay's images and
-    gradients equal the eager call's bit for bit."""
+@pytest.mark.parametrize("fused", [False, True])
+def test_forward_backward_replay_from_a_graph(fused):
+    """Advect + render and the loss's backward (loss gradient + backward, or the
+    loss-fused backward with its loss value) captured as HIP graphs and
+    replayed three times, with eager work in between: every replay's images,
+    gradients and loss equal the eager call's bit for bit."""
     sizes = [(64, 80), (48, 48)]
     grids = [(16, 20), (12, 12)]
     P, flows, batch, dev, flow_dev = _batch(sizes, grids, 60, 77)
     for blur in (1, 2):
         rp = sp.render_params(0.5, 5.0, blur, 0.8, 0.0, 0, 0, 1.0, 2, "rk4")
         wsf = sp.alloc_workspace(batch, rp)
-        wsb = sp.alloc_workspace(batch, rp, backward=True)
+        wsb = sp.alloc_workspace(batch, rp, backward="mse" if fused else True)
         x2 = torch.empty_like(dev["x"])
         y2 = torch.empty_like(dev["y"])
         img = torch.empty(batch.n_pixels, dtype=torch.float32, device=gu.DEV)
@@ -616,6 +618,11 @@ def test_forward_backward_replay_from_a_graph():
         def step():
             sp.advect(batch, flow_dev, rp.advect, dev["x"], dev["y"], x2, y2, wsf)
             sp.render_pair(batch, dev["x"], dev["y"], x2, y2, dev["z"], dev["d"], dev["I0"], rp, None, img, wsf)
+            if fused:
+                out["g"] = sp.render_pair_backward_mse(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"],
+                                                       dev["I0"], rp, img, target, 2.0 / batch.n_pixels, loss=True,
+                                                       workspace=wsb, x2=x2, y2=y2)
+                return
             sp.mse_grad(img, target, out=gJ)
             out["g"] = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"],
                                                rp, gJ, None, wsb, x2=x2, y2=y2)

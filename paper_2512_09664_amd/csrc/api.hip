@@ -433,7 +433,7 @@ BwdPlan bwd_plan(const synthpix_pair* ph, int32_t n_pairs, int64_t span, const s
         max_h = std::max(max_h, (int)ph[p].H);
         max_w = std::max(max_w, (int)ph[p].W);
     }
-    const int64_t n_loss = mse ? sp::blur_grad_blocks(n_pairs, max_w, max_h, rp.blur_radius, true) : 0;
+    const int64_t n_loss = mse ? sp::blur_grad_blocks(n_pairs, max_w, max_h, true) : 0;
     b.wl = bwd_layout(span, grid_workgroups(ph, n_pairs), n_pairs,
                       eblur_span(ph, n_pairs, rp.blur_radius, b.tile, mse), b.tile, n_loss);
     b.total = b.wl.total + b.ob * (b.tile ? 2 : 1);

@@ -1290,9 +1290,8 @@ hipError_t launch_mse_grad(const float* J, const float* T, int64_t n, float scal
 
 // Workgroups of the per-pixel blur adjoint: (pair, frame, strip row, strip
 // column) over the batch's largest pair.
-int64_t blur_grad_blocks(int n_pairs, int max_w, int max_h, int blur, bool mse)
+int64_t blur_grad_blocks(int n_pairs, int max_w, int max_h, bool mse)
 {
-    (void)blur;
     const int sh = blur_strip_rows(mse);
     return (int64_t)n_pairs * 2 * ((max_w + 255) / 256) * ((max_h + sh - 1) / sh);
 }
@@ -1336,7 +1335,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
     const bool per_pixel = a.eblur && (a.mse || (blur >= 1 && (tile || blur >= 2)));
     if (per_pixel && (n_span > 0 || (a.mse && a.loss))) {
         TimedScope ts("bwd_blur", s);
-        const int64_t nb = blur_grad_blocks(a.n_pairs, a.max_w, a.max_h, blur, a.mse);
+        const int64_t nb = blur_grad_blocks(a.n_pairs, a.max_w, a.max_h, a.mse);
         if (nb < 1 || nb > 0xFFFFFFFFll) return hipErrorInvalidValue;
         const int sh = blur_strip_rows(a.mse);
         const int nsx = (a.max_w + 255) / 256, nsy = (a.max_h + sh - 1) / sh;

@@ -314,7 +314,7 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
 // batch whose largest pair is max_h x max_w (the loss partials of the
 // loss-fused form, one each).
 constexpr int blur_strip_rows(bool mse) { return mse ? 16 : 24; }
-int64_t blur_grad_blocks(int n_pairs, int max_w, int max_h, int blur, bool mse);
+int64_t blur_grad_blocks(int n_pairs, int max_w, int max_h, bool mse);
 
 // Image loss gradient grad = scale (J - T) and, with loss, the mean of (J - T)^2
 // (float64 partials of MSE_BLOCKS workgroups in part, summed in a fixed order).

@@ -145,21 +145,37 @@ def test_backward_matches_oracle_gradient(integ, n_sub, blur, sheet, d_range, d_
             assert np.all(G[key][sl][dead] == 0.0)
 
 
-@pytest.mark.parametrize("blur", [2, 3])
-def test_backward_wide_blur_across_strips(ra, blur):
-    """Pairs wider than one strip of the wide blur's adjoint (256 - 2b columns)
-    and with ragged row counts (not multiples of 32): every gradient against the
-    oracle, frame-2 positions from the binary32 mirror."""
+@pytest.mark.parametrize("blur,fused", [(2, False), (3, False), (0, True), (1, True), (2, True), (3, True)])
+def test_backward_wide_blur_across_strips(ra, blur, fused):
+    """Pairs wider than one strip of the per-pixel pass (256 columns; the last
+    strip of each row ragged) and with ragged row counts (not multiples of the
+    strip's 24 or 16 rows): every gradient against the oracle, frame-2
+    positions from the binary32 mirror.  fused: the loss-fused backward, whose
+    per-pixel pass runs at every blur radius, with dL/dJ = scale (J - T) of
+    seeded images and targets (the product formed in binary32 on the host for
+    the oracle), and its loss against the float64 mean over the pairs' pixels."""
     sizes = [(70, 530), (45, 300)]
     grids = [(18, 133), (12, 75)]
     n = 40
     P, flows, batch, dev, flow_dev = _batch(sizes, grids, n, 60 + blur, d_range=(1.0, 4.5))
     rp = sp.render_params(0.5, 5.0, blur, 0.9, 0.0, 0, 0, 1.0, 2, "rk4")
-    gJ, gJ_dev = _grad_images(batch, 300 + blur)
-    ws = sp.alloc_workspace(batch, rp, backward=True)
-    g = sp.render_pair_backward(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp, gJ_dev,
-                                workspace=ws)
-    torch.cuda.synchronize()
+    args = (batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp)
+    if fused:
+        rng = np.random.default_rng(400 + blur)
+        J = rng.standard_normal(batch.n_pixels, dtype=np.float32)
+        T = rng.standard_normal(batch.n_pixels, dtype=np.float32)
+        scale = np.float32(2.0 / sum(2 * H * W for (H, W) in sizes))
+        gJ = scale * (J - T)
+        ws = sp.alloc_workspace(batch, rp, backward="mse")
+        g = sp.render_pair_backward_mse(*args, gu.to_dev(J), gu.to_dev(T), float(scale), loss=True, workspace=ws)
+        torch.cuda.synchronize()
+        ref_loss = float(np.mean((J.astype(np.float64) - T) ** 2))
+        assert abs(float(g.pop("loss")) - ref_loss) <= 1e-12 * ref_loss
+    else:
+        gJ, gJ_dev = _grad_images(batch, 300 + blur)
+        ws = sp.alloc_workspace(batch, rp, backward=True)
+        g = sp.render_pair_backward(*args, gJ_dev, workspace=ws)
+        torch.cuda.synchronize()
     assert sp.read_status(ws) == 0
     G = {k: gu.to_np(v) for k, v in g.items()}
     for p, (H, W) in enumerate(sizes):

@@ -109,7 +109,9 @@ __device__ __forceinline__ bool cover_range(float p, float R, int n, int& lo, in
 // (global memory, or a region staged in LDS).  Every lane returns the group's
 // sums.  on: the particle is valid and its support [c0, c1] x [r0, r1] is not
 // empty.
-template <int B, int BT, bool RY, int G>
+// CS: the source's row stride in elements when known at compile time (rows
+// then load at immediate offsets), 0 for the runtime stride.
+template <int B, int BT, bool RY, int G, int CS = 0>
 __device__ __forceinline__ float4 frame_sums(GatherLds<G, BT, RY>& S, int grp, int lane, bool on, float x, float y,
                                              float kap, float R, int c0, int c1, int r0, int r1, int W, int H,
                                              const float* __restrict__ src, int64_t stride, int sr, int sc,
@@ -195,16 +197,23 @@ __device__ __forceinline__ float4 frame_sums(GatherLds<G, BT, RY>& S, int grp, i
             const int t = tlo + cb + cl;
             // walk down the column slice with a row pointer: whole batches of GROWS
             // rows (their loads issued together), then batches of 4, 2 and 1
-            const float* __restrict__ q = src + (int64_t)(r0 - B + ua - sr) * stride + (c0 - B + t - sc);
+            const int64_t str = CS > 0 ? (int64_t)CS : stride;
+            const float* __restrict__ q = src + (int64_t)(r0 - B + ua - sr) * str + (c0 - B + t - sc);
             float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
             int u = ua;
 #pragma unroll 1
             for (; u + GROWS <= ub; u += GROWS) {
                 float e[GROWS];
+                if constexpr (CS > 0) {
 #pragma unroll
-                for (int k = 0; k < GROWS; ++k) {
-                    e[k] = *q;
-                    q += stride;
+                    for (int k = 0; k < GROWS; ++k) e[k] = q[k * CS];
+                    q += GROWS * CS;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < GROWS; ++k) {
+                        e[k] = *q;
+                        q += str;
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < GROWS; ++k) {
@@ -218,10 +227,16 @@ __device__ __forceinline__ float4 frame_sums(GatherLds<G, BT, RY>& S, int grp, i
             for (int nb = GROWS / 2; nb >= 1; nb >>= 1) {
                 if (ub - u >= nb) {
                     float e[GROWS / 2];
+                    if constexpr (CS > 0) {
 #pragma unroll
-                    for (int k = 0; k < nb; ++k) {
-                        e[k] = *q;
-                        q += stride;
+                        for (int k = 0; k < nb; ++k) e[k] = q[k * CS];
+                        q += nb * CS;
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < nb; ++k) {
+                            e[k] = *q;
+                            q += str;
+                        }
                     }
 #pragma unroll
                     for (int k = 0; k < nb; ++k) {
@@ -371,6 +386,10 @@ bwd_gather(BwdArgs a, int64_t n_span)
 // position lies in the block (or beyond the image edge next to it, where the
 // home block is clamped) is inside the staged region.  The sums go to
 // parts[f * n_span + slot]; bwd_particles turns them into gradients.
+// RS: the staged region's row stride (a multiple of 8 at least its width, so
+// the gather's row loads take immediate offsets), 0 for a stride equal to the
+// width.
+template <int RS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
 bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
 {
@@ -398,6 +417,7 @@ bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
     const int col = wi / rows, by = s0 + (wi - col * rows);
     const int bx = (s0 & 4) ? PL.ntx - 1 - col : col;
     const int side = 1 << lb, rw = side + 2 * hb;
+    const int rs = RS > 0 ? RS : rw;
     const int ox = (bx << lb) - hb, oy = (by << lb) - hb;
     const int H = P.H, W = P.W;
     const float* __restrict__ src = a.grad + P.image_offset + (int64_t)f * H * W;
@@ -410,7 +430,7 @@ bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
             const float* __restrict__ row = src + (int64_t)(rin ? R : 0) * W;
             for (int c = ln; c < rw; c += 64) {
                 const int C = ox + c;
-                region[r * rw + c] = (rin && C >= 0 && C < W) ? row[C] : 0.0f;
+                region[r * rs + c] = (rin && C >= 0 && C < W) ? row[C] : 0.0f;
             }
         }
     }
@@ -439,8 +459,8 @@ bwd_tile_gather(BwdArgs a, int64_t n_span, int lb, int hb)
         on = on && cover_range(y, R, H, r0, r1);
         // in-image support inside the staged region (always, for d <= d_max)
         on = on && c0 >= ox && c1 < ox + rw && r0 >= oy && r1 < oy + rw;
-        const float4 sums = frame_sums<0, 32, false, G>(S, grp, lane, on, x, y, kap, R, c0, c1, r0, r1, W, H, region, rw,
-                                              oy, ox, a.blur_w);
+        const float4 sums = frame_sums<0, 32, false, G, RS>(S, grp, lane, on, x, y, kap, R, c0, c1, r0, r1, W, H,
+                                                          region, rs, oy, ox, a.blur_w);
         if (act && lane == 0) a.parts[(int64_t)f * n_span + g] = sums;
     }
 }
@@ -1366,8 +1386,19 @@ hipError_t launch_backward(const BwdArgs& a, int64_t n_span, int64_t n_flow, con
             const int rw = (1 << a.order.log_block) + 2 * hb;
             const int64_t items = 2 * a.order.blocks;
             if (items > 0xFFFFFFFFll) return hipErrorInvalidValue;
-            hipLaunchKernelGGL(bwd_tile_gather, dim3((unsigned)items), dim3(256), sizeof(float) * (size_t)rw * rw, s,
-                               b, n_span, a.order.log_block, hb);
+            // the region's row stride rounded up to one of the compiled ones
+            const int rs = rw <= 40 ? 40 : rw <= 48 ? 48 : rw <= 56 ? 56 : rw <= 64 ? 64 : rw;
+            const size_t lds = sizeof(float) * (size_t)rs * rw;
+#define SP_TILE(RS_) hipLaunchKernelGGL(bwd_tile_gather<RS_>, dim3((unsigned)items), dim3(256), lds, s, b, n_span, \
+                                        a.order.log_block, hb)
+            switch (rs) {
+            case 40: SP_TILE(40); break;
+            case 48: SP_TILE(48); break;
+            case 56: SP_TILE(56); break;
+            case 64: SP_TILE(64); break;
+            default: SP_TILE(0); break;
+            }
+#undef SP_TILE
             hipLaunchKernelGGL(bwd_particles, dim3((unsigned)((n_span + 255) / 256)), dim3(256), 0, s, b, n_span);
         } else if (per_pixel) {
             TimedScope ts("bwd_gather", s);

@@ -324,7 +324,8 @@ hipError_t enqueue_render(const synthpix_pair* pairs_dev, int32_t n_pairs, const
                           const sp::BatchTotals& T, const sp::WorkspaceLayout& wl, const float* x1, const float* y1,
                           const float* x2, const float* y2, const float* z, const float* d, const float* I0,
                           const synthpix_render_params& rp, void* images, void* workspace, hipStream_t stream,
-                          const synthpix_batch_io* iod = nullptr, const synthpix_particle_extras* ex = nullptr)
+                          const synthpix_batch_io* iod = nullptr, const synthpix_particle_extras* ex = nullptr,
+                          const int32_t* live = nullptr)
 {
     sp::RenderArgs a{};
     if (ex) {
@@ -342,6 +343,7 @@ hipError_t enqueue_render(const synthpix_pair* pairs_dev, int32_t n_pairs, const
     a.model = model_in_use(rp, ex);
     a.aniso = aniso_in_use(rp, ex);
     a.iod = iod;
+    a.live = live;
     a.pairs = pairs_dev;
     a.n_pairs = n_pairs;
     a.x[0] = x1; a.y[0] = y1; a.x[1] = x2; a.y[1] = y2;
@@ -1068,7 +1070,8 @@ hipError_t enqueue_batch(synthpix_plan* P, const synthpix_tiling& t, hipStream_t
     const synthpix_batch_io& io = P->io;
     const synthpix_batch_io* iod = P->io_dev;
     // masked candidates (slots past each pair's active count) are seeded but not
-    // ordered or advected: the seed sets their frame-2 position to frame 1's
+    // ordered, advected, prepared or binned: the seed sets their frame-2
+    // position to frame 1's
     hipError_t e = sp::launch_seed(P->pairs_dev, P->n_pairs, P->span, P->sp, io.seed, io.x1, io.y1, io.z, io.d,
                                    io.I0, io.n_active, io.ppp, s, iod, P->live);
     if (e != hipSuccess) return e;
@@ -1084,7 +1087,7 @@ hipError_t enqueue_batch(synthpix_plan* P, const synthpix_tiling& t, hipStream_t
     if (batch_totals(P->pairs_host.data(), P->n_pairs, cfg, &T) != SP_OK) return hipErrorInvalidValue;
     const sp::WorkspaceLayout wl = workspace_layout(P->n_pairs, T, 0, P->pairs_host.data());
     e = enqueue_render(P->pairs_dev, P->n_pairs, cfg, T, wl, io.x1, io.y1, io.x2, io.y2, io.z, io.d, io.I0, P->rp,
-                       io.images, P->workspace, s, iod);
+                       io.images, P->workspace, s, iod, nullptr, P->live);
     if (e != hipSuccess) return e;
     if (with_advance && P->advance) e = sp::launch_advance(P->io_dev, (uint64_t)P->n_pairs, s);
     return e;

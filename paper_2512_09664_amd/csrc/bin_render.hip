@@ -102,7 +102,8 @@ bin_layout(const synthpix_pair* __restrict__ pairs, int n_pairs, RenderConfig cf
 // |dx|, |dy| <= 1.5 d clipped to the image (computed once here for every tile
 // list and tile that uses the particle).  Particles that add nothing (I0 <= 0,
 // d <= 0 or not a number, non-finite position) or whose d exceeds d_max
-// (flagged) get an empty box.
+// (flagged) get an empty box.  With live counts (captured plans), the masked
+// slots past a pair's count are skipped: the binning passes skip them too.
 __global__ void __launch_bounds__(256)
 prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_span, RenderArgs a,
              float d_max, float4* __restrict__ rec0, float4* __restrict__ rec1, uint2* __restrict__ box0,
@@ -113,7 +114,7 @@ prep_records(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_spa
     if (g >= n_span) return;
     const int p = find_pair_from(pairs, n_pairs, g0, g);
     const int64_t i = g - pairs[p].particle_offset;
-    if (i < 0 || i >= pairs[p].n_max) return;
+    if (i < 0 || i >= (a.live ? (int64_t)min(a.live[p], pairs[p].n_max) : (int64_t)pairs[p].n_max)) return;
     if (a.iod) {
         a.x[0] = a.iod->x1;
         a.y[0] = a.iod->y1;
@@ -241,7 +242,7 @@ __global__ void __launch_bounds__(256)
 bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__ L, int n_pairs,
          const uint2* __restrict__ box0, const uint2* __restrict__ box1, RenderConfig cfg, uint32_t* __restrict__ hist,
          const int64_t* __restrict__ tile_offset, int64_t tiles_total, int32_t* __restrict__ entries,
-         unsigned n_chunks_total)
+         unsigned n_chunks_total, const int32_t* __restrict__ live)
 {
     extern __shared__ uint32_t lh[];
     const int f = blockIdx.y;
@@ -258,7 +259,7 @@ bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__
     const int64_t seg0 = PL.entry_base + (int64_t)f * PL.entry_cap;
     for (int t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = SCATTER ? gh[t] + (uint32_t)(toff[t] - seg0) : 0u;
     __syncthreads();
-    const int i_end = min(P.n_max, (chunk + 1) * cfg.chunk);
+    const int i_end = min(live ? min(live[p], P.n_max) : P.n_max, (chunk + 1) * cfg.chunk);
     const uint2* __restrict__ bxs = f ? box1 : box0;
     // BIN_ILP particles per thread and step: their box loads and LDS atomic
     // round trips overlap
@@ -967,10 +968,12 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
     }
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
     const dim3 bgrid((unsigned)tot.chunks, 2);
+    // the full model's prep writes every slot; live counts only with the isotropic prep
+    const int32_t* live = a.model ? nullptr : a.live;
     if (tot.chunks > 0) {
         TimedScope ts("bin_count", s);
         hipLaunchKernelGGL(bin_pass<false>, bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, box0, box1, cfg,
-                           hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
+                           hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks, live);
     }
     if (tot.tiles > 0) {
         TimedScope ts("bin_scan", s);
@@ -979,7 +982,7 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
     if (tot.chunks > 0) {
         TimedScope ts("bin_scatter", s);
         hipLaunchKernelGGL(bin_pass<true>, bgrid, dim3(256), hist_lds, s, a.pairs, L, a.n_pairs, box0, box1, cfg,
-                           hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks);
+                           hist, tile_offset, tot.tiles, entries, (unsigned)tot.chunks, live);
     }
     return hipGetLastError();
 }

@@ -187,6 +187,8 @@ struct RenderArgs {
     uint64_t seed;
     float blur_w[7];
     const synthpix_batch_io* iod;   // captured plans: buffers, key and pair-id offset (else null)
+    const int32_t* live;            // captured plans: each pair's active count; the masked slots past
+                                    // it are neither prepared nor binned (else null: every slot)
     // the full particle model (all zero / null: the isotropic Gaussian-sheet path)
     const float* dy;                // second diameter per particle (null: d)
     const float* rho;               // correlation per particle (null: 0)

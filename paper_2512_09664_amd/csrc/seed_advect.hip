@@ -289,7 +289,13 @@ advect_kernel(const synthpix_pair* __restrict__ pairs, int n_pairs, int64_t n_sp
         }
         __syncthreads();
     }
-    integrate_n<ADVECT_ILP>(fv, px, py, ap.dt, ap.substeps, ap.integrator, win, (lds_float*)s_win);
+    // a wave none of whose slots holds a particle to move (slots past every
+    // pair's range or, with live counts, masked candidates) skips the steps
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < ADVECT_ILP; ++q) any = any || gi[q] >= 0;
+    if (__builtin_amdgcn_ballot_w64(any) != 0)
+        integrate_n<ADVECT_ILP>(fv, px, py, ap.dt, ap.substeps, ap.integrator, win, (lds_float*)s_win);
 #pragma unroll
     for (int q = 0; q < ADVECT_ILP; ++q) {
         if (gi[q] >= 0) {

@@ -257,9 +257,12 @@ bin_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict__
     // scatter cursors start at the chunk's first slot in each tile list
     const int64_t* toff = tile_offset + f * tiles_total + PL.tile_base;
     const int64_t seg0 = PL.entry_base + (int64_t)f * PL.entry_cap;
+    const int i_end = min(live ? min(live[p], P.n_max) : P.n_max, (chunk + 1) * cfg.chunk);
+    // a chunk past the live slots holds nothing (and is not scanned): the whole
+    // workgroup returns before its barrier
+    if (live && chunk * cfg.chunk >= i_end) return;
     for (int t = threadIdx.x; t < nt; t += blockDim.x) lh[t] = SCATTER ? gh[t] + (uint32_t)(toff[t] - seg0) : 0u;
     __syncthreads();
-    const int i_end = min(live ? min(live[p], P.n_max) : P.n_max, (chunk + 1) * cfg.chunk);
     const uint2* __restrict__ bxs = f ? box1 : box0;
     // BIN_ILP particles per thread and step: their box loads and LDS atomic
     // round trips overlap
@@ -333,10 +336,13 @@ order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict
     uint32_t* gh = hist + PL.hist_base + (int64_t)chunk * nt;
     int32_t* seg = entries + PL.entry_base;
     const int64_t* toff = tile_offset + PL.tile_base;
+    const int i_end = min(live ? min(live[p], P.n_max) : P.n_max, (chunk + 1) * cfg.chunk);
+    // a chunk past the live slots holds nothing (and is not scanned): the whole
+    // workgroup returns before its barrier
+    if (live && chunk * cfg.chunk >= i_end) return;
     for (int t = threadIdx.x; t < nt; t += blockDim.x)
         lh[t] = SCATTER ? gh[t] + (uint32_t)(toff[t] - PL.entry_base) : 0u;
     __syncthreads();
-    const int i_end = min(live ? min(live[p], P.n_max) : P.n_max, (chunk + 1) * cfg.chunk);
     for (int i = chunk * cfg.chunk + threadIdx.x; i < i_end; i += blockDim.x) {
         const int64_t g = P.particle_offset + i;
         const uint32_t slot = atomicAdd(&lh[home_block(x[g], y[g], P.W, P.H, PL, cfg)], 1u);
@@ -351,10 +357,12 @@ order_pass(const synthpix_pair* __restrict__ pairs, const PairLayout* __restrict
 // Per (pair, frame, tile), one thread each: exclusive prefix of the chunk
 // histograms over the chunks, in place (each chunk's first slot inside the
 // tile's list), and the tile's total.  Consecutive threads take consecutive
-// tiles, so every chunk row is read and written with coalesced accesses.
+// tiles, so every chunk row is read and written with coalesced accesses.  With
+// live counts only the chunks that hold a live slot are scanned (the count and
+// scatter passes of the others return at once).
 __global__ void __launch_bounds__(256)
 scan_chunks(const PairLayout* __restrict__ L, int n_pairs, uint32_t* __restrict__ hist,
-            uint32_t* __restrict__ tile_count, int64_t tiles_total)
+            uint32_t* __restrict__ tile_count, int64_t tiles_total, const int32_t* __restrict__ live, int chunk)
 {
     const int f = blockIdx.y;
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -363,16 +371,17 @@ scan_chunks(const PairLayout* __restrict__ L, int n_pairs, uint32_t* __restrict_
     const PairLayout PL = L[p];
     const int nt = PL.ntx * PL.nty;
     const int t = (int)(gt - PL.tile_base);
+    const int nc = live ? min(PL.n_chunks, (max(live[p], 0) + chunk - 1) / chunk) : PL.n_chunks;
     uint32_t* h = hist + PL.hist_base + (int64_t)f * PL.n_chunks * nt + t;
     constexpr int U = 8;                 // chunk rows loaded together
     uint32_t run = 0;
-    for (int c0 = 0; c0 < PL.n_chunks; c0 += U) {
+    for (int c0 = 0; c0 < nc; c0 += U) {
         uint32_t v[U];
 #pragma unroll
-        for (int k = 0; k < U; ++k) v[k] = c0 + k < PL.n_chunks ? h[(int64_t)(c0 + k) * nt] : 0u;
+        for (int k = 0; k < U; ++k) v[k] = c0 + k < nc ? h[(int64_t)(c0 + k) * nt] : 0u;
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            if (c0 + k < PL.n_chunks) h[(int64_t)(c0 + k) * nt] = run;
+            if (c0 + k < nc) h[(int64_t)(c0 + k) * nt] = run;
             run += v[k];
         }
     }
@@ -862,10 +871,11 @@ bool render_shape_supported(int tw, int th)
 // ------------------------------------------------------------------ launcher
 
 static void launch_scans(const PairLayout* L, int n_pairs, uint32_t* hist, uint32_t* tile_count,
-                         int64_t* tile_offset, int64_t tiles, int frames, hipStream_t s)
+                         int64_t* tile_offset, int64_t tiles, int frames, hipStream_t s, const int32_t* live,
+                         int chunk)
 {
     hipLaunchKernelGGL(scan_chunks, dim3((unsigned)((tiles + 255) / 256), frames), dim3(256), 0, s, L, n_pairs, hist,
-                       tile_count, tiles);
+                       tile_count, tiles, live, chunk);
     hipLaunchKernelGGL(scan_tiles, dim3((unsigned)n_pairs, frames), dim3(256), 0, s, L, tile_count, tile_offset,
                        tiles);
 }
@@ -977,7 +987,7 @@ hipError_t launch_bins(const RenderArgs& a, const RenderConfig& cfg, const Batch
     }
     if (tot.tiles > 0) {
         TimedScope ts("bin_scan", s);
-        launch_scans(L, a.n_pairs, hist, tile_count, tile_offset, tot.tiles, 2, s);
+        launch_scans(L, a.n_pairs, hist, tile_count, tile_offset, tot.tiles, 2, s, live, cfg.chunk);
     }
     if (tot.chunks > 0) {
         TimedScope ts("bin_scatter", s);
@@ -1036,7 +1046,7 @@ hipError_t launch_order(const synthpix_pair* pairs_dev, int n_pairs, const float
     const size_t hist_lds = (size_t)tot.max_tiles * sizeof(uint32_t);
     hipLaunchKernelGGL(order_pass<false>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
                        y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks, iod, live);
-    launch_scans(L, n_pairs, hist, tile_count, tile_offset, tot.tiles, 1, s);
+    launch_scans(L, n_pairs, hist, tile_count, tile_offset, tot.tiles, 1, s, live, cfg.chunk);
     hipLaunchKernelGGL(order_pass<true>, dim3((unsigned)tot.chunks), dim3(256), hist_lds, s, pairs_dev, L, n_pairs, x,
                        y, cfg, hist, tile_offset, entries, (unsigned)tot.chunks, iod, live);
     return hipGetLastError();

@@ -874,20 +874,27 @@ bwd_advect(BwdArgs a, synthpix_advect_params ap)
             }
             if (s + 1 < S) substep(fv, qx, qy, h, hh, ap.integrator);
         }
-        float spx[SK], spy[SK];
-        for (int seg = nseg - 1; seg >= 0; --seg) {
-            const int s0 = seg * L;
-            const int len = (S - s0) < L ? (S - s0) : L;
-            spx[0] = cpx[seg];
-            spy[0] = cpy[seg];
-            for (int k = 1; k < len; ++k) {
-                float tx = spx[k - 1], ty = spy[k - 1];
-                substep(fv, tx, ty, h, hh, ap.integrator);
-                spx[k] = tx;
-                spy[k] = ty;
+        if constexpr (SK == 1) {
+            // S <= CK: every substep's start is a checkpoint, the sweep walks them
+            // (no segment slots, whose runtime indexing would live in scratch)
+            for (int seg = nseg - 1; seg >= 0; --seg)
+                substep_adjoint(fv, run, cpx[seg], cpy[seg], h, hh, ap.integrator, gpx, gpy);
+        } else {
+            float spx[SK], spy[SK];
+            for (int seg = nseg - 1; seg >= 0; --seg) {
+                const int s0 = seg * L;
+                const int len = (S - s0) < L ? (S - s0) : L;
+                spx[0] = cpx[seg];
+                spy[0] = cpy[seg];
+                for (int k = 1; k < len; ++k) {
+                    float tx = spx[k - 1], ty = spy[k - 1];
+                    substep(fv, tx, ty, h, hh, ap.integrator);
+                    spx[k] = tx;
+                    spy[k] = ty;
+                }
+                for (int k = len - 1; k >= 0; --k)
+                    substep_adjoint(fv, run, spx[k], spy[k], h, hh, ap.integrator, gpx, gpy);
             }
-            for (int k = len - 1; k >= 0; --k)
-                substep_adjoint(fv, run, spx[k], spy[k], h, hh, ap.integrator, gpx, gpy);
         }
         run.finish();
         a.g_x1[g] += gpx;

@@ -782,3 +782,60 @@ def test_backward_mse_full_size(ra, name):
             _close(gu.to_np(g[k]), gu.to_np(two[k]).astype(np.float64), f"{name} {k}", tol=1e-5)
         else:
             assert torch.equal(g[k], two[k]), k
+
+
+@pytest.mark.parametrize("blur", [1, 2])
+def test_backward_mse_with_gaps_matches_packed(blur):
+    """The loss-fused backward on a batch whose particle, image and flow arrays
+    leave gaps before every pair, the images' and the target's gaps holding NaN:
+    gradients and loss equal those of the packed batch bit for bit (so no gap
+    pixel is read), gap slots come back 0."""
+    sizes, grids, m = [(40, 48), (24, 20), (31, 17)], [(10, 12), (8, 7), (6, 5)], 30
+    P, flows, batch, dev, flow_dev = _batch(sizes, grids, m, 23)
+    rp = sp.render_params(0.5, 5.0, blur, 0.7, 0.0, 0, 0, 1.0, 2, "rk4")
+    rng = np.random.default_rng(29)
+    J = rng.standard_normal(batch.n_pixels).astype(np.float32)
+    T = rng.standard_normal(batch.n_pixels).astype(np.float32)
+    scale = 0.125
+    ref = sp.render_pair_backward_mse(batch, flow_dev, dev["x"], dev["y"], dev["z"], dev["d"], dev["I0"], rp,
+                                      gu.to_dev(J), gu.to_dev(T), scale, loss=True)
+    gaps = (5, 12, 4)
+    gb = sp.PairBatch.build(sizes, grids, [m] * 3, device=gu.DEV, gaps=gaps)
+
+    def spread(a, n_total, gap, sizes_):
+        out = np.full(n_total, np.nan, np.float32)
+        o = 0
+        for p, k in enumerate(sizes_):
+            o += gap
+            out[o:o + k] = a[sum(sizes_[:p]):sum(sizes_[:p]) + k]
+            o += k
+        return out
+
+    gdev = {k: gu.to_dev(np.nan_to_num(spread(np.concatenate(P[k]), gb.n_particles, gaps[0], [m] * 3), nan=0.0))
+            for k in P}
+    pix = [2 * H * W for (H, W) in sizes]
+    Jg, Tg = gu.to_dev(spread(J, gb.n_pixels, gaps[1], pix)), gu.to_dev(spread(T, gb.n_pixels, gaps[1], pix))
+    fl = [2 * a * b for (a, b) in grids]
+    gflow = gu.to_dev(np.nan_to_num(spread(np.concatenate([f.reshape(-1) for f in flows]), gb.n_flow, gaps[2], fl),
+                                    nan=0.0))
+    got = sp.render_pair_backward_mse(gb, gflow, gdev["x"], gdev["y"], gdev["z"], gdev["d"], gdev["I0"], rp, Jg, Tg,
+                                      scale, loss=True)
+    torch.cuda.synchronize()
+    assert float(got["loss"]) == float(ref["loss"])
+    for key in ("x1", "y1", "z", "d", "I0"):
+        g, r = gu.to_np(got[key]), gu.to_np(ref[key])
+        o = 0
+        for p in range(3):
+            assert np.all(g[o:o + gaps[0]] == 0.0), (key, p)
+            o += gaps[0]
+            assert np.array_equal(g[o:o + m], r[p * m:(p + 1) * m]), (key, p)
+            o += m
+    assert torch.equal(got["sheet"], ref["sheet"]) and torch.equal(got["sheet_total"], ref["sheet_total"])
+    gf, rf = gu.to_np(got["flow"]), gu.to_np(ref["flow"])
+    o = ro = 0
+    for p in range(3):
+        assert np.all(gf[o:o + gaps[2]] == 0.0)
+        o += gaps[2]
+        assert np.array_equal(gf[o:o + fl[p]], rf[ro:ro + fl[p]]), p
+        o += fl[p]
+        ro += fl[p]
